@@ -1,0 +1,201 @@
+"""FP64 Krylov solvers of the oracle.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/wilson.py``).
+
+The paper (section 1) names the inversion D phi = psi with Krylov methods,
+conjugate gradient in particular, as the most expensive part of the
+simulation, and (section 3) lists standard inversion algorithms.  The two
+solvers here are the textbook methods:
+
+* CGNR: conjugate gradient on the normal equations M^+ M x = M^+ b that
+  tracks the residual r = b - M x of the original system (Saad, "Iterative
+  Methods for Sparse Linear Systems", the CGNR algorithm);
+* BiCGStab (van der Vorst 1992) on the non-Hermitian M directly.
+
+Both stop when the tracked residual satisfies ||r|| <= tol * ||b_ref||, then
+recompute the true residual in FP64; if that misses the tolerance they
+restart from the recomputed residual.  ``b_ref`` is the right-hand side of
+the full, unpreconditioned system, so the even-odd solve stops on the same
+criterion as the full-lattice one.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import wilson as W
+
+OK = 0
+ENOCONV = -3
+EBREAKDOWN = -4
+ENONFINITE = -5
+
+
+@dataclass
+class SolveInfo:
+    status: int = OK
+    iters: int = 0
+    restarts: int = 0
+    true_resid: float = float("nan")
+    eo_resid: float = float("nan")
+
+
+def _dot(a, b):
+    return complex(np.vdot(a.ravel(), b.ravel()))
+
+
+def _nrm2(a):
+    return float(np.vdot(a.ravel(), a.ravel()).real)
+
+
+def cgnr(A, Ah, b, tol, maxiter, b_ref_norm=None, residual=None, x0=None):
+    """Solve A x = b by CG on A^+ A, tracking r = b - A x.
+
+    ``residual(x)`` returns the true relative residual used to confirm
+    convergence (defaults to ||b - A x|| / b_ref_norm).
+    """
+    info = SolveInfo()
+    bn = float(np.sqrt(_nrm2(b))) if b_ref_norm is None else float(b_ref_norm)
+    if residual is None:
+        residual = lambda x: float(np.sqrt(_nrm2(b - A(x)))) / bn  # noqa: E731
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    if bn == 0.0:
+        info.true_resid = 0.0
+        return x, info
+    if not np.all(np.isfinite(b)):
+        info.status = ENONFINITE
+        return x, info
+    r = b - A(x)
+    z = Ah(r)
+    p = z.copy()
+    zz = _nrm2(z)
+    k = 0
+    while True:
+        if np.sqrt(_nrm2(r)) <= tol * bn:
+            tr = residual(x)
+            if tr <= tol:
+                info.true_resid = tr
+                break
+            # recursion drifted: restart from the true residual
+            info.restarts += 1
+            r = b - A(x)
+            z = Ah(r)
+            p = z.copy()
+            zz = _nrm2(z)
+        if k >= maxiter:
+            info.status = ENOCONV
+            info.true_resid = residual(x)
+            break
+        w = A(p)
+        alpha = zz / _nrm2(w)
+        x = x + alpha * p
+        r = r - alpha * w
+        z = Ah(r)
+        zz_new = _nrm2(z)
+        beta = zz_new / zz
+        zz = zz_new
+        p = z + beta * p
+        k += 1
+        if not np.isfinite(zz):
+            info.status = ENONFINITE
+            break
+    info.iters = k
+    return x, info
+
+
+def bicgstab(A, b, tol, maxiter, b_ref_norm=None, residual=None, x0=None):
+    """BiCGStab (van der Vorst 1992) on A x = b."""
+    info = SolveInfo()
+    bn = float(np.sqrt(_nrm2(b))) if b_ref_norm is None else float(b_ref_norm)
+    if residual is None:
+        residual = lambda x: float(np.sqrt(_nrm2(b - A(x)))) / bn  # noqa: E731
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    if bn == 0.0:
+        info.true_resid = 0.0
+        return x, info
+    if not np.all(np.isfinite(b)):
+        info.status = ENONFINITE
+        return x, info
+
+    def start(x):
+        r = b - A(x)
+        return r, r.copy(), 1.0 + 0j, 1.0 + 0j, 1.0 + 0j, np.zeros_like(b), np.zeros_like(b)
+
+    r, r0, rho, alpha, omega, v, p = start(x)
+    k = 0
+    while True:
+        if np.sqrt(_nrm2(r)) <= tol * bn:
+            tr = residual(x)
+            if tr <= tol:
+                info.true_resid = tr
+                break
+            info.restarts += 1
+            r, r0, rho, alpha, omega, v, p = start(x)
+        if k >= maxiter:
+            info.status = ENOCONV
+            info.true_resid = residual(x)
+            break
+        rho_new = _dot(r0, r)
+        if rho_new == 0 or omega == 0:
+            info.status = EBREAKDOWN
+            info.true_resid = residual(x)
+            break
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = A(p)
+        alpha = rho_new / _dot(r0, v)
+        s = r - alpha * v
+        t = A(s)
+        tt = _nrm2(t)
+        if tt == 0.0:
+            # s is already the exact residual of x + alpha p
+            x = x + alpha * p
+            r = s
+            k += 1
+            continue
+        omega = _dot(t, s) / tt
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho = rho_new
+        k += 1
+        if not np.isfinite(_nrm2(r)):
+            info.status = ENONFINITE
+            break
+    info.iters = k
+    return x, info
+
+
+def solve(U, b, L, theta, kappa, mu, tol, maxiter=100000, method="cgnr", eo=True):
+    """x = M^-1 b with the chosen method, on the full lattice or through the
+    even-odd Schur complement (prepare, solve on even sites, reconstruct)."""
+    bn = float(np.sqrt(_nrm2(b)))
+    if not eo:
+        A = lambda v: W.apply_M(U, v, L, theta, kappa, mu)  # noqa: E731
+        Ah = lambda v: W.apply_M(U, v, L, theta, kappa, mu, dagger=True)  # noqa: E731
+        res = lambda x: W.true_residual(U, x, b, L, theta, kappa, mu)  # noqa: E731
+        if method == "cgnr":
+            x, info = cgnr(A, Ah, b, tol, maxiter, bn, res)
+        else:
+            x, info = bicgstab(A, b, tol, maxiter, bn, res)
+        return x, info
+
+    bhat = W.eo_source(U, b, L, theta, kappa, mu)
+    A = lambda v: W.schur(U, v, L, theta, kappa, mu)  # noqa: E731
+    Ah = lambda v: W.schur(U, v, L, theta, kappa, mu, dagger=True)  # noqa: E731
+
+    def res(x_e):
+        x = W.eo_reconstruct(U, x_e, b, L, theta, kappa, mu)
+        return W.true_residual(U, x, b, L, theta, kappa, mu)
+
+    if method == "cgnr":
+        x_e, info = cgnr(A, Ah, bhat, tol, maxiter, bn, res)
+    else:
+        x_e, info = bicgstab(A, bhat, tol, maxiter, bn, res)
+    x = W.eo_reconstruct(U, x_e, b, L, theta, kappa, mu)
+    info.true_resid = W.true_residual(U, x, b, L, theta, kappa, mu)
+    r_eo = bhat - A(x_e)
+    nbh = np.sqrt(_nrm2(bhat))
+    info.eo_resid = float(np.sqrt(_nrm2(r_eo)) / nbh) if nbh > 0 else 0.0
+    return x, info
