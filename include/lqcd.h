@@ -1,0 +1,182 @@
+/*
+ * lqcd.h - C ABI of the MI355X (gfx950) Wilson / twisted-mass Wilson
+ * Dslash and Krylov solver library.
+ *
+ * The operation is the inversion D phi = psi of the lattice fermion matrix
+ * with Krylov methods, whose cost is dominated by repeated applications of
+ * the Wilson Dslash (arxiv 1411.5219, section 1; twisted-mass Wilson
+ * fermions: section 3; measured Dslash bandwidth: section 6).  The paper
+ * prints no formulas; the library implements the standard forms below.
+ *
+ * Operator (mu = 0,1,2,3 are x,y,z,t):
+ *   (H psi)(x) = sum_mu [ (1 - gamma_mu) U_mu(x) f+ psi(x + mu)
+ *                       + (1 + gamma_mu) U_mu(x - mu)^+ f- psi(x - mu) ]
+ *   M = 1 + 2 i kappa mu gamma_5 - kappa H         (mu = 0: plain Wilson)
+ *   M^+ = 1 - 2 i kappa mu gamma_5 - kappa H^+, H^+ swaps the projector signs.
+ * f+ = exp(i theta_mu) on hops that cross the boundary forwards (x_mu = L_mu - 1),
+ * f- = exp(-i theta_mu) on hops that cross it backwards (x_mu = 0), 1 otherwise;
+ * theta = (0, 0, 0, pi) is periodic in space and antiperiodic in time.
+ * Gamma matrices in the chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]]
+ * (k = x, y, z), gamma_t = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1).
+ *
+ * Even-odd: parity of a site is (x + y + z + t) mod 2, even = 0.  With
+ * A = 1 + 2 i kappa mu gamma_5 the Schur complement on even sites is
+ *   Mhat = A - kappa^2 H_eo A^-1 H_oe.
+ *
+ * Memory: every field pointer is a DEVICE pointer owned by the caller, in
+ * the library's internal layout (structure of arrays, split by parity; sizes
+ * from lqcd_field_bytes).  lqcd_pack_* / lqcd_unpack_spinor convert from /
+ * to the canonical layout:
+ *   gauge  complex128 U[4][V][3][3]  (link from site to site + mu, row, column)
+ *   spinor complex128 psi[V][4][3]   (spin, colour), site = x + Lx*(y + Ly*(z + Lz*t)),
+ *          nrhs fields stacked: psi[nrhs][V][4][3].
+ * The library never allocates or frees caller memory; scratch comes from a
+ * caller workspace of lqcd_workspace_bytes() bytes (device memory).  A
+ * small pinned host buffer per thread is kept for reading back solver status.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  dslash_* and
+ * pack calls only enqueue work and return.  Solvers return once x is final
+ * on the device and *info is filled.
+ *
+ * Errors: functions return LQCD_OK (0) or a negative code; the message of
+ * the last error on the calling thread is lqcd_last_error().  Arguments are
+ * validated before any device work is enqueued.
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LQCD_API __attribute__((visibility("default")))
+
+enum {
+    LQCD_OK = 0,
+    LQCD_EINVAL = -1,        /* null pointer, bad extent (< 2 or odd), bad nrhs or parameter */
+    LQCD_EUNSUPPORTED = -2,  /* precision / recon combination not built (FP16 needs recon 12) */
+    LQCD_ENOCONV = -3,       /* maxiter reached: x holds the last iterate, info is valid */
+    LQCD_EBREAKDOWN = -4,    /* BiCGStab breakdown (rho = 0 or omega = 0) */
+    LQCD_ENONFINITE = -5,    /* NaN or Inf met (source or recursion) */
+    LQCD_EHIP = -6           /* HIP runtime error */
+};
+
+enum { LQCD_PREC_64 = 64, LQCD_PREC_32 = 32, LQCD_PREC_16 = 16 };
+enum { LQCD_RECON_18 = 18, LQCD_RECON_12 = 12 };
+enum { LQCD_OP_HOP = 0, LQCD_OP_SCHUR = 1 };
+enum { LQCD_FIELD_SPINOR_PARITY = 0, LQCD_FIELD_SPINOR_FULL = 1, LQCD_FIELD_GAUGE = 2 };
+
+/* Lattice extents (x, y, z, t; all even, >= 2) and boundary phases:
+ * psi(x + L_mu mu-hat) = exp(i theta_mu) psi(x). */
+typedef struct {
+    int32_t L[4];
+    double theta[4];
+} lqcd_geom;
+
+/* kappa, twisted mass a*mu (lattice units), and the storage of the fields
+ * handed to dslash_apply / dslash_eo_apply: prec 64, 32 or 16 (FP16 storage
+ * with FP32 arithmetic), recon 18 (full links) or 12 (two rows; the third
+ * is rebuilt as conj(row0 x row1), valid for SU(3) links). */
+typedef struct {
+    double kappa;
+    double mu;
+    int32_t prec;
+    int32_t recon;
+} lqcd_op;
+
+/* Solver parameters.
+ *   tol            stop when ||b - M x||_2 / ||b||_2 <= tol (full system, FP64)
+ *   maxiter        iteration limit (inner iterations for mixed precision)
+ *   eo             1: even-odd Schur complement; 0: full lattice
+ *   inner_prec     64: plain FP64; 32 or 16: mixed precision with an inner
+ *                  Dslash in FP32 or FP16 storage and FP64 reliable updates
+ *   inner_recon    18 or 12: links of the inner Dslash
+ *   nrhs           right-hand sides (1..16), solved together
+ *   delta_reliable reliable-update trigger (||r_low|| < delta * max ||r_low||)
+ *   use_graph      1: replay iterations from a captured HIP graph
+ *   check_every    iterations enqueued between status read-backs (>= 1) */
+typedef struct {
+    double tol;
+    int32_t maxiter;
+    int32_t eo;
+    int32_t inner_prec;
+    int32_t inner_recon;
+    int32_t nrhs;
+    int32_t use_graph;
+    double delta_reliable;
+    int32_t check_every;
+    int32_t reserved;
+} lqcd_solve_params;
+
+/* Filled by the solvers (one per right-hand side / system). */
+typedef struct {
+    int32_t status;            /* mirrors the return code */
+    int32_t iters;             /* Krylov iterations */
+    int32_t reliable_updates;  /* FP64 residual replacements (mixed precision) */
+    int32_t restarts;          /* restarts after a failed true-residual check */
+    double true_resid;         /* ||b - M x||_2 / ||b||_2 in FP64, full lattice */
+    double seconds;            /* wall time of the call */
+} lqcd_solve_info;
+
+/* Message of the last error on this thread ("" if none). */
+LQCD_API const char* lqcd_last_error(void);
+
+/* Library version string. */
+LQCD_API const char* lqcd_version(void);
+
+/* Bytes of one field in the internal layout.  kind: LQCD_FIELD_*; prec and
+ * recon as in lqcd_op (recon ignored for spinors).  nrhs fields stacked are
+ * nrhs times this size. */
+LQCD_API int lqcd_field_bytes(const lqcd_geom* geom, int32_t kind, int32_t prec, int32_t recon, size_t* bytes);
+
+/* Workspace bytes needed by dslash_* (params = NULL) or by a solver call
+ * with these parameters. */
+LQCD_API int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, const lqcd_solve_params* params,
+                         size_t* bytes);
+
+/* Canonical complex128 gauge field (device) -> internal layout at prec/recon. */
+LQCD_API int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,
+                    void* stream);
+
+/* Canonical complex128 spinors (device, nrhs stacked) -> internal full-lattice
+ * fields at prec, and back. */
+LQCD_API int lqcd_pack_spinor(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* psi_canonical, void* out,
+                     void* stream);
+LQCD_API int lqcd_unpack_spinor(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* in, void* psi_canonical,
+                       void* stream);
+
+/* out = M in (dagger = 0) or M^+ in (dagger = 1) on the full lattice; in and
+ * out are nrhs stacked full-lattice fields at op->prec, U at op->prec /
+ * op->recon.  in and out must not overlap. */
+LQCD_API int dslash_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                 int32_t dagger, int32_t nrhs, void* ws, void* stream);
+
+/* Even-odd pieces on parity fields (nrhs stacked):
+ *   op = LQCD_OP_HOP  : out = H_{p,1-p} in, the pure hopping term onto
+ *                       parity p = out_parity (in holds parity 1 - p);
+ *   op = LQCD_OP_SCHUR: out = Mhat in (dagger: Mhat^+ in) on even sites;
+ *                       out_parity must be 0; needs ws.
+ * in and out must not overlap. */
+LQCD_API int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                    int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs, void* ws, void* stream);
+
+/* Solve M x = b (nrhs stacked full-lattice FP64 fields, U internal FP64 at
+ * op->recon; op->prec must be 64) by CG on the normal equations (CGNR),
+ * tracking r = b - M x; stops on the FP64 true residual.  x is overwritten
+ * (initial guess ignored).  info: nrhs entries. */
+LQCD_API int cg_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
+             const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Same contract, BiCGStab on M (or on Mhat with eo = 1). */
+LQCD_API int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
+                   const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes,
+                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQCD_H */

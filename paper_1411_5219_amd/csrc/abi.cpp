@@ -1,0 +1,908 @@
+// C ABI of the library: argument checks, workspace planning, the operator
+// compositions (full M, Schur complement) and the Krylov solvers.
+//
+// The solvers keep every scalar on the device (see lqcd_fin.h): each
+// iteration is a fixed sequence of kernel launches whose coefficients are
+// read from the control block, so the host enqueues iterations in chunks
+// (optionally replayed from a captured HIP graph) and only reads the status
+// back once per chunk, overlapped with the next chunk.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "lqcd.h"
+#include "lqcd_device.h"
+#include "lqcd_kernels.h"
+
+using namespace lqcd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define LQCD_HIP(call)                                                                                     \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess) return set_error(LQCD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxRhs = 16;
+constexpr int kMinBlock = 64;  // smallest block size any launcher uses (partials sizing)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int make_geom(const lqcd_geom* gi, Geom* g)
+{
+    if (!gi) return set_error(LQCD_EINVAL, "geom is NULL");
+    int64_t V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = gi->L[mu];
+        if (L < 2 || (L & 1)) return set_error(LQCD_EINVAL, "extent L[%d] = %d must be even and >= 2", mu, L);
+        if (!std::isfinite(gi->theta[mu])) return set_error(LQCD_EINVAL, "theta[%d] is not finite", mu);
+        V *= L;
+    }
+    if (V / 2 > (int64_t)1 << 29) return set_error(LQCD_EINVAL, "volume %lld too large", (long long)V);
+    for (int mu = 0; mu < 4; ++mu) g->L[mu] = gi->L[mu];
+    g->Lxh = gi->L[0] / 2;
+    g->Vh = (int)(V / 2);
+    g->S = (int64_t)align_up((size_t)g->Vh, 256);
+    for (int mu = 0; mu < 4; ++mu) {
+        g->ph[mu][0] = std::cos(gi->theta[mu]);
+        g->ph[mu][1] = std::sin(gi->theta[mu]);
+    }
+    return LQCD_OK;
+}
+
+int check_prec(int prec, int recon)
+{
+    if (prec != 64 && prec != 32 && prec != 16) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
+    if (recon != 18 && recon != 12) return set_error(LQCD_EINVAL, "recon %d not in {18, 12}", recon);
+    if (prec == 16 && recon != 12) return set_error(LQCD_EUNSUPPORTED, "FP16 links need recon 12");
+    return LQCD_OK;
+}
+
+int check_op(const lqcd_op* op)
+{
+    if (!op) return set_error(LQCD_EINVAL, "op is NULL");
+    if (!std::isfinite(op->kappa) || !std::isfinite(op->mu)) return set_error(LQCD_EINVAL, "kappa / mu not finite");
+    return check_prec(op->prec, op->recon);
+}
+
+int64_t parity_bytes(const Geom& g, int prec) { return spinor_parity_bytes(prec, g.S); }
+int64_t gauge_bytes(const Geom& g, int prec, int recon) { return 8 * g.S * link_bytes(prec, recon); }
+
+// Spin-block coefficients of the twisted-mass site term.
+//   A = 1 + 2 i kappa mu gamma_5 : (1 + 2 i k m) on spins 0,1 and (1 - 2 i k m) on 2,3
+//   A^+ conjugates; A^-1 = (1 - 2 i kappa mu gamma_5) / (1 + 4 kappa^2 mu^2).
+SpinCoef coef_A(double k, double m, bool dag, double scale = 1.0)
+{
+    const double t = (dag ? -2.0 : 2.0) * k * m;
+    return {{scale, scale * t}, {scale, -scale * t}};
+}
+SpinCoef coef_Ainv(double k, double m, bool dag, double scale = 1.0)
+{
+    const double n = 1.0 + 4.0 * k * k * m * m;
+    const double t = (dag ? 2.0 : -2.0) * k * m;
+    return {{scale / n, scale * t / n}, {scale / n, -scale * t / n}};
+}
+SpinCoef coef_real(double v) { return {{v, 0.0}, {v, 0.0}}; }
+
+// Bump allocator over the caller's workspace.
+struct Arena {
+    char* base;
+    size_t off = 0;
+    size_t cap;
+    void* take(size_t bytes)
+    {
+        off = align_up(off, 256);
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Reduction scratch shared by every kernel of one call (kernels run in
+// stream order, so one set of partials is enough).
+struct RedScratch {
+    double* partials = nullptr;
+    unsigned* counters = nullptr;
+    Ctl* ctl = nullptr;
+};
+
+void plan_reductions(Arena& ar, const Geom& g, int nrhs, RedScratch* rs)
+{
+    const int64_t nblk = (2 * (int64_t)g.Vh + kMinBlock - 1) / kMinBlock;
+    rs->partials = static_cast<double*>(ar.take(sizeof(double) * 3 * nblk * nrhs));
+    rs->counters = static_cast<unsigned*>(ar.take(sizeof(unsigned) * kMaxRhs));
+    rs->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs));
+}
+
+// One operator bound to a gauge field, a precision and a stream.
+struct Op {
+    Geom g;
+    int prec = 64, recon = 18;
+    const void* U = nullptr;
+    double kappa = 0, mu = 0;
+    int nrhs = 1;
+    int64_t pb = 0;  // bytes of one parity field at prec
+    hipStream_t s = nullptr;
+    RedScratch rs;
+    Launch dcfg, bcfg;
+
+    DslashArgs base() const
+    {
+        DslashArgs a{};
+        a.g = g;
+        a.U = U;
+        a.st_in = a.st_out = a.st_site = a.st_add = a.st_aux = pb;
+        a.par_bytes = pb;
+        a.r.partials = rs.partials;
+        a.r.counter = rs.counters;
+        a.ctl = rs.ctl;
+        return a;
+    }
+
+    // out(parity p) = add + a * site + c * H_{p,1-p} in     (dag: H^+)
+    hipError_t hop(int p, const void* in, void* out, bool dag, SpinCoef ca, const void* site, SpinCoef cc,
+                   const void* add, int red, int fin, int pred, const void* aux = nullptr) const
+    {
+        DslashArgs a = base();
+        a.parity = p;
+        a.pred = pred;
+        a.in = in;
+        a.out = out;
+        a.site = site;
+        a.add = add;
+        a.aux = aux;
+        a.a = ca;
+        a.c = cc;
+        a.r.fin = fin;
+        return launch_dslash(prec, recon, dag, red, a, nrhs, dcfg, s);
+    }
+
+    // out = add + sgn * M in on full-lattice fields (M^+ for dag), one launch.
+    hipError_t full_M(const void* in, void* out, bool dag, double sgn, const void* add, int red, int fin, int pred,
+                      const void* aux = nullptr, int64_t st_in = -1, int64_t st_out = -1, int64_t st_add = -1) const
+    {
+        DslashArgs a = base();
+        a.full = 1;
+        a.pred = pred;
+        a.in = in;
+        a.site = in;
+        a.out = out;
+        a.add = add;
+        a.aux = aux;
+        a.st_in = a.st_site = st_in >= 0 ? st_in : 2 * pb;
+        a.st_out = st_out >= 0 ? st_out : 2 * pb;
+        a.st_add = st_add >= 0 ? st_add : 2 * pb;
+        a.st_aux = 2 * pb;
+        a.a = coef_A(kappa, mu, dag, sgn);
+        a.c = coef_real(-sgn * kappa);
+        a.r.fin = fin;
+        return launch_dslash(prec, recon, dag, red, a, nrhs, dcfg, s);
+    }
+
+    // out = add + sgn * Mhat in on even parity fields, tmp an odd field.
+    //   Mhat = A - kappa^2 H_eo A^-1 H_oe ;  Mhat^+ = A^+ - kappa^2 H^+_eo (A^-1)^+ H^+_oe
+    hipError_t schur(const void* in, void* out, void* tmp, bool dag, double sgn, const void* add, int red, int fin,
+                     int pred, const void* aux = nullptr, int64_t st_in = -1, int64_t st_add = -1) const
+    {
+        DslashArgs a = base();
+        a.parity = 1;
+        a.pred = pred;
+        a.in = in;
+        a.out = tmp;
+        a.st_in = st_in >= 0 ? st_in : pb;
+        a.c = coef_Ainv(kappa, mu, dag);
+        a.r.fin = FIN_STORE;
+        hipError_t e = launch_dslash(prec, recon, dag, RED_NONE, a, nrhs, dcfg, s);
+        if (e != hipSuccess) return e;
+        DslashArgs b = base();
+        b.parity = 0;
+        b.pred = pred;
+        b.in = tmp;
+        b.out = out;
+        b.site = in;
+        b.st_site = st_in >= 0 ? st_in : pb;
+        b.add = add;
+        b.st_add = st_add >= 0 ? st_add : pb;
+        b.aux = aux;
+        b.a = coef_A(kappa, mu, dag, sgn);
+        b.c = coef_real(-sgn * kappa * kappa);
+        b.r.fin = fin;
+        return launch_dslash(prec, recon, dag, red, b, nrhs, dcfg, s);
+    }
+
+    BlasArgs blas_base(int nsub) const
+    {
+        BlasArgs a{};
+        a.Vh = g.Vh;
+        a.S = g.S;
+        a.nsub = nsub;
+        a.sub_stride = pb;
+        const int64_t st = nsub * pb;
+        a.st_x = a.st_y = a.st_z = a.st_w = a.st_v = a.st_r0 = st;
+        a.r.partials = rs.partials;
+        a.r.counter = rs.counters;
+        a.ctl = rs.ctl;
+        return a;
+    }
+
+    hipError_t blas(int op, int nsub, int pred, int fin, void* x, void* y = nullptr, void* z = nullptr,
+                    void* w = nullptr, void* v = nullptr, const void* r0 = nullptr, SpinCoef coef = {}) const
+    {
+        BlasArgs a = blas_base(nsub);
+        a.pred = pred;
+        a.x = x;
+        a.y = y;
+        a.z = z;
+        a.w = w;
+        a.v = v;
+        a.r0 = r0;
+        a.coef = coef;
+        a.r.fin = fin;
+        return launch_blas(prec, op, a, nrhs, bcfg, s);
+    }
+};
+
+#define LQCD_K(call)                                                                                         \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess) return set_error(LQCD_EHIP, "kernel launch failed (%s): %s", #call,           \
+                                               hipGetErrorString(e_));                                       \
+    } while (0)
+
+// Pinned host mirror of the control blocks (per thread, allocated once).
+struct Pinned {
+    Ctl* buf = nullptr;  // 2 * kMaxRhs
+    ~Pinned()
+    {
+        if (buf) (void)hipHostFree(buf);
+    }
+};
+thread_local Pinned g_pinned;
+
+int pinned_ctl(Ctl** out)
+{
+    if (!g_pinned.buf) LQCD_HIP(hipHostMalloc((void**)&g_pinned.buf, sizeof(Ctl) * 2 * kMaxRhs, hipHostMallocDefault));
+    *out = g_pinned.buf;
+    return LQCD_OK;
+}
+
+enum Method { M_CG = 0, M_BICG = 1 };
+
+// Workspace plan of one solver call: the reductions first, then the vectors.
+struct SolverPlan {
+    RedScratch rs;
+    void* v[12] = {};        // FP64 (or outer-precision) vectors
+    void* lo[8] = {};        // low-precision vectors (mixed)
+    void* Ulo = nullptr;     // low-precision gauge field (mixed)
+    size_t bytes = 0;
+};
+
+int plan_solver(const Geom& g, const lqcd_op* op, const lqcd_solve_params* prm, int method, void* ws, SolverPlan* sp)
+{
+    Arena ar{static_cast<char*>(ws), 0, 0};
+    const int nrhs = prm->nrhs;
+    plan_reductions(ar, g, nrhs, &sp->rs);
+    const int64_t pb = parity_bytes(g, 64);
+    const bool eo = prm->eo != 0;
+    const int64_t vec = (eo ? 1 : 2) * pb * nrhs;
+    const bool mixed = prm->inner_prec != 64;
+    // FP64 vectors: CG eo: r p w z t bhat | BiCG eo: r r0 p v s t tmp bhat
+    //               CG full: r p w z     | BiCG full: r r0 p v s t
+    int nv = 0;
+    if (method == M_CG) nv = mixed ? 3 : (eo ? 6 : 4);
+    else nv = eo ? 8 : 6;
+    for (int i = 0; i < nv; ++i) sp->v[i] = ar.take((size_t)vec);
+    if (mixed) {
+        const int64_t lpb = parity_bytes(g, prm->inner_prec);
+        // xl rl pl wl zl tl
+        for (int i = 0; i < 6; ++i) sp->lo[i] = ar.take((size_t)(lpb * nrhs));
+        sp->Ulo = ar.take((size_t)gauge_bytes(g, prm->inner_prec, prm->inner_recon));
+    }
+    (void)op;
+    sp->bytes = align_up(ar.off, 256);
+    return LQCD_OK;
+}
+
+int check_params(const lqcd_solve_params* p, int method)
+{
+    if (!p) return set_error(LQCD_EINVAL, "params is NULL");
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return set_error(LQCD_EINVAL, "tol must be > 0");
+    if (p->maxiter < 0) return set_error(LQCD_EINVAL, "maxiter < 0");
+    if (p->nrhs < 1 || p->nrhs > kMaxRhs) return set_error(LQCD_EINVAL, "nrhs %d not in [1, %d]", p->nrhs, kMaxRhs);
+    if (p->inner_prec != 64) {
+        if (method != M_CG) return set_error(LQCD_EUNSUPPORTED, "mixed precision is implemented for CG only");
+        if (!p->eo) return set_error(LQCD_EUNSUPPORTED, "mixed precision needs eo = 1");
+        int rc = check_prec(p->inner_prec, p->inner_recon);
+        if (rc) return rc;
+        if (!(p->delta_reliable > 0.0 && p->delta_reliable < 1.0))
+            return set_error(LQCD_EINVAL, "delta_reliable must be in (0, 1)");
+    }
+    return LQCD_OK;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Runs `enqueue(k)` for chunks of iterations until every right-hand side is
+// done; the status of chunk n is read while chunk n+1 runs.
+template <class F>
+int drive(const Op& o, int nrhs, int chunk, int maxiter, bool use_graph, F&& enqueue_iter)
+{
+    Ctl* pin = nullptr;
+    int rc = pinned_ctl(&pin);
+    if (rc) return rc;
+    hipEvent_t ev[2];
+    LQCD_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    LQCD_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int result = LQCD_OK;
+    auto enqueue_chunk = [&]() -> int {
+        if (use_graph) {
+            if (!exec) {
+                LQCD_HIP(hipStreamBeginCapture(o.s, hipStreamCaptureModeThreadLocal));
+                int r = LQCD_OK;
+                for (int k = 0; k < chunk && r == LQCD_OK; ++k) r = enqueue_iter();
+                hipGraph_t gph = nullptr;
+                hipError_t e = hipStreamEndCapture(o.s, &gph);
+                if (r) return r;
+                if (e != hipSuccess) return set_error(LQCD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+                graph = gph;
+                LQCD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            LQCD_HIP(hipGraphLaunch(exec, o.s));
+            return LQCD_OK;
+        }
+        for (int k = 0; k < chunk; ++k) {
+            int r = enqueue_iter();
+            if (r) return r;
+        }
+        return LQCD_OK;
+    };
+    const int max_chunks = maxiter / chunk + 2;
+    int n = 0;
+    for (;; ++n) {
+        if (n < max_chunks) {
+            result = enqueue_chunk();
+            if (result) break;
+            hipError_t e = hipMemcpyAsync(pin + (n & 1) * kMaxRhs, o.rs.ctl, sizeof(Ctl) * nrhs, hipMemcpyDeviceToHost, o.s);
+            if (e == hipSuccess) e = hipEventRecord(ev[n & 1], o.s);
+            if (e != hipSuccess) { result = set_error(LQCD_EHIP, "status read-back: %s", hipGetErrorString(e)); break; }
+        }
+        if (n == 0) continue;
+        const int m = (n - 1) & 1;
+        hipError_t e = hipEventSynchronize(ev[m]);
+        if (e != hipSuccess) { result = set_error(LQCD_EHIP, "stream: %s", hipGetErrorString(e)); break; }
+        bool all = true;
+        for (int i = 0; i < nrhs; ++i) all = all && pin[m * kMaxRhs + i].done;
+        if (all || n >= max_chunks) break;
+    }
+    (void)hipStreamSynchronize(o.s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return result;
+}
+
+int read_ctl(const Op& o, int nrhs, std::vector<Ctl>& out)
+{
+    out.resize(nrhs);
+    LQCD_HIP(hipMemcpyAsync(out.data(), o.rs.ctl, sizeof(Ctl) * nrhs, hipMemcpyDeviceToHost, o.s));
+    LQCD_HIP(hipStreamSynchronize(o.s));
+    return LQCD_OK;
+}
+
+// The solver proper (CGNR or BiCGStab, FP64 or mixed, eo or full lattice).
+int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, const void* b, void* x,
+          const lqcd_solve_params* prm, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+{
+    const double t0 = now_s();
+    g_err[0] = 0;
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(opi))) return rc;
+    if (opi->prec != 64) return set_error(LQCD_EINVAL, "solvers take FP64 fields (op->prec = 64)");
+    if ((rc = check_params(prm, method))) return rc;
+    if (!U || !b || !x || !info) return set_error(LQCD_EINVAL, "NULL field or info pointer");
+    if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
+    if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
+    SolverPlan sp;
+    plan_solver(g, opi, prm, method, ws, &sp);
+    if (ws_bytes < sp.bytes)
+        return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, sp.bytes);
+
+    const int nrhs = prm->nrhs;
+    const bool eo = prm->eo != 0;
+    const bool mixed = prm->inner_prec != 64;
+    const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    Op o;
+    o.g = g;
+    o.prec = 64;
+    o.recon = opi->recon;
+    o.U = U;
+    o.kappa = opi->kappa;
+    o.mu = opi->mu;
+    o.nrhs = nrhs;
+    o.pb = parity_bytes(g, 64);
+    o.s = s;
+    o.rs = sp.rs;
+    o.bcfg.block = 256;
+    const int64_t pb = o.pb;
+    const int64_t fb = 2 * pb;  // full field
+    char* bc = static_cast<char*>(const_cast<void*>(b));
+    char* xc = static_cast<char*>(x);
+    const double k = opi->kappa, m = opi->mu;
+
+    LQCD_K(launch_fill_zero(sp.rs.counters, sizeof(unsigned) * kMaxRhs, s));
+    LQCD_K(launch_ctl_init(sp.rs.ctl, nrhs, prm->tol, mixed ? prm->delta_reliable : 0.0, prm->maxiter, s));
+    // ||b||^2 over the full lattice -> bb, thresh
+    {
+        BlasArgs a = o.blas_base(2);
+        a.pred = PRED_ALWAYS;
+        a.x = bc;
+        a.r.fin = FIN_BB_FULL;
+        LQCD_K(launch_blas(64, BLAS_NORM, a, nrhs, o.bcfg, s));
+    }
+
+    // Field roles.  Even-odd: parity fields (stride pb) except b and x
+    // (full fields, stride fb, even part first).
+    void* bhat = nullptr;
+    void* xe = xc;  // even half of x
+    void* r = sp.v[0];
+    if (eo) {
+        bhat = method == M_CG ? (mixed ? sp.v[2] : sp.v[5]) : sp.v[7];
+        void* t = method == M_CG ? (mixed ? sp.v[1] : sp.v[4]) : sp.v[6];
+        // t = A^-1 b_o ; bhat = b_e + kappa H_eo t
+        BlasArgs a = o.blas_base(1);
+        a.pred = PRED_ALWAYS;
+        a.x = bc + pb;
+        a.y = t;
+        a.st_x = fb;
+        a.coef = coef_Ainv(k, m, false);
+        LQCD_K(launch_blas(64, BLAS_SPIN_SCALE, a, nrhs, o.bcfg, s));
+        DslashArgs d = o.base();
+        d.parity = 0;
+        d.pred = PRED_ALWAYS;
+        d.in = t;
+        d.out = bhat;
+        d.add = bc;
+        d.st_add = fb;
+        d.c = coef_real(k);
+        LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
+        // x_e = 0
+        BlasArgs z = o.blas_base(1);
+        z.pred = PRED_ALWAYS;
+        z.y = xe;
+        z.st_y = fb;
+        LQCD_K(launch_blas(64, BLAS_ZERO, z, nrhs, o.bcfg, s));
+    } else {
+        LQCD_K(o.blas(BLAS_ZERO, 2, PRED_ALWAYS, FIN_STORE, nullptr, xc));
+    }
+
+    // Helpers with the right strides for x (full field) in eo mode.
+    const int nsub = eo ? 1 : 2;
+    auto blas_x = [&](int op, int pred, int fin, void* X, void* Y, void* Z, void* W, void* V, const void* R0) {
+        BlasArgs a = o.blas_base(nsub);
+        a.pred = pred;
+        a.x = X;
+        a.y = Y;
+        a.z = Z;
+        a.w = W;
+        a.v = V;
+        a.r0 = R0;
+        a.st_x = eo ? fb : fb;  // X is always the solution field here
+        a.r.fin = fin;
+        return launch_blas(64, op, a, nrhs, o.bcfg, s);
+    };
+    // r = rhs - Op x   (rhs = bhat for eo, b for full)
+    auto residual = [&](int red, int fin, int pred) -> hipError_t {
+        if (eo) {
+            void* t = method == M_CG ? (mixed ? sp.v[1] : sp.v[4]) : sp.v[6];
+            return o.schur(xe, r, t, false, -1.0, bhat, red, fin, pred, nullptr, fb, pb);
+        }
+        return o.full_M(xc, r, false, -1.0, bc, red, fin, pred);
+    };
+    auto apply = [&](const void* in, void* out, bool dag, int red, int fin, int pred, const void* aux) -> hipError_t {
+        if (eo) {
+            void* t = method == M_CG ? sp.v[4] : sp.v[6];
+            return o.schur(in, out, t, dag, 1.0, nullptr, red, fin, pred, aux);
+        }
+        return o.full_M(in, out, dag, 1.0, nullptr, red, fin, pred, aux);
+    };
+
+    std::vector<Ctl> ctl;
+    int restarts = 0;
+    unsigned open_mask = (nrhs >= 32) ? ~0u : ((1u << nrhs) - 1u);
+
+    if (method == M_CG && !mixed) {
+        void *p = sp.v[1], *w = sp.v[2], *z = sp.v[3];
+        auto start = [&]() -> int {
+            // r = rhs - Op x ; z = Op^+ r ; zz ; p = z
+            LQCD_K(residual(RED_NONE, FIN_STORE, PRED_ACTIVE));
+            LQCD_K(apply(r, z, true, RED_NORM, FIN_CG_ZZ, PRED_ACTIVE, nullptr));
+            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, z, p));
+            return LQCD_OK;
+        };
+        auto iter = [&]() -> int {
+            LQCD_K(apply(p, w, false, RED_NORM, FIN_CG_ALPHA, PRED_ACTIVE, nullptr));
+            LQCD_K(blas_x(BLAS_CG_XR, PRED_ACTIVE, FIN_CG_RR, xc, p, r, w, nullptr, nullptr));
+            LQCD_K(apply(r, z, true, RED_NORM, FIN_CG_BETA, PRED_ACTIVE, nullptr));
+            LQCD_K(o.blas(BLAS_CG_P, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p, z));
+            return LQCD_OK;
+        };
+        for (;;) {
+            if ((rc = start())) return rc;
+            if ((rc = drive(o, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
+            // reconstruct and check the true residual
+            if (eo) {
+                DslashArgs d = o.base();
+                d.parity = 1;
+                d.pred = PRED_ALWAYS;
+                d.in = xe;
+                d.st_in = fb;
+                d.out = xc + pb;
+                d.st_out = fb;
+                d.site = bc + pb;
+                d.st_site = fb;
+                d.a = coef_Ainv(k, m, false);
+                d.c = coef_Ainv(k, m, false, k);
+                LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
+            }
+            LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
+            if ((rc = read_ctl(o, nrhs, ctl))) return rc;
+            unsigned reopen = 0;
+            for (int i = 0; i < nrhs; ++i) {
+                const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
+                if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) reopen |= 1u << i;
+            }
+            if (!reopen || restarts >= 20) break;
+            ++restarts;
+            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
+        }
+    } else if (method == M_CG && mixed) {
+        // FP64: r (v0), t64 (v1), bhat (v2); low: xl rl pl wl zl tl
+        const int lp = prm->inner_prec, lr = prm->inner_recon;
+        Op lo = o;
+        lo.prec = lp;
+        lo.recon = lr;
+        lo.U = sp.Ulo;
+        lo.pb = parity_bytes(g, lp);
+        void *xl = sp.lo[0], *rl = sp.lo[1], *pl = sp.lo[2], *wl = sp.lo[3], *zl = sp.lo[4], *tl = sp.lo[5];
+        void* t64 = sp.v[1];
+        if (opi->recon != 18) return set_error(LQCD_EUNSUPPORTED, "mixed precision reads FP64/18 links");
+        LQCD_K(launch_convert_gauge(lp, lr, g, U, sp.Ulo, s));
+        auto to_low = [&](void* dst, const void* src, int pred) {
+            ConvertArgs c{};
+            c.Vh = g.Vh;
+            c.S = g.S;
+            c.nsub = 1;
+            c.dst = dst;
+            c.src = const_cast<void*>(src);
+            c.rhs_stride_dst = lo.pb;
+            c.rhs_stride_src = pb;
+            c.pred = pred;
+            c.ctl = sp.rs.ctl;
+            return launch_convert(lp, 64, c, nrhs, s);
+        };
+        auto fold = [&](int pred) {  // x_e += x_low ; x_low = 0
+            ConvertArgs c{};
+            c.Vh = g.Vh;
+            c.S = g.S;
+            c.nsub = 1;
+            c.dst = xe;
+            c.src = xl;
+            c.rhs_stride_dst = fb;
+            c.rhs_stride_src = lo.pb;
+            c.accumulate = 1;
+            c.zero_src = 1;
+            c.pred = pred;
+            c.ctl = sp.rs.ctl;
+            return launch_convert(64, lp, c, nrhs, s);
+        };
+        auto start = [&]() -> int {
+            // r = bhat - Mhat x (FP64) ; rr_max ; r_low ; x_low = 0 ; z = Mhat^+ r_low ; p = z
+            LQCD_K(o.schur(xe, r, t64, false, -1.0, bhat, RED_NORM, FIN_RR_INIT, PRED_ACTIVE, nullptr, fb, pb));
+            LQCD_K(to_low(rl, r, PRED_ACTIVE));
+            LQCD_K(lo.blas(BLAS_ZERO, 1, PRED_ACTIVE, FIN_STORE, nullptr, xl));
+            LQCD_K(lo.schur(rl, zl, tl, true, 1.0, nullptr, RED_NORM, FIN_CG_ZZ, PRED_ACTIVE));
+            LQCD_K(lo.blas(BLAS_COPY, 1, PRED_ACTIVE, FIN_STORE, zl, pl));
+            return LQCD_OK;
+        };
+        auto iter = [&]() -> int {
+            LQCD_K(lo.schur(pl, wl, tl, false, 1.0, nullptr, RED_NORM, FIN_CG_ALPHA, PRED_ACTIVE));
+            LQCD_K(lo.blas(BLAS_CG_XR, 1, PRED_ACTIVE, FIN_CG_RR, xl, pl, rl, wl));
+            // reliable update (runs only when FIN_CG_RR requested it)
+            LQCD_K(fold(PRED_UPDATE));
+            LQCD_K(o.schur(xe, r, t64, false, -1.0, bhat, RED_NORM, FIN_RU_RR, PRED_UPDATE, nullptr, fb, pb));
+            LQCD_K(to_low(rl, r, PRED_UPDATE));
+            LQCD_K(lo.schur(rl, zl, tl, true, 1.0, nullptr, RED_NORM, FIN_CG_BETA, PRED_ACTIVE));
+            LQCD_K(lo.blas(BLAS_CG_P, 1, PRED_ACTIVE, FIN_STORE, nullptr, pl, zl));
+            return LQCD_OK;
+        };
+        for (;;) {
+            if ((rc = start())) return rc;
+            if ((rc = drive(o, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
+            LQCD_K(fold(PRED_ALWAYS));
+            DslashArgs d = o.base();
+            d.parity = 1;
+            d.pred = PRED_ALWAYS;
+            d.in = xe;
+            d.st_in = fb;
+            d.out = xc + pb;
+            d.st_out = fb;
+            d.site = bc + pb;
+            d.st_site = fb;
+            d.a = coef_Ainv(k, m, false);
+            d.c = coef_Ainv(k, m, false, k);
+            LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
+            LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
+            if ((rc = read_ctl(o, nrhs, ctl))) return rc;
+            unsigned reopen = 0;
+            for (int i = 0; i < nrhs; ++i) {
+                const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
+                if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) reopen |= 1u << i;
+            }
+            if (!reopen || restarts >= 20) break;
+            ++restarts;
+            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
+        }
+    } else {
+        // BiCGStab: r r0 p v s t (tmp bhat)
+        void *r0 = sp.v[1], *p = sp.v[2], *v = sp.v[3], *sv = sp.v[4], *t = sp.v[5];
+        auto start = [&]() -> int {
+            LQCD_K(residual(RED_NONE, FIN_STORE, PRED_ACTIVE));
+            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, r, r0));
+            LQCD_K(o.blas(BLAS_NORM_DOT, nsub, PRED_ACTIVE, FIN_BI_INIT, r, nullptr, nullptr, nullptr, nullptr, r0));
+            LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p));
+            LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, v));
+            return LQCD_OK;
+        };
+        auto iter = [&]() -> int {
+            LQCD_K(o.blas(BLAS_BI_P, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p, r, nullptr, v));
+            LQCD_K(apply(p, v, false, RED_DOT_AUX, FIN_BI_ALPHA, PRED_ACTIVE, r0));
+            LQCD_K(o.blas(BLAS_BI_S, nsub, PRED_ACTIVE, FIN_STORE, nullptr, nullptr, r, sv, v));
+            LQCD_K(apply(sv, t, false, RED_NORM_DS, FIN_BI_OMEGA, PRED_ACTIVE, nullptr));
+            LQCD_K(blas_x(BLAS_BI_XR, PRED_ACTIVE, FIN_BI_RHO, xc, p, r, sv, t, r0));
+            return LQCD_OK;
+        };
+        for (;;) {
+            if ((rc = start())) return rc;
+            if ((rc = drive(o, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
+            if (eo) {
+                DslashArgs d = o.base();
+                d.parity = 1;
+                d.pred = PRED_ALWAYS;
+                d.in = xe;
+                d.st_in = fb;
+                d.out = xc + pb;
+                d.st_out = fb;
+                d.site = bc + pb;
+                d.st_site = fb;
+                d.a = coef_Ainv(k, m, false);
+                d.c = coef_Ainv(k, m, false, k);
+                LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
+            }
+            LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
+            if ((rc = read_ctl(o, nrhs, ctl))) return rc;
+            unsigned reopen = 0;
+            for (int i = 0; i < nrhs; ++i) {
+                const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
+                if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) reopen |= 1u << i;
+            }
+            if (!reopen || restarts >= 20) break;
+            ++restarts;
+            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
+        }
+    }
+    (void)open_mask;
+
+    const double secs = now_s() - t0;
+    int worst = LQCD_OK;
+    for (int i = 0; i < nrhs; ++i) {
+        lqcd_solve_info& in = info[i];
+        in.iters = ctl[i].iter;
+        in.reliable_updates = ctl[i].nupdates;
+        in.restarts = restarts;
+        in.true_resid = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
+        in.seconds = secs;
+        int st = ctl[i].status;
+        if (st == LQCD_OK && in.true_resid > prm->tol) st = LQCD_ENOCONV;
+        if (st == LQCD_OK && !std::isfinite(in.true_resid)) st = LQCD_ENONFINITE;
+        in.status = st;
+        if (st != LQCD_OK && worst == LQCD_OK) worst = st;
+    }
+    if (worst != LQCD_OK) set_error(worst, "solve did not converge for every right-hand side (status %d)", worst);
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lqcd_last_error(void) { return g_err; }
+
+const char* lqcd_version(void) { return "lqcd-gfx950 1.0"; }
+
+int lqcd_field_bytes(const lqcd_geom* geom, int32_t kind, int32_t prec, int32_t recon, size_t* bytes)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if (!bytes) return set_error(LQCD_EINVAL, "bytes is NULL");
+    if (kind == LQCD_FIELD_GAUGE) {
+        if ((rc = check_prec(prec, recon))) return rc;
+        *bytes = (size_t)gauge_bytes(g, prec, recon);
+        return LQCD_OK;
+    }
+    if ((rc = check_prec(prec, 12))) return rc;
+    if (kind == LQCD_FIELD_SPINOR_PARITY) *bytes = (size_t)parity_bytes(g, prec);
+    else if (kind == LQCD_FIELD_SPINOR_FULL) *bytes = (size_t)(2 * parity_bytes(g, prec));
+    else return set_error(LQCD_EINVAL, "unknown field kind %d", kind);
+    return LQCD_OK;
+}
+
+int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, const lqcd_solve_params* params, size_t* bytes)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (!bytes) return set_error(LQCD_EINVAL, "bytes is NULL");
+    if (!params) {
+        // dslash_*: reductions plus one parity field per right-hand side
+        Arena ar{nullptr, 0, 0};
+        RedScratch rs;
+        plan_reductions(ar, g, kMaxRhs, &rs);
+        ar.take((size_t)(parity_bytes(g, op->prec) * kMaxRhs));
+        *bytes = align_up(ar.off, 256);
+        return LQCD_OK;
+    }
+    size_t best = 0;
+    for (int method = 0; method < 2; ++method) {
+        if (params->inner_prec != 64 && method == M_BICG) continue;
+        if ((rc = check_params(params, method))) return rc;
+        SolverPlan sp;
+        plan_solver(g, op, params, method, nullptr, &sp);
+        best = sp.bytes > best ? sp.bytes : best;
+    }
+    *bytes = best;
+    return LQCD_OK;
+}
+
+int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,
+                    void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_prec(prec, recon))) return rc;
+    if (!U_canonical || !U_out) return set_error(LQCD_EINVAL, "NULL pointer");
+    LQCD_K(launch_pack_gauge(prec, recon, g, U_canonical, U_out, static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
+
+int lqcd_pack_spinor(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* psi, void* out, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_prec(prec, 12))) return rc;
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    if (!psi || !out) return set_error(LQCD_EINVAL, "NULL pointer");
+    LQCD_K(launch_pack_spinor(prec, g, psi, out, nrhs, static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
+
+int lqcd_unpack_spinor(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* in, void* psi, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_prec(prec, 12))) return rc;
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    if (!psi || !in) return set_error(LQCD_EINVAL, "NULL pointer");
+    LQCD_K(launch_unpack_spinor(prec, g, in, psi, nrhs, static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
+
+int dslash_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out, int32_t dagger,
+                 int32_t nrhs, void* ws, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    (void)ws;
+    Op o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.kappa = op->kappa;
+    o.mu = op->mu;
+    o.nrhs = nrhs;
+    o.pb = parity_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    LQCD_K(o.full_M(in, out, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS));
+    return LQCD_OK;
+}
+
+int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                    int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs, void* ws, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (out_parity != 0 && out_parity != 1) return set_error(LQCD_EINVAL, "out_parity must be 0 or 1");
+    if (nrhs < 1 || nrhs > kMaxRhs) return set_error(LQCD_EINVAL, "nrhs %d not in [1, %d]", nrhs, kMaxRhs);
+    Op o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.kappa = op->kappa;
+    o.mu = op->mu;
+    o.nrhs = nrhs;
+    o.pb = parity_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    if (op_kind == LQCD_OP_HOP) {
+        LQCD_K(o.hop(out_parity, in, out, dagger != 0, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE,
+                     FIN_STORE, PRED_ALWAYS));
+        return LQCD_OK;
+    }
+    if (op_kind == LQCD_OP_SCHUR) {
+        if (out_parity != 0) return set_error(LQCD_EINVAL, "the Schur complement acts on even sites (out_parity 0)");
+        if (!ws) return set_error(LQCD_EINVAL, "LQCD_OP_SCHUR needs a workspace");
+        Arena ar{static_cast<char*>(ws), 0, 0};
+        RedScratch rs;
+        plan_reductions(ar, g, kMaxRhs, &rs);
+        void* tmp = ar.take((size_t)(o.pb * nrhs));
+        LQCD_K(o.schur(in, out, tmp, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS));
+        return LQCD_OK;
+    }
+    return set_error(LQCD_EINVAL, "unknown op_kind %d", op_kind);
+}
+
+int cg_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
+             const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+{
+    return solve(M_CG, geom, op, U, b, x, params, info, ws, ws_bytes, stream);
+}
+
+int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
+                   const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes,
+                   void* stream)
+{
+    return solve(M_BICG, geom, op, U, b, x, params, info, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

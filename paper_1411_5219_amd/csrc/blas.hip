@@ -1,0 +1,453 @@
+// Site-local kernels: the fused BLAS-1 steps of CGNR and BiCGStab with
+// FP64 reductions, precision conversion, canonical <-> internal packing,
+// and small utilities (zero fill, control-block set-up).
+//
+// Every kernel maps one work-item to one site of a parity field and walks
+// that site's planes, so loads of one plane are coalesced across the
+// wavefront and padding sites are never touched.
+#include "lqcd.h"
+#include "lqcd_device.h"
+#include "lqcd_fin.h"
+#include "lqcd_kernels.h"
+
+namespace lqcd {
+
+template <int OP>
+struct BlasRed {
+    static constexpr int N = OP == BLAS_CG_XR ? 1 : OP == BLAS_NORM ? 1 : (OP == BLAS_BI_XR || OP == BLAS_NORM_DOT) ? 3 : 0;
+};
+
+template <class R>
+__device__ __forceinline__ cplx<R> cval(const double* d) { return {R(d[0]), R(d[1])}; }
+
+template <int PREC, int OP>
+__global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
+{
+    using IO = SpinorIO<PREC>;
+    using R = typename IO::R;
+    constexpr int N = BlasRed<OP>::N;
+    constexpr int NN = N > 0 ? N : 1;
+    const int rhs = blockIdx.y;
+    Ctl* ctl = a.ctl ? a.ctl + rhs : nullptr;
+    if (pred_skip(a.pred, ctl)) return;
+
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = (int)(gid / a.Vh);
+    const int64_t h = gid - (int64_t)sub * a.Vh;
+    const int64_t soff = (int64_t)sub * a.sub_stride;
+    const int64_t r64 = rhs;
+    const int64_t S = a.S;
+    auto P = [&](void* base, int64_t st) { return static_cast<char*>(base) + r64 * st + soff; };
+
+    double red[NN];
+#pragma unroll
+    for (int j = 0; j < NN; ++j) red[j] = 0.0;
+
+    if (sub < a.nsub) {
+        if (OP == BLAS_CG_XR) {
+            const R al = R(ctl->alpha);
+            Spinor<R> x, p, r, w;
+            IO::load(P(a.x, a.st_x), S, h, x);
+            IO::load(P(a.y, a.st_y), S, h, p);
+            IO::load(P(a.z, a.st_z), S, h, r);
+            IO::load(P(a.w, a.st_w), S, h, w);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    x.s[s][c] = x.s[s][c] + al * p.s[s][c];
+                    r.s[s][c] = r.s[s][c] - al * w.s[s][c];
+                    red[0] += (double)norm2(r.s[s][c]);
+                }
+            IO::store(P(a.x, a.st_x), S, h, x);
+            IO::store(P(a.z, a.st_z), S, h, r);
+        } else if (OP == BLAS_CG_P) {
+            const R be = R(ctl->beta);
+            Spinor<R> p, z;
+            IO::load(P(a.y, a.st_y), S, h, p);
+            IO::load(P(a.z, a.st_z), S, h, z);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) p.s[s][c] = z.s[s][c] + be * p.s[s][c];
+            IO::store(P(a.y, a.st_y), S, h, p);
+        } else if (OP == BLAS_COPY) {
+            Spinor<R> x;
+            IO::load(P(a.x, a.st_x), S, h, x);
+            IO::store(P(a.y, a.st_y), S, h, x);
+        } else if (OP == BLAS_ZERO) {
+            Spinor<R> x;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) x.s[s][c] = {R(0), R(0)};
+            IO::store(P(a.y, a.st_y), S, h, x);
+        } else if (OP == BLAS_SPIN_SCALE) {
+            const cplx<R> cu = cval<R>(a.coef.up), cl = cval<R>(a.coef.lo);
+            Spinor<R> x;
+            IO::load(P(a.x, a.st_x), S, h, x);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) x.s[s][c] = (s < 2 ? cu : cl) * x.s[s][c];
+            IO::store(P(a.y, a.st_y), S, h, x);
+        } else if (OP == BLAS_NORM) {
+            Spinor<R> x;
+            IO::load(P(a.x, a.st_x), S, h, x);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) red[0] += (double)norm2(x.s[s][c]);
+        } else if (OP == BLAS_NORM_DOT) {
+            Spinor<R> x, r0;
+            IO::load(P(a.x, a.st_x), S, h, x);
+            IO::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, r0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    red[0] += (double)norm2(x.s[s][c]);
+                    const cplx<R> d = cmulc(r0.s[s][c], x.s[s][c]);
+                    red[1] += (double)d.x;
+                    red[2] += (double)d.y;
+                }
+        } else if (OP == BLAS_XPY) {
+            Spinor<R> x, y;
+            IO::load(P(a.x, a.st_x), S, h, x);
+            IO::load(P(a.y, a.st_y), S, h, y);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) y.s[s][c] = y.s[s][c] + x.s[s][c];
+            IO::store(P(a.y, a.st_y), S, h, y);
+        } else if (OP == BLAS_BI_P) {
+            // beta = (rho / rho_old) (alpha / omega), computed in FP64
+            double t1[2], t2[2], be[2];
+            cdiv(ctl->rho, ctl->rho_old, t1);
+            cdiv(ctl->balpha, ctl->omega, t2);
+            be[0] = t1[0] * t2[0] - t1[1] * t2[1];
+            be[1] = t1[0] * t2[1] + t1[1] * t2[0];
+            const cplx<R> b = cval<R>(be), om = cval<R>(ctl->omega);
+            Spinor<R> p, r, v;
+            IO::load(P(a.y, a.st_y), S, h, p);
+            IO::load(P(a.z, a.st_z), S, h, r);
+            IO::load(P(a.v, a.st_v), S, h, v);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) p.s[s][c] = r.s[s][c] + b * (p.s[s][c] - om * v.s[s][c]);
+            IO::store(P(a.y, a.st_y), S, h, p);
+        } else if (OP == BLAS_BI_S) {
+            const cplx<R> al = cval<R>(ctl->balpha);
+            Spinor<R> r, v;
+            IO::load(P(a.z, a.st_z), S, h, r);
+            IO::load(P(a.v, a.st_v), S, h, v);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r.s[s][c] = r.s[s][c] - al * v.s[s][c];
+            IO::store(P(a.w, a.st_w), S, h, r);
+        } else if (OP == BLAS_BI_XR) {
+            const cplx<R> al = cval<R>(ctl->balpha), om = cval<R>(ctl->omega);
+            Spinor<R> x, p, sv, t, r0;
+            IO::load(P(a.x, a.st_x), S, h, x);
+            IO::load(P(a.y, a.st_y), S, h, p);
+            IO::load(P(a.w, a.st_w), S, h, sv);
+            IO::load(P(a.v, a.st_v), S, h, t);
+            IO::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, r0);
+            Spinor<R> r;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    x.s[s][c] = x.s[s][c] + al * p.s[s][c] + om * sv.s[s][c];
+                    r.s[s][c] = sv.s[s][c] - om * t.s[s][c];
+                    red[0] += (double)norm2(r.s[s][c]);
+                    const cplx<R> d = cmulc(r0.s[s][c], r.s[s][c]);
+                    red[1] += (double)d.x;
+                    red[2] += (double)d.y;
+                }
+            IO::store(P(a.x, a.st_x), S, h, x);
+            IO::store(P(a.z, a.st_z), S, h, r);
+        }
+    }
+
+    if (N > 0) {
+        const int nb = gridDim.x;
+        double* partials = a.r.partials + (int64_t)rhs * nb * NN;
+        if (block_reduce_last<NN>(red, partials, a.r.counter + rhs, nb, blockIdx.x) && threadIdx.x == 0) {
+            if (ctl) finalize<NN>(a.r.fin, ctl, red);
+        }
+    }
+}
+
+template <int PREC>
+static hipError_t blas_op(int op, const BlasArgs& a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (op) {
+#define LQCD_BLAS_CASE(OP) \
+    case OP: hipLaunchKernelGGL((k_blas<PREC, OP>), grid, block, 0, s, a); break;
+        LQCD_BLAS_CASE(BLAS_CG_XR)
+        LQCD_BLAS_CASE(BLAS_CG_P)
+        LQCD_BLAS_CASE(BLAS_COPY)
+        LQCD_BLAS_CASE(BLAS_ZERO)
+        LQCD_BLAS_CASE(BLAS_SPIN_SCALE)
+        LQCD_BLAS_CASE(BLAS_NORM)
+        LQCD_BLAS_CASE(BLAS_BI_P)
+        LQCD_BLAS_CASE(BLAS_BI_S)
+        LQCD_BLAS_CASE(BLAS_BI_XR)
+        LQCD_BLAS_CASE(BLAS_XPY)
+        LQCD_BLAS_CASE(BLAS_NORM_DOT)
+#undef LQCD_BLAS_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, hipStream_t s)
+{
+    const int blk = cfg.block;
+    const int64_t sites = (int64_t)a.Vh * a.nsub;
+    dim3 grid((unsigned)((sites + blk - 1) / blk), nrhs), block(blk);
+    if (prec == 64) return blas_op<64>(op, a, grid, block, s);
+    if (prec == 32) return blas_op<32>(op, a, grid, block, s);
+    if (prec == 16) return blas_op<16>(op, a, grid, block, s);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Precision conversion
+
+template <int PD, int PS, bool ACC>
+__global__ void __launch_bounds__(256) k_convert(const ConvertArgs a)
+{
+    const int rhs = blockIdx.y;
+    Ctl* ctl = a.ctl ? a.ctl + rhs : nullptr;
+    if (pred_skip(a.pred, ctl)) return;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = (int)(gid / a.Vh);
+    const int64_t h = gid - (int64_t)sub * a.Vh;
+    if (sub >= a.nsub) return;
+    char* dst = static_cast<char*>(a.dst) + rhs * a.rhs_stride_dst + sub * a.sub_stride_dst;
+    char* src = static_cast<char*>(a.src) + rhs * a.rhs_stride_src + sub * a.sub_stride_src;
+    using RD = typename SpinorIO<PD>::R;
+    using RS = typename SpinorIO<PS>::R;
+    Spinor<RS> v;
+    SpinorIO<PS>::load(src, a.S, h, v);
+    Spinor<RD> d;
+    if (ACC) SpinorIO<PD>::load(dst, a.S, h, d);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cplx<RD> cv = {RD(v.s[s][c].x), RD(v.s[s][c].y)};
+            d.s[s][c] = ACC ? d.s[s][c] + cv : cv;
+        }
+    SpinorIO<PD>::store(dst, a.S, h, d);
+    if (a.zero_src) {
+        Spinor<RS> z;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) z.s[s][c] = {RS(0), RS(0)};
+        SpinorIO<PS>::store(src, a.S, h, z);
+    }
+}
+
+template <int PD, int PS>
+static hipError_t convert2(const ConvertArgs& a, dim3 g, dim3 b, hipStream_t s)
+{
+    if (a.accumulate) hipLaunchKernelGGL((k_convert<PD, PS, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_convert<PD, PS, false>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int pd, int ps, const ConvertArgs& a, int nrhs, hipStream_t s)
+{
+    const int blk = 256;
+    const int64_t sites = (int64_t)a.Vh * a.nsub;
+    dim3 g((unsigned)((sites + blk - 1) / blk), nrhs), b(blk);
+    if (a.accumulate && pd != 64) return hipErrorInvalidValue;
+#define LQCD_CONV(D, S_)                               \
+    if (pd == D && ps == S_) return convert2<D, S_>(a, g, b, s);
+    LQCD_CONV(64, 64)
+    LQCD_CONV(64, 32)
+    LQCD_CONV(64, 16)
+    LQCD_CONV(32, 64)
+    LQCD_CONV(32, 32)
+    LQCD_CONV(32, 16)
+    LQCD_CONV(16, 64)
+    LQCD_CONV(16, 32)
+    LQCD_CONV(16, 16)
+#undef LQCD_CONV
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Canonical complex128 <-> internal layouts
+
+__device__ __forceinline__ int64_t canonical_site(const Geom& g, int p, int64_t h)
+{
+    const int Lxh = g.Lxh;
+    const int xh = (int)(h % Lxh);
+    int64_t r = h / Lxh;
+    const int y = (int)(r % g.L[1]);
+    r /= g.L[1];
+    const int z = (int)(r % g.L[2]);
+    const int t = (int)(r / g.L[2]);
+    const int x = 2 * xh + ((y + z + t + p) & 1);
+    return x + (int64_t)g.L[0] * (y + (int64_t)g.L[1] * (z + (int64_t)g.L[2] * t));
+}
+
+template <int PREC, bool PACK>
+__global__ void __launch_bounds__(256) k_pack_spinor(const Geom g, const double2* canon_c, double2* canon_m,
+                                                     const char* in, char* out)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    const int p = (int)(gid / g.Vh);
+    const int64_t h = gid - (int64_t)p * g.Vh;
+    if (p >= 2) return;
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const int64_t i = canonical_site(g, p, h);
+    const int64_t par_bytes = spinor_parity_bytes(PREC, g.S);
+    const int64_t foff = (int64_t)rhs * 2 * par_bytes + p * par_bytes;
+    using R = typename SpinorIO<PREC>::R;
+    Spinor<R> v;
+    if (PACK) {
+        const double2* c = canon_c + ((int64_t)rhs * V + i) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v.s[k / 3][k % 3] = {R(c[k].x), R(c[k].y)};
+        SpinorIO<PREC>::store(out + foff, g.S, h, v);
+    } else {
+        SpinorIO<PREC>::load(in + foff, g.S, h, v);
+        double2* c = canon_m + ((int64_t)rhs * V + i) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) c[k] = make_double2((double)v.s[k / 3][k % 3].x, (double)v.s[k / 3][k % 3].y);
+    }
+}
+
+hipError_t launch_pack_spinor(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s)
+{
+    dim3 b(256), gr((unsigned)((2 * (int64_t)g.Vh + 255) / 256), nrhs);
+    const double2* c = static_cast<const double2*>(canon);
+    char* o = static_cast<char*>(out);
+    if (prec == 64) hipLaunchKernelGGL((k_pack_spinor<64, true>), gr, b, 0, s, g, c, nullptr, nullptr, o);
+    else if (prec == 32) hipLaunchKernelGGL((k_pack_spinor<32, true>), gr, b, 0, s, g, c, nullptr, nullptr, o);
+    else if (prec == 16) hipLaunchKernelGGL((k_pack_spinor<16, true>), gr, b, 0, s, g, c, nullptr, nullptr, o);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spinor(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s)
+{
+    dim3 b(256), gr((unsigned)((2 * (int64_t)g.Vh + 255) / 256), nrhs);
+    double2* c = static_cast<double2*>(canon);
+    const char* i = static_cast<const char*>(in);
+    if (prec == 64) hipLaunchKernelGGL((k_pack_spinor<64, false>), gr, b, 0, s, g, nullptr, c, i, nullptr);
+    else if (prec == 32) hipLaunchKernelGGL((k_pack_spinor<32, false>), gr, b, 0, s, g, nullptr, c, i, nullptr);
+    else if (prec == 16) hipLaunchKernelGGL((k_pack_spinor<16, false>), gr, b, 0, s, g, nullptr, c, i, nullptr);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int PREC, int RECON, bool FROM_CANON>
+__global__ void __launch_bounds__(256) k_pack_gauge(const Geom g, const double2* canon, const void* U64, void* out)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int blk = blockIdx.y;  // mu * 2 + parity
+    const int mu = blk >> 1, p = blk & 1;
+    if (gid >= g.Vh) return;
+    const int64_t h = gid;
+    Link<double> U;
+    if (FROM_CANON) {
+        const int64_t V = 2 * (int64_t)g.Vh;
+        const int64_t i = canonical_site(g, p, h);
+        const double2* c = canon + ((int64_t)mu * V + i) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) U.u[k / 3][k % 3] = {c[k].x, c[k].y};
+    } else {
+        LinkIO<64, 18>::load(U64, g.S, blk, h, U);
+    }
+    LinkIO<PREC, RECON>::store(out, g.S, blk, h, U);
+}
+
+template <bool FC>
+static hipError_t pack_gauge_any(int prec, int recon, const Geom& g, const void* canon, const void* U64, void* out,
+                                 hipStream_t s)
+{
+    dim3 b(256), gr((unsigned)((g.Vh + 255) / 256), 8);
+    const double2* c = static_cast<const double2*>(canon);
+    if (prec == 64 && recon == 18) hipLaunchKernelGGL((k_pack_gauge<64, 18, FC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 64 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<64, 12, FC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 32 && recon == 18) hipLaunchKernelGGL((k_pack_gauge<32, 18, FC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 32 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<32, 12, FC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 16 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<16, 12, FC>), gr, b, 0, s, g, c, U64, out);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_gauge(int prec, int recon, const Geom& g, const void* canon, void* out, hipStream_t s)
+{
+    return pack_gauge_any<true>(prec, recon, g, canon, nullptr, out, s);
+}
+
+hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, void* out, hipStream_t s)
+{
+    return pack_gauge_any<false>(prec, recon, g, nullptr, U64, out, s);
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_zero(uint4* p, int64_t n16, unsigned char* tail, int ntail)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < ntail) tail[i] = 0;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int ntail = (int)(bytes - 16 * n16);
+    const int64_t n = n16 > ntail ? n16 : ntail;
+    dim3 b(256), g((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_fill_zero, g, b, 0, s, static_cast<uint4*>(p), n16,
+                       static_cast<unsigned char*>(p) + 16 * n16, ntail);
+    return hipGetLastError();
+}
+
+__global__ void k_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrhs) return;
+    Ctl c = {};
+    c.tol2 = tol * tol;
+    c.delta2 = delta * delta;
+    c.iter_limit = iter_limit;
+    ctl[i] = c;
+}
+
+hipError_t launch_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_init, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, tol, delta, iter_limit);
+    return hipGetLastError();
+}
+
+__global__ void k_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrhs || !((mask >> i) & 1u)) return;
+    ctl[i].done = 0;
+    ctl[i].status = 0;
+    ctl[i].update = 0;
+}
+
+hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_reopen, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, mask);
+    return hipGetLastError();
+}
+
+}  // namespace lqcd

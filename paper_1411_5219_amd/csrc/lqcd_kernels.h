@@ -1,0 +1,190 @@
+// Kernel argument blocks, the device-resident solver control block, and the
+// host-side launchers of every kernel in the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lqcd {
+
+// Lattice geometry as the kernels see it.
+struct Geom {
+    int L[4];        // extents x, y, z, t (all even)
+    int Lxh;         // L[0] / 2
+    int Vh;          // sites per parity
+    int64_t S;       // plane stride in sites (Vh rounded up to 256)
+    double ph[4][2]; // exp(i theta_mu): applied on hops that cross the boundary
+};
+
+// Spin-block coefficients (upper spins 0,1 / lower spins 2,3), complex.
+struct SpinCoef {
+    double up[2];
+    double lo[2];
+};
+
+// Which scalars a reduction produces (totals per right-hand side):
+//   RED_NONE
+//   RED_NORM    : ||out||^2
+//   RED_NORM_DS : ||out||^2, <out, site>          (re, im)
+//   RED_DOT_AUX : <aux, out>                      (re, im)
+//   RED_NORM_DA : ||out||^2, <aux, out>           (re, im)
+enum Red { RED_NONE = 0, RED_NORM = 1, RED_NORM_DS = 2, RED_DOT_AUX = 3, RED_NORM_DA = 4 };
+
+// What the last block does with the totals of a reduction.
+enum Fin {
+    FIN_STORE = 0,        // copy totals to Ctl::red[]
+    FIN_CG_ZZ = 1,        // zz = ||z||^2 (start of CGNR)
+    FIN_CG_ALPHA = 2,     // ww = ||w||^2, alpha = zz / ww
+    FIN_CG_RR = 3,        // rr = ||r||^2, iteration done: convergence / reliable-update test
+    FIN_CG_BETA = 4,      // zz' = ||z'||^2, beta = zz' / zz, zz = zz'
+    FIN_TRUE_RR = 5,      // true_rr = ||b - M x||^2 (FP64)
+    FIN_BI_ALPHA = 6,     // alpha = rho / <r0, v>
+    FIN_BI_OMEGA = 7,     // omega = <t, s> / ||t||^2
+    FIN_BI_RHO = 8,       // rr, rho_old = rho, rho = <r0, r>, convergence / breakdown test
+    FIN_BI_INIT = 9,      // rr and rho at the start of BiCGStab
+    FIN_RU_RR = 10,       // reliable update: rr = ||r||^2 in FP64 after the update
+    FIN_BB_E = 11,        // red[0] = ||b_e||^2 (first half of ||b||^2)
+    FIN_BB = 12,          // bb = red[0] + ||b_o||^2, thresh = tol^2 * bb
+    FIN_BB_FULL = 13,     // bb = ||b||^2 of a full-lattice field, thresh = tol^2 * bb
+    FIN_RR_INIT = 14,     // rr = rr_max = ||r||^2 (start of a reliable-update solve)
+};
+
+// Predicates on the control block evaluated at the top of a kernel.
+enum Pred {
+    PRED_ALWAYS = 0,      // ignore the control block
+    PRED_ACTIVE = 1,      // skip when done
+    PRED_UPDATE = 2,      // run only while a reliable update is pending (and not done)
+    PRED_NO_UPDATE = 3,   // run only while no update is pending (and not done)
+};
+
+// Device-resident control block of one solve (one per right-hand side).
+// Kernels read their scalars from here, so no host round trip is needed
+// inside an iteration.
+struct Ctl {
+    double bb;        // ||b||^2 of the full system (stopping reference)
+    double thresh;    // tol^2 * bb
+    double zz, ww, rr, alpha, beta;
+    double rr_max;    // largest ||r||^2 since the last reliable update
+    double delta2;    // reliable-update trigger: rr < delta2 * rr_max
+    double tol2;      // tol^2
+    double true_rr;
+    double rho[2], rho_old[2], balpha[2], omega[2], r0v[2], ts[2], tt;
+    double red[6];    // FIN_STORE totals
+    int iter;         // completed iterations
+    int done;         // 1 when converged (or failed): every kernel becomes a no-op
+    int status;       // 0, or a negative LQCD error code
+    int update;       // reliable update pending
+    int nupdates;     // reliable updates performed
+    int iter_limit;   // stop (done, status ENOCONV) at this many iterations
+    int pad[2];
+};
+
+struct RedArgs {
+    double* partials;       // [nrhs][nblocks][N]
+    unsigned int* counter;  // [nrhs]
+    int fin;                // Fin
+};
+
+// Dslash_eo with a fused epilogue:
+//   out = add + a * site + c * (sum of the 8 hops of `in` onto parity `parity`)
+// with a, c spin-block coefficients; `add`, `site`, `out` may be null.
+struct DslashArgs {
+    Geom g;
+    int parity;
+    int pred;
+    const void* in;
+    void* out;
+    const void* site;
+    const void* add;
+    const void* aux;
+    const void* U;
+    SpinCoef a, c;
+    // bytes between right-hand sides of each field
+    int64_t st_in, st_out, st_site, st_add, st_aux;
+    int full;               // 1: both parities in one launch (fields are full-lattice)
+    int64_t par_bytes;      // bytes of one parity field (full = 1)
+    RedArgs r;
+    Ctl* ctl;               // per right-hand side, or null
+    int swizzle;
+};
+
+// Launch configuration picked per kernel (autotuned).
+struct Launch {
+    int block = 128;
+    int swizzle = 1;
+};
+
+// ---- launchers (return hipError_t) ----
+hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& a, int nrhs,
+                         const Launch& cfg, hipStream_t s);
+
+// Site-local BLAS-1 on parity fields of precision prec (all operands the same).
+enum Blas {
+    BLAS_CG_XR = 0,       // x += alpha p; r -= alpha w;           red ||r||^2
+    BLAS_CG_P = 1,        // p = z + beta p
+    BLAS_COPY = 2,        // y = x
+    BLAS_ZERO = 3,        // y = 0
+    BLAS_SPIN_SCALE = 4,  // y = coef * x                          (spin-block coefficient)
+    BLAS_NORM = 5,        // red ||x||^2
+    BLAS_BI_P = 6,        // p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
+    BLAS_BI_S = 7,        // s = r - alpha v
+    BLAS_BI_XR = 8,       // x += alpha p + omega s; r = s - omega t; red ||r||^2, <r0, r>
+    BLAS_XPY = 9,         // y += x
+    BLAS_NORM_DOT = 10,   // red ||x||^2, <r0, x>
+};
+
+struct BlasArgs {
+    int Vh;
+    int64_t S;
+    int nsub;               // sub-fields of Vh sites each (1: parity field, 2: full lattice)
+    int64_t sub_stride;     // bytes between sub-fields
+    int pred;
+    void* x;
+    void* y;
+    void* z;
+    void* w;
+    void* v;
+    const void* r0;
+    SpinCoef coef;
+    // bytes between right-hand sides of each operand
+    int64_t st_x, st_y, st_z, st_w, st_v, st_r0;
+    RedArgs r;
+    Ctl* ctl;
+};
+
+hipError_t launch_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, hipStream_t s);
+
+// Precision conversion of a parity field: dst(prec_dst) = src(prec_src);
+// with accumulate, dst += src (dst FP64).  Optional FP64 ||dst||^2 reduction.
+struct ConvertArgs {
+    int Vh;
+    int64_t S;
+    int nsub;
+    int64_t sub_stride_dst, sub_stride_src;
+    int64_t rhs_stride_dst, rhs_stride_src;
+    void* dst;
+    void* src;
+    int accumulate;         // dst += src
+    int zero_src;           // src = 0 afterwards
+    int pred;
+    Ctl* ctl;
+};
+hipError_t launch_convert(int prec_dst, int prec_src, const ConvertArgs& a, int nrhs, hipStream_t s);
+
+// Canonical complex128 <-> internal layouts.
+hipError_t launch_pack_spinor(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s);
+hipError_t launch_unpack_spinor(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s);
+hipError_t launch_pack_gauge(int prec, int recon, const Geom& g, const void* canon, void* out, hipStream_t s);
+// Re-encode an internal FP64/18 gauge field at another precision / recon.
+hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, void* out, hipStream_t s);
+
+// Fill memory with zero bytes through a kernel (graph-capture safe).
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// Initialise control blocks on the device.
+hipError_t launch_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit, hipStream_t s);
+// Re-open the solves whose bit is set in mask (done = 0, status = 0) after a
+// failed true-residual check.
+hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s);
+
+}  // namespace lqcd

@@ -1,0 +1,196 @@
+"""ctypes binding of the C ABI in include/lqcd.h (argument marshalling only).
+
+Every call forwards device pointers (``torch.Tensor.data_ptr()``), sizes and
+a HIP stream handle to ``lib/liblqcd.so``; all work runs in the library's
+HIP kernels.  Importing this module fails loudly if the library has not been
+built (``python -m paper_1411_5219_amd.build``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "liblqcd.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOCONV, EBREAKDOWN, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
+PREC_64, PREC_32, PREC_16 = 64, 32, 16
+RECON_18, RECON_12 = 18, 12
+OP_HOP, OP_SCHUR = 0, 1
+FIELD_SPINOR_PARITY, FIELD_SPINOR_FULL, FIELD_GAUGE = 0, 1, 2
+
+ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV: "ENOCONV",
+               EBREAKDOWN: "EBREAKDOWN", ENONFINITE: "ENONFINITE", EHIP: "EHIP"}
+
+# Every symbol the header declares.
+SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_pack_gauge",
+           "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
+           "bicgstab_solve"]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("theta", ctypes.c_double * 4)]
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("mu", ctypes.c_double), ("prec", ctypes.c_int32),
+                ("recon", ctypes.c_int32)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32), ("eo", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("inner_recon", ctypes.c_int32), ("nrhs", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LqcdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is missing: build it with "
+                          "`python -m paper_1411_5219_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, szp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)
+    G, O, P, I = ctypes.POINTER(Geom), ctypes.POINTER(Op), ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)
+    sig = {
+        "lqcd_last_error": ([], ctypes.c_char_p),
+        "lqcd_version": ([], ctypes.c_char_p),
+        "lqcd_field_bytes": ([G, i32, i32, i32, szp], ctypes.c_int),
+        "lqcd_workspace_bytes": ([G, O, P, szp], ctypes.c_int),
+        "lqcd_pack_gauge": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
+        "lqcd_pack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
+        "lqcd_unpack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
+        "dslash_apply": ([G, O, vp, vp, vp, i32, i32, vp, vp], ctypes.c_int),
+        "dslash_eo_apply": ([G, O, vp, vp, vp, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+        "cg_solve": ([G, O, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "bicgstab_solve": ([G, O, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(rc):
+    if rc != OK:
+        raise LqcdError(rc, lqcd_last_error())
+    return rc
+
+
+def geom(L, theta=(0.0, 0.0, 0.0, math.pi)) -> Geom:
+    g = Geom()
+    for m in range(4):
+        g.L[m] = int(L[m])
+        g.theta[m] = float(theta[m])
+    return g
+
+
+def op(kappa, mu=0.0, prec=64, recon=18) -> Op:
+    return Op(float(kappa), float(mu), int(prec), int(recon))
+
+
+def solve_params(tol=1e-10, maxiter=10000, eo=1, inner_prec=64, inner_recon=12, nrhs=1, use_graph=0,
+                 delta_reliable=0.1, check_every=8) -> SolveParams:
+    return SolveParams(float(tol), int(maxiter), int(eo), int(inner_prec), int(inner_recon), int(nrhs),
+                       int(use_graph), float(delta_reliable), int(check_every), 0)
+
+
+def lqcd_last_error() -> str:
+    return _lib.lqcd_last_error().decode()
+
+
+def lqcd_version() -> str:
+    return _lib.lqcd_version().decode()
+
+
+def lqcd_field_bytes(g, kind, prec, recon=18) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.lqcd_field_bytes(ctypes.byref(g), kind, prec, recon, ctypes.byref(n)))
+    return n.value
+
+
+def lqcd_workspace_bytes(g, o, params=None) -> int:
+    n = ctypes.c_size_t()
+    p = ctypes.byref(params) if params is not None else None
+    _check(_lib.lqcd_workspace_bytes(ctypes.byref(g), ctypes.byref(o), p, ctypes.byref(n)))
+    return n.value
+
+
+def lqcd_pack_gauge(g, prec, recon, U_canonical, U_out, stream=None):
+    return _check(_lib.lqcd_pack_gauge(ctypes.byref(g), prec, recon, _ptr(U_canonical), _ptr(U_out),
+                                       _stream(stream)))
+
+
+def lqcd_pack_spinor(g, prec, nrhs, psi_canonical, out, stream=None):
+    return _check(_lib.lqcd_pack_spinor(ctypes.byref(g), prec, nrhs, _ptr(psi_canonical), _ptr(out),
+                                        _stream(stream)))
+
+
+def lqcd_unpack_spinor(g, prec, nrhs, inp, psi_canonical, stream=None):
+    return _check(_lib.lqcd_unpack_spinor(ctypes.byref(g), prec, nrhs, _ptr(inp), _ptr(psi_canonical),
+                                          _stream(stream)))
+
+
+def dslash_apply(g, o, U, inp, out, dagger=0, nrhs=1, ws=None, stream=None):
+    return _check(_lib.dslash_apply(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(dagger),
+                                    int(nrhs), _ptr(ws), _stream(stream)))
+
+
+def dslash_eo_apply(g, o, U, inp, out, out_parity, op_kind=OP_HOP, dagger=0, nrhs=1, ws=None, stream=None):
+    return _check(_lib.dslash_eo_apply(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out),
+                                       int(out_parity), int(op_kind), int(dagger), int(nrhs), _ptr(ws),
+                                       _stream(stream)))
+
+
+def _solve(fn, g, o, U, b, x, params, ws, stream):
+    infos = (SolveInfo * params.nrhs)()
+    nbytes = ws.numel() * ws.element_size() if hasattr(ws, "numel") else 0
+    rc = fn(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(b), _ptr(x), ctypes.byref(params), infos, _ptr(ws),
+            nbytes, _stream(stream))
+    if rc in (EINVAL, EUNSUPPORTED, EHIP):
+        raise LqcdError(rc, lqcd_last_error())
+    return rc, [i.as_dict() for i in infos]
+
+
+def cg_solve(g, o, U, b, x, params, ws, stream=None):
+    """Returns (status, [info per right-hand side]); raises on EINVAL / EUNSUPPORTED / EHIP."""
+    return _solve(_lib.cg_solve, g, o, U, b, x, params, ws, stream)
+
+
+def bicgstab_solve(g, o, U, b, x, params, ws, stream=None):
+    return _solve(_lib.bicgstab_solve, g, o, U, b, x, params, ws, stream)

@@ -1,0 +1,91 @@
+"""The C-ABI library loads on the host, exports every symbol include/lqcd.h
+declares, and validates arguments before touching the GPU."""
+
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lqcd.h")).read()
+    return sorted(set(re.findall(r"LQCD_API\s+(?:const\s+char\s*\*|int)\s+([a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["dslash_apply", "dslash_eo_apply", "cg_solve", "bicgstab_solve"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1411_5219_amd import lqcd as L
+    names = _declared()
+    assert sorted(L.SYMBOLS) == names
+    for n in names:
+        assert hasattr(L._lib, n), n
+
+
+def test_field_sizes():
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((4, 4, 4, 4))
+    S = 256  # 128 sites per parity, padded to 256
+    assert L.lqcd_field_bytes(g, L.FIELD_SPINOR_PARITY, 64) == 192 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_SPINOR_FULL, 32) == 2 * 96 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_SPINOR_PARITY, 16) == 52 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_GAUGE, 64, 18) == 8 * 144 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_GAUGE, 32, 12) == 8 * 48 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_GAUGE, 16, 12) == 8 * 24 * S
+
+
+@pytest.mark.parametrize("L4", [(3, 4, 4, 4), (4, 4, 4, 0), (4, 4, 5, 4), (1, 2, 2, 2)])
+def test_bad_extents_rejected(L4):
+    from paper_1411_5219_amd import lqcd as L
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_field_bytes(L.geom(L4), L.FIELD_SPINOR_FULL, 64)
+    assert e.value.code == L.EINVAL
+
+
+def test_bad_arguments_rejected_before_device_work():
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((4, 4, 4, 4))
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_field_bytes(g, L.FIELD_GAUGE, 16, 18)
+    assert e.value.code == L.EUNSUPPORTED
+    with pytest.raises(L.LqcdError) as e:
+        L.dslash_apply(g, L.op(0.1), 0, 0, 0, stream=0)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.dslash_eo_apply(g, L.op(0.1), 16, 32, 48, out_parity=2, stream=0)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.dslash_eo_apply(g, L.op(0.1), 16, 32, 48, out_parity=1, op_kind=L.OP_SCHUR, stream=0, ws=64)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.dslash_apply(g, L.op(0.1, prec=48), 16, 32, 48, stream=0)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes(g, L.op(0.1), L.solve_params(nrhs=17))
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes(g, L.op(0.1), L.solve_params(inner_prec=16, inner_recon=18))
+    assert e.value.code == L.EUNSUPPORTED
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes(g, L.op(0.1), L.solve_params(tol=-1))
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes(L.geom((4, 4, 4, 4), (0, 0, 0, math.inf)), L.op(0.1))
+    assert e.value.code == L.EINVAL
+
+
+def test_workspace_grows_with_rhs_and_mixed():
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((8, 8, 8, 8))
+    o = L.op(0.16, 0.005)
+    a = L.lqcd_workspace_bytes(g, o, L.solve_params(nrhs=1))
+    b = L.lqcd_workspace_bytes(g, o, L.solve_params(nrhs=4))
+    c = L.lqcd_workspace_bytes(g, o, L.solve_params(inner_prec=32))
+    assert b > 3 * a > 0 and c > 0

@@ -1,0 +1,179 @@
+"""GPU parity of the Dslash family against the FP64 oracle.
+
+Every case runs the HIP kernels through the C ABI on seeded inputs and
+compares, site by site, with the oracle on the same inputs.  FP64 must agree
+to 1e-13 per site (relative, with an RMS floor); FP32 and FP16 storage are
+held to 1e-5 and 1e-2.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import site_rel_err
+from lattice_inputs import gauge_field, gaussian_spinor
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-13, 32: 1e-5, 16: 1e-2}
+
+# several tiles (128 sites per block) plus ragged tails; non-cubic shapes; 2^4
+LATTICES = [
+    ((2, 2, 2, 2), (0.0, 0.0, 0.0, math.pi)),
+    ((4, 6, 8, 2), (0.0, 0.0, 0.0, math.pi)),
+    ((6, 4, 6, 10), (0.3, -0.7, 1.1, math.pi + 0.2)),
+    ((8, 8, 6, 6), (0.0, 0.0, 0.0, math.pi)),
+]
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    from paper_1411_5219_amd import fields, lqcd
+    assert torch.cuda.is_available()
+    return torch, fields, lqcd
+
+
+def _setup(L4, theta, seed=0, kind="haar", eps=0.4, nrhs=None):
+    U = gauge_field(L4, kind, eps=eps, seed=1000 + seed)
+    psi = gaussian_spinor(L4, seed=2000 + seed, nrhs=nrhs)
+    return U, psi
+
+
+@pytest.mark.parametrize("L4,theta", LATTICES)
+@pytest.mark.parametrize("prec,recon", [(64, 18), (64, 12), (32, 18), (32, 12), (16, 12)])
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_full_M(mods, L4, theta, prec, recon, dagger):
+    torch, fields, lqcd = mods
+    kappa, mu = 0.13, 0.05
+    U, psi = _setup(L4, theta)
+    print(f"\n[case] full M L={L4} prec={prec} recon={recon} dagger={dagger}", flush=True)
+    lat = fields.Lattice(L4, theta)
+    Ud = lat.gauge(U, prec, recon)
+    inp = lat.spinor(psi, prec)
+    out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec)
+    lqcd.dslash_apply(lat.g, lqcd.op(kappa, mu, prec, recon), Ud, inp, out, dagger=dagger)
+    got = lat.unpack(out, prec)
+    ref = W.apply_M(U, psi, L4, theta, kappa, mu, dagger=bool(dagger))
+    err = site_rel_err(got, ref)
+    assert err <= TOL[prec], err
+
+
+@pytest.mark.parametrize("L4,theta", LATTICES[1:3])
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_eo_hop(mods, L4, theta, parity, dagger):
+    torch, fields, lqcd = mods
+    U, psi = _setup(L4, theta, seed=1, kind="exp")
+    print(f"\n[case] hop L={L4} parity={parity} dagger={dagger}", flush=True)
+    lat = fields.Lattice(L4, theta)
+    Ud = lat.gauge(U, 64, 18)
+    full = lat.spinor(psi, 64)
+    src = lat.parity_view(full, 1 - parity)
+    out = lat.empty(lqcd.FIELD_SPINOR_PARITY, 64)
+    lqcd.dslash_eo_apply(lat.g, lqcd.op(0.16, 0.0), Ud, src, out, parity, lqcd.OP_HOP, dagger)
+    # place the parity result into a full field to unpack it
+    both = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, 64)
+    both.view(2, pb)[parity].copy_(out)
+    got = W.mask(lat.unpack(both, 64), L4, parity)
+    ref = W.hop_eo(U, psi, L4, theta, parity, dagger=bool(dagger))
+    assert site_rel_err(got[W.parity(L4) == parity], ref[W.parity(L4) == parity]) <= 1e-13
+
+
+@pytest.mark.parametrize("L4,theta", LATTICES)
+@pytest.mark.parametrize("dagger", [0, 1])
+@pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
+def test_schur(mods, L4, theta, dagger, prec, recon):
+    torch, fields, lqcd = mods
+    kappa, mu = 0.16, 0.005
+    U, psi = _setup(L4, theta, seed=2, kind="exp")
+    print(f"\n[case] schur L={L4} prec={prec} dagger={dagger}", flush=True)
+    lat = fields.Lattice(L4, theta)
+    o = lqcd.op(kappa, mu, prec, recon)
+    Ud = lat.gauge(U, prec, recon)
+    full = lat.spinor(W.mask(psi, L4, 0), prec)
+    src = lat.parity_view(full, 0, prec)
+    out = lat.empty(lqcd.FIELD_SPINOR_PARITY, prec)
+    ws = lat.workspace(o)
+    lqcd.dslash_eo_apply(lat.g, o, Ud, src, out, 0, lqcd.OP_SCHUR, dagger, ws=ws)
+    both = lat.zeros(lqcd.FIELD_SPINOR_FULL, prec)
+    pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, prec)
+    both.view(2, pb)[0].copy_(out)
+    got = lat.unpack(both, prec)
+    ref = W.schur(U, W.mask(psi, L4, 0), L4, theta, kappa, mu, dagger=bool(dagger))
+    ev = W.parity(L4) == 0
+    assert site_rel_err(got[ev], ref[ev]) <= TOL[prec]
+
+
+def test_multi_rhs_equals_single(mods):
+    torch, fields, lqcd = mods
+    L4, theta = (6, 4, 6, 10), (0.0, 0.0, 0.0, math.pi)
+    U, psi = _setup(L4, theta, seed=3, kind="exp", nrhs=5)
+    print("\n[case] multi-rhs full M nrhs=5", flush=True)
+    lat = fields.Lattice(L4, theta)
+    o = lqcd.op(0.16, 0.005)
+    Ud = lat.gauge(U)
+    inp = lat.spinor(psi)
+    out = lat.empty(lqcd.FIELD_SPINOR_FULL, 64, nrhs=5)
+    lqcd.dslash_apply(lat.g, o, Ud, inp, out, nrhs=5)
+    got = lat.unpack(out, 64, nrhs=5)
+    for k in range(5):
+        one = lat.spinor(psi[k])
+        o1 = lat.empty(lqcd.FIELD_SPINOR_FULL, 64)
+        lqcd.dslash_apply(lat.g, o, Ud, one, o1)
+        assert np.array_equal(lat.unpack(o1), got[k])
+
+
+def test_pack_roundtrip(mods):
+    torch, fields, lqcd = mods
+    L4 = (6, 4, 6, 10)
+    psi = gaussian_spinor(L4, seed=5, nrhs=2)
+    lat = fields.Lattice(L4)
+    for prec, tol in [(64, 0.0), (32, 1e-7), (16, 1e-3)]:
+        back = lat.unpack(lat.spinor(psi, prec), prec, nrhs=2)
+        assert site_rel_err(back, psi) <= tol, prec
+
+
+def test_deterministic(mods):
+    torch, fields, lqcd = mods
+    L4, theta = (8, 8, 6, 6), (0.0, 0.0, 0.0, math.pi)
+    U, psi = _setup(L4, theta, seed=4, kind="exp")
+    lat = fields.Lattice(L4, theta)
+    Ud = lat.gauge(U)
+    inp = lat.spinor(psi)
+    # zero-filled so the padding sites past V/2 compare equal too
+    a = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    b = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    o = lqcd.op(0.16, 0.005)
+    lqcd.dslash_apply(lat.g, o, Ud, inp, a)
+    lqcd.dslash_apply(lat.g, o, Ud, inp, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("L4", [(24, 24, 24, 8), (48, 48, 48, 12)])
+def test_full_size_fp64(mods, L4):
+    """The production shapes (24^3x8 and 48^3x12), exp(i eps H) links at
+    eps = 0.4: the whole FP64 full-lattice M against the oracle, and FP32/12,
+    FP16/12 against their bounds."""
+    torch, fields, lqcd = mods
+    theta = (0.0, 0.0, 0.0, math.pi)
+    kappa, mu = 0.16, 0.005
+    print(f"\n[case] full-size M L={L4}", flush=True)
+    U = gauge_field(L4, "exp", eps=0.4, seed=1002)
+    psi = gaussian_spinor(L4, seed=2002)
+    ref = W.apply_M(U, psi, L4, theta, kappa, mu)
+    lat = fields.Lattice(L4, theta)
+    for prec, recon in [(64, 18), (64, 12), (32, 12), (16, 12)]:
+        Ud = lat.gauge(U, prec, recon)
+        inp = lat.spinor(psi, prec)
+        out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec)
+        lqcd.dslash_apply(lat.g, lqcd.op(kappa, mu, prec, recon), Ud, inp, out)
+        err = site_rel_err(lat.unpack(out, prec), ref)
+        print(f"  prec={prec} recon={recon} max site err={err:.3e}", flush=True)
+        assert err <= TOL[prec]
+        del Ud, inp, out
+        torch.cuda.empty_cache()
