@@ -119,7 +119,28 @@ typedef struct {
     int32_t restarts;          /* restarts after a failed true-residual check */
     double true_resid;         /* ||b - M x||_2 / ||b||_2 in FP64, full lattice */
     double seconds;            /* wall time of the call */
+    double hops_outer;         /* Dslash applications at the outer (FP64) precision, in units
+                                  of one even-odd hop over V/2 output sites */
+    double hops_inner;         /* same, at the inner precision (mixed precision only) */
 } lqcd_solve_info;
+
+/* Launch configuration of a kernel family at one storage precision:
+ *   block   work-items per block (64, 128, 192 or 256; with order = 1 the
+ *           requested size, the block then holds whole x-rows)
+ *   swizzle 1: block indices are remapped so that each of the 8 XCDs works
+ *           on a contiguous range of blocks
+ *   order   Dslash only.  0: blocks walk the sites in memory order;
+ *           1: a block covers whole x-rows at one (z, t) and blocks run
+ *           t fastest, then z, so neighbour spinors are reused from the
+ *           XCD's L2 cache.
+ * Process-wide; the defaults come from measurements on MI355X. */
+typedef struct {
+    int32_t block;
+    int32_t swizzle;
+    int32_t order;
+} lqcd_launch;
+
+enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1 };
 
 /* Message of the last error on this thread ("" if none). */
 LQCD_API const char* lqcd_last_error(void);
@@ -136,6 +157,12 @@ LQCD_API int lqcd_field_bytes(const lqcd_geom* geom, int32_t kind, int32_t prec,
  * with these parameters. */
 LQCD_API int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, const lqcd_solve_params* params,
                          size_t* bytes);
+
+/* Set / read the launch configuration of kernel family `kernel`
+ * (LQCD_KERNEL_*) at storage precision prec (64, 32, 16).  Takes effect for
+ * calls issued afterwards from any thread. */
+LQCD_API int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg);
+LQCD_API int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg);
 
 /* Canonical complex128 gauge field (device) -> internal layout at prec/recon. */
 LQCD_API int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,

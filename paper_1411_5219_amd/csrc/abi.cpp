@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lqcd.h"
@@ -40,10 +41,27 @@ int set_error(int code, const char* fmt, ...)
         if (e_ != hipSuccess) return set_error(LQCD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+#ifndef LQCD_PLANE_PAD
+#define LQCD_PLANE_PAD 1
+#endif
+
 constexpr int kMaxRhs = 16;
 constexpr int kMinBlock = 64;  // smallest block size any launcher uses (partials sizing)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Sites between consecutive planes of a field.  Planes of one site are read
+// together, so their base addresses must not share their low address bits
+// (they would compete for the same cache sets and memory channels): the
+// stride in bytes is an odd multiple of 256 for 16-byte planes.
+int64_t plane_stride(int64_t Vh)
+{
+    int64_t S = (int64_t)align_up((size_t)Vh, 16);
+#if LQCD_PLANE_PAD
+    if ((S / 16) % 2 == 0) S += 16;
+#endif
+    return S;
+}
 
 int make_geom(const lqcd_geom* gi, Geom* g)
 {
@@ -55,11 +73,13 @@ int make_geom(const lqcd_geom* gi, Geom* g)
         if (!std::isfinite(gi->theta[mu])) return set_error(LQCD_EINVAL, "theta[%d] is not finite", mu);
         V *= L;
     }
-    if (V / 2 > (int64_t)1 << 29) return set_error(LQCD_EINVAL, "volume %lld too large", (long long)V);
+    // one parity of an FP64 spinor field (192 bytes per site) must stay below
+    // 4 GiB: every field is addressed through a 32-bit-sized buffer resource
+    if (V / 2 > (int64_t)21 << 20) return set_error(LQCD_EUNSUPPORTED, "volume %lld too large for one device field", (long long)V);
     for (int mu = 0; mu < 4; ++mu) g->L[mu] = gi->L[mu];
     g->Lxh = gi->L[0] / 2;
     g->Vh = (int)(V / 2);
-    g->S = (int64_t)align_up((size_t)g->Vh, 256);
+    g->S = plane_stride(g->Vh);
     for (int mu = 0; mu < 4; ++mu) {
         g->ph[mu][0] = std::cos(gi->theta[mu]);
         g->ph[mu][1] = std::sin(gi->theta[mu]);
@@ -101,6 +121,22 @@ SpinCoef coef_Ainv(double k, double m, bool dag, double scale = 1.0)
 }
 SpinCoef coef_real(double v) { return {{v, 0.0}, {v, 0.0}}; }
 
+// Process-wide launch table: [kernel family][precision 64 / 32 / 16].
+std::mutex g_launch_mu;
+// Defaults measured on MI355X at 24^3x8 .. 64^3x16: whole x-rows per block
+// in t-fastest order with the XCD remap for the Dslash; plain 256-wide
+// blocks for the site-local kernels.
+Launch g_launch[2][3] = {{{256, 1, 1}, {256, 1, 1}, {256, 1, 1}}, {{256, 0, 0}, {256, 0, 0}, {256, 0, 0}}};
+
+int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
+
+Launch launch_for(int kernel, int prec)
+{
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    const int k = prec_slot(prec);
+    return k < 0 ? Launch{} : g_launch[kernel][k];
+}
+
 // Bump allocator over the caller's workspace.
 struct Arena {
     char* base;
@@ -119,7 +155,6 @@ struct Arena {
 // stream order, so one set of partials is enough).
 struct RedScratch {
     double* partials = nullptr;
-    unsigned* counters = nullptr;
     Ctl* ctl = nullptr;
 };
 
@@ -127,7 +162,6 @@ void plan_reductions(Arena& ar, const Geom& g, int nrhs, RedScratch* rs)
 {
     const int64_t nblk = (2 * (int64_t)g.Vh + kMinBlock - 1) / kMinBlock;
     rs->partials = static_cast<double*>(ar.take(sizeof(double) * 3 * nblk * nrhs));
-    rs->counters = static_cast<unsigned*>(ar.take(sizeof(unsigned) * kMaxRhs));
     rs->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs));
 }
 
@@ -143,6 +177,8 @@ struct Op {
     RedScratch rs;
     Launch dcfg, bcfg;
 
+    void tune() { dcfg = launch_for(LQCD_KERNEL_DSLASH, prec); bcfg = launch_for(LQCD_KERNEL_BLAS, prec); }
+
     DslashArgs base() const
     {
         DslashArgs a{};
@@ -151,7 +187,6 @@ struct Op {
         a.st_in = a.st_out = a.st_site = a.st_add = a.st_aux = pb;
         a.par_bytes = pb;
         a.r.partials = rs.partials;
-        a.r.counter = rs.counters;
         a.ctl = rs.ctl;
         return a;
     }
@@ -237,7 +272,6 @@ struct Op {
         const int64_t st = nsub * pb;
         a.st_x = a.st_y = a.st_z = a.st_w = a.st_v = a.st_r0 = st;
         a.r.partials = rs.partials;
-        a.r.counter = rs.counters;
         a.ctl = rs.ctl;
         return a;
     }
@@ -449,14 +483,13 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
     o.pb = parity_bytes(g, 64);
     o.s = s;
     o.rs = sp.rs;
-    o.bcfg.block = 256;
+    o.tune();
     const int64_t pb = o.pb;
     const int64_t fb = 2 * pb;  // full field
     char* bc = static_cast<char*>(const_cast<void*>(b));
     char* xc = static_cast<char*>(x);
     const double k = opi->kappa, m = opi->mu;
 
-    LQCD_K(launch_fill_zero(sp.rs.counters, sizeof(unsigned) * kMaxRhs, s));
     LQCD_K(launch_ctl_init(sp.rs.ctl, nrhs, prm->tol, mixed ? prm->delta_reliable : 0.0, prm->maxiter, s));
     // ||b||^2 over the full lattice -> bb, thresh
     {
@@ -590,6 +623,7 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
         lo.recon = lr;
         lo.U = sp.Ulo;
         lo.pb = parity_bytes(g, lp);
+        lo.tune();
         void *xl = sp.lo[0], *rl = sp.lo[1], *pl = sp.lo[2], *wl = sp.lo[3], *zl = sp.lo[4], *tl = sp.lo[5];
         void* t64 = sp.v[1];
         if (opi->recon != 18) return set_error(LQCD_EUNSUPPORTED, "mixed precision reads FP64/18 links");
@@ -728,6 +762,19 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
         in.restarts = restarts;
         in.true_resid = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
         in.seconds = secs;
+        // Dslash applications (eo-hop units): eo solves apply Mhat as 2 hops,
+        // full-lattice solves apply M as one launch over V = 2 x V/2 sites.
+        const double it = ctl[i].iter, starts = restarts + 1;
+        const double prep = eo ? 1.0 : 0.0;                 // bhat
+        const double finish = (eo ? 1.0 : 0.0) + 2.0;       // reconstruct, true residual (full M)
+        if (!mixed) {
+            const double per_start = method == M_CG ? 4.0 : 2.0;  // residual (+ z = Op^+ r for CG)
+            in.hops_outer = prep + starts * (per_start + finish) + 4.0 * it;
+            in.hops_inner = 0.0;
+        } else {
+            in.hops_outer = prep + starts * (2.0 + finish) + 2.0 * ctl[i].nupdates;
+            in.hops_inner = starts * 2.0 + 4.0 * it;
+        }
         int st = ctl[i].status;
         if (st == LQCD_OK && in.true_resid > prm->tol) st = LQCD_ENOCONV;
         if (st == LQCD_OK && !std::isfinite(in.true_resid)) st = LQCD_ENONFINITE;
@@ -792,6 +839,35 @@ int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, const lqcd_so
     return LQCD_OK;
 }
 
+int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
+{
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS) return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
+    const int k = prec_slot(prec);
+    if (k < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
+    if (!cfg) return set_error(LQCD_EINVAL, "cfg is NULL");
+    if (cfg->block < 64 || cfg->block > 256 || cfg->block % 64)
+        return set_error(LQCD_EINVAL, "block %d not in {64, 128, 192, 256}", cfg->block);
+    if (cfg->swizzle != 0 && cfg->swizzle != 1) return set_error(LQCD_EINVAL, "swizzle must be 0 or 1");
+    if (cfg->order != 0 && cfg->order != 1) return set_error(LQCD_EINVAL, "order must be 0 or 1");
+    if (cfg->order == 1 && kernel != LQCD_KERNEL_DSLASH) return set_error(LQCD_EINVAL, "order 1 applies to the Dslash only");
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    g_launch[kernel][k] = Launch{cfg->block, cfg->swizzle, cfg->order};
+    return LQCD_OK;
+}
+
+int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
+{
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS) return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
+    const int k = prec_slot(prec);
+    if (k < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
+    if (!cfg) return set_error(LQCD_EINVAL, "cfg is NULL");
+    const Launch l = launch_for(kernel, prec);
+    cfg->block = l.block;
+    cfg->swizzle = l.swizzle;
+    cfg->order = l.order;
+    return LQCD_OK;
+}
+
 int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,
                     void* stream)
 {
@@ -849,6 +925,7 @@ int dslash_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const 
     o.nrhs = nrhs;
     o.pb = parity_bytes(g, op->prec);
     o.s = static_cast<hipStream_t>(stream);
+    o.tune();
     LQCD_K(o.full_M(in, out, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS));
     return LQCD_OK;
 }
@@ -874,6 +951,7 @@ int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, con
     o.nrhs = nrhs;
     o.pb = parity_bytes(g, op->prec);
     o.s = static_cast<hipStream_t>(stream);
+    o.tune();
     if (op_kind == LQCD_OP_HOP) {
         LQCD_K(o.hop(out_parity, in, out, dagger != 0, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE,
                      FIN_STORE, PRED_ALWAYS));

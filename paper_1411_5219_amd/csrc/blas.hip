@@ -31,9 +31,10 @@ __global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
     Ctl* ctl = a.ctl ? a.ctl + rhs : nullptr;
     if (pred_skip(a.pred, ctl)) return;
 
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int sub = (int)(gid / a.Vh);
-    const int64_t h = gid - (int64_t)sub * a.Vh;
+    // each sub-field covers nbs whole blocks, so the sub-field is uniform per block
+    const int nbs = gridDim.x / a.nsub;
+    const int sub = blockIdx.x / nbs;
+    const int64_t h = (int64_t)(blockIdx.x - sub * nbs) * blockDim.x + threadIdx.x;
     const int64_t soff = (int64_t)sub * a.sub_stride;
     const int64_t r64 = rhs;
     const int64_t S = a.S;
@@ -43,7 +44,7 @@ __global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
 #pragma unroll
     for (int j = 0; j < NN; ++j) red[j] = 0.0;
 
-    if (sub < a.nsub) {
+    if (h < a.Vh) {
         if (OP == BLAS_CG_XR) {
             const R al = R(ctl->alpha);
             Spinor<R> x, p, r, w;
@@ -172,13 +173,7 @@ __global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
         }
     }
 
-    if (N > 0) {
-        const int nb = gridDim.x;
-        double* partials = a.r.partials + (int64_t)rhs * nb * NN;
-        if (block_reduce_last<NN>(red, partials, a.r.counter + rhs, nb, blockIdx.x) && threadIdx.x == 0) {
-            if (ctl) finalize<NN>(a.r.fin, ctl, red);
-        }
-    }
+    if (N > 0) block_reduce_store<NN>(red, a.r.partials + (int64_t)rhs * gridDim.x * NN, blockIdx.x);
 }
 
 template <int PREC>
@@ -207,12 +202,52 @@ static hipError_t blas_op(int op, const BlasArgs& a, dim3 grid, dim3 block, hipS
 hipError_t launch_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, hipStream_t s)
 {
     const int blk = cfg.block;
-    const int64_t sites = (int64_t)a.Vh * a.nsub;
-    dim3 grid((unsigned)((sites + blk - 1) / blk), nrhs), block(blk);
-    if (prec == 64) return blas_op<64>(op, a, grid, block, s);
-    if (prec == 32) return blas_op<32>(op, a, grid, block, s);
-    if (prec == 16) return blas_op<16>(op, a, grid, block, s);
-    return hipErrorInvalidValue;
+    const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
+    dim3 grid(nbs * a.nsub, nrhs), block(blk);
+    hipError_t e;
+    if (prec == 64) e = blas_op<64>(op, a, grid, block, s);
+    else if (prec == 32) e = blas_op<32>(op, a, grid, block, s);
+    else if (prec == 16) e = blas_op<16>(op, a, grid, block, s);
+    else return hipErrorInvalidValue;
+    const int N = (op == BLAS_CG_XR || op == BLAS_NORM) ? 1 : (op == BLAS_BI_XR || op == BLAS_NORM_DOT) ? 3 : 0;
+    if (e != hipSuccess || N == 0) return e;
+    return launch_finalize(N, a.r.partials, (int)grid.x, a.r.fin, a.ctl, a.pred, nrhs, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_finalize(const double* partials, int nblocks, int fin, Ctl* ctl, int pred)
+{
+    const int rhs = blockIdx.x;
+    Ctl* c = ctl + rhs;
+    if (pred_skip(pred, c)) return;
+    const double* p = partials + (int64_t)rhs * nblocks * N;
+    double v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] += p[(int64_t)b * N + j];
+    __shared__ double tot[N];
+    block_reduce_store<N>(v, tot, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) t[j] = tot[j];
+        finalize<N>(fin, c, t);
+    }
+}
+
+hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, Ctl* ctl, int pred, int nrhs,
+                           hipStream_t s)
+{
+    if (!ctl) return hipErrorInvalidValue;
+    dim3 g(nrhs), b(256);
+    if (N == 1) hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
+    else if (N == 2) hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
+    else if (N == 3) hipLaunchKernelGGL(k_finalize<3>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -224,10 +259,10 @@ __global__ void __launch_bounds__(256) k_convert(const ConvertArgs a)
     const int rhs = blockIdx.y;
     Ctl* ctl = a.ctl ? a.ctl + rhs : nullptr;
     if (pred_skip(a.pred, ctl)) return;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int sub = (int)(gid / a.Vh);
-    const int64_t h = gid - (int64_t)sub * a.Vh;
-    if (sub >= a.nsub) return;
+    const int nbs = gridDim.x / a.nsub;
+    const int sub = blockIdx.x / nbs;
+    const int64_t h = (int64_t)(blockIdx.x - sub * nbs) * blockDim.x + threadIdx.x;
+    if (h >= a.Vh) return;
     char* dst = static_cast<char*>(a.dst) + rhs * a.rhs_stride_dst + sub * a.sub_stride_dst;
     char* src = static_cast<char*>(a.src) + rhs * a.rhs_stride_src + sub * a.sub_stride_src;
     using RD = typename SpinorIO<PD>::R;
@@ -265,8 +300,8 @@ static hipError_t convert2(const ConvertArgs& a, dim3 g, dim3 b, hipStream_t s)
 hipError_t launch_convert(int pd, int ps, const ConvertArgs& a, int nrhs, hipStream_t s)
 {
     const int blk = 256;
-    const int64_t sites = (int64_t)a.Vh * a.nsub;
-    dim3 g((unsigned)((sites + blk - 1) / blk), nrhs), b(blk);
+    const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
+    dim3 g(nbs * a.nsub, nrhs), b(blk);
     if (a.accumulate && pd != 64) return hipErrorInvalidValue;
 #define LQCD_CONV(D, S_)                               \
     if (pd == D && ps == S_) return convert2<D, S_>(a, g, b, s);

@@ -114,30 +114,46 @@ __global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
     if (pred_skip(a.pred, ctl)) return;
 
     const int nb = gridDim.x;
-    const int bid = a.swizzle ? xcd_swizzle(blockIdx.x, nb) : (int)blockIdx.x;
-    int h = bid * blockDim.x + threadIdx.x;
+    int bid = a.swizzle ? xcd_swizzle(blockIdx.x, nb) : (int)blockIdx.x;
     int p = a.parity;
     int64_t poff = 0, ioff = 0;  // parity offsets of output-side / neighbour fields
-    if (a.full) {  // both parities in one launch: sites [0, Vh) even, [Vh, 2 Vh) odd
-        p = h >= a.g.Vh;
-        if (p) h -= a.g.Vh;
+    if (a.full) {  // both parities in one launch: the first nb/2 blocks even, the rest odd
+        const int nbh = nb >> 1;
+        p = bid >= nbh;
+        bid -= p * nbh;
         poff = p * a.par_bytes;
         ioff = (1 - p) * a.par_bytes;
     }
-    const int64_t r64 = rhs;
+    const int Lx = a.g.L[0], Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
+    const int Lxh = a.g.Lxh;
+    int h, xh, y, z, t;
+    bool valid;
+    if (a.rows == 0) {
+        h = bid * blockDim.x + threadIdx.x;
+        valid = h < a.g.Vh;
+        xh = h % Lxh;
+        int r = h / Lxh;
+        y = r % Ly;
+        r /= Ly;
+        z = r % Lz;
+        t = r / Lz;
+    } else {
+        t = bid % Lt;
+        const int r = bid / Lt;
+        z = r % Lz;
+        const int yc = r / Lz;
+        const int yr = threadIdx.x / Lxh;
+        xh = threadIdx.x - yr * Lxh;
+        y = yc * a.rows + yr;
+        valid = yr < a.rows && y < Ly;
+        h = xh + Lxh * (y + Ly * (z + Lz * t));
+    }
     const int64_t S = a.g.S;
+    const int64_t r64 = rhs;
 
     double tot[3] = {0.0, 0.0, 0.0};
 
-    if (h < a.g.Vh) {
-        const int Lx = a.g.L[0], Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
-        const int Lxh = a.g.Lxh;
-        const int xh = h % Lxh;
-        int r = h / Lxh;
-        const int y = r % Ly;
-        r /= Ly;
-        const int z = r % Lz;
-        const int t = r / Lz;
+    if (valid) {
         const int x = 2 * xh + ((y + z + t + p) & 1);
         const int64_t hy = Lxh, hz = (int64_t)Lxh * Ly, ht = hz * Lz;
         const int64_t base = h - xh;
@@ -209,7 +225,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) o.s[s][c] = o.s[s][c] + ad.s[s][c];
         }
-        if (a.out) SpinorIO<PREC>::store(static_cast<char*>(a.out) + r64 * a.st_out + poff, S, h, o);
+        if (a.out) SpinorIO<PREC>::template store<LQCD_OUT_AUX>(static_cast<char*>(a.out) + r64 * a.st_out + poff, S, h, o);
 
         if (RED != RED_NONE) {
             // reduce what was stored (re-read rounding of low-precision storage is not modelled)
@@ -256,10 +272,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
         double red[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) red[j] = tot[j];
-        double* partials = a.r.partials + (int64_t)rhs * nb * N;
-        if (block_reduce_last<N>(red, partials, a.r.counter + rhs, nb, blockIdx.x) && threadIdx.x == 0) {
-            if (ctl) finalize<N>(a.r.fin, ctl, red);
-        }
+        block_reduce_store<N>(red, a.r.partials + (int64_t)rhs * nb * N, blockIdx.x);
     }
 }
 
@@ -289,16 +302,40 @@ hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const Dslash
 {
     DslashArgs a = args;
     a.swizzle = cfg.swizzle;
-    const int blk = cfg.block;
+    int blk = cfg.block;
+    unsigned nbh = (unsigned)((a.g.Vh + blk - 1) / blk);
+    a.rows = 0;
+    a.nyc = 0;
+    const int Lxh = a.g.Lxh, Ly = a.g.L[1];
+    if (cfg.order == 1 && Lxh <= 256) {
+        // R whole x-rows per block: the largest divisor of Ly with R*Lxh at
+        // most the requested block size (at least one row); the block is
+        // rounded up to whole wavefronts.
+        int R = 1;
+        for (int d = 1; d <= Ly; ++d)
+            if (Ly % d == 0 && d * Lxh <= cfg.block) R = d;
+        int B = (R * Lxh + 63) / 64 * 64;
+        if (B > 256) {  // one row per block: keep the block within the kernel's bound
+            R = 1;
+            B = (Lxh + 63) / 64 * 64;
+        }
+        a.rows = R;
+        a.nyc = (Ly + R - 1) / R;
+        blk = B;
+        nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
+    }
     dim3 block(blk);
-    const int64_t sites = (int64_t)a.g.Vh * (a.full ? 2 : 1);
-    dim3 grid((unsigned)((sites + blk - 1) / blk), nrhs);
-    if (prec == 64 && recon == 18) return launch_dag<64, 18>(dagger, red, a, grid, block, s);
-    if (prec == 64 && recon == 12) return launch_dag<64, 12>(dagger, red, a, grid, block, s);
-    if (prec == 32 && recon == 18) return launch_dag<32, 18>(dagger, red, a, grid, block, s);
-    if (prec == 32 && recon == 12) return launch_dag<32, 12>(dagger, red, a, grid, block, s);
-    if (prec == 16 && recon == 12) return launch_dag<16, 12>(dagger, red, a, grid, block, s);
-    return hipErrorInvalidValue;
+    dim3 grid(nbh * (a.full ? 2u : 1u), nrhs);
+    hipError_t e;
+    if (prec == 64 && recon == 18) e = launch_dag<64, 18>(dagger, red, a, grid, block, s);
+    else if (prec == 64 && recon == 12) e = launch_dag<64, 12>(dagger, red, a, grid, block, s);
+    else if (prec == 32 && recon == 18) e = launch_dag<32, 18>(dagger, red, a, grid, block, s);
+    else if (prec == 32 && recon == 12) e = launch_dag<32, 12>(dagger, red, a, grid, block, s);
+    else if (prec == 16 && recon == 12) e = launch_dag<16, 12>(dagger, red, a, grid, block, s);
+    else return hipErrorInvalidValue;
+    if (e != hipSuccess || red == RED_NONE) return e;
+    return launch_finalize((red == RED_NORM ? 1 : red == RED_DOT_AUX ? 2 : 3), a.r.partials,
+                           (int)grid.x, a.r.fin, a.ctl, a.pred, nrhs, s);
 }
 
 }  // namespace lqcd

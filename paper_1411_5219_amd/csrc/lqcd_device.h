@@ -66,6 +66,59 @@ struct Spinor {
 };
 
 // ---------------------------------------------------------------------------
+// Memory access through buffer resources.  A field (one parity of a spinor
+// field, or one (mu, parity) block of links) is described by a buffer
+// resource built from uniform kernel arguments, so it lives in scalar
+// registers; the plane offset (uniform) goes in the scalar offset and one
+// 32-bit per-lane byte offset per site is shared by all planes.  The
+// resource carries the field size: an access outside the field returns zero
+// (loads) or is dropped (stores) instead of touching other memory.
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Buffer resource word 3 for raw (untyped, stride 0) buffers on gfx9-class
+// hardware: 32-bit data format, no swizzling.
+constexpr int kRsrcWord3 = 0x00020000;
+
+// Cache-policy bits of link loads: links are read once per application, so
+// FP64 and FP32 links are loaded non-temporally (bit 1) to spare the cached
+// neighbour spinors.  FP16 links measured faster without the hint.
+#ifndef LQCD_LINK_AUX
+#define LQCD_LINK_AUX 2
+#endif
+#ifndef LQCD_LINK16_AUX
+#define LQCD_LINK16_AUX 0
+#endif
+// Cache-policy bits of the Dslash output stores (written once).
+#ifndef LQCD_OUT_AUX
+#define LQCD_OUT_AUX 0
+#endif
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <class T, int AUX = 0>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 16) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+    else if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+}
+
+using u32x4 = __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t;
+using u32x2 = __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t;
+
+template <int AUX = 0, class T>
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, const T& v)
+{
+    if constexpr (sizeof(T) == 16) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, AUX);
+    else if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
+    else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, AUX);
+}
+
+// ---------------------------------------------------------------------------
 // Spinor storage
 
 template <int PREC>
@@ -77,20 +130,23 @@ struct SpinorIO<64> {
     static constexpr int kBytesPerSite = 192;
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v)
     {
-        const double2* p = static_cast<const double2*>(base) + site;
+        const rsrc_t r = make_rsrc(base, 192 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            double2 d = p[k * S];
+            const double2 d = bload<double2>(r, o, (uint32_t)(k * S * 16));
             v.s[k / 3][k % 3] = {d.x, d.y};
         }
     }
+    template <int AUX = 0>
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v)
     {
-        double2* p = static_cast<double2*>(base) + site;
+        const rsrc_t r = make_rsrc(base, 192 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const cplx<R> c = v.s[k / 3][k % 3];
-            p[k * S] = make_double2(c.x, c.y);
+            bstore<AUX>(r, o, (uint32_t)(k * S * 16), make_double2(c.x, c.y));
         }
     }
 };
@@ -101,22 +157,25 @@ struct SpinorIO<32> {
     static constexpr int kBytesPerSite = 96;
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v)
     {
-        const float4* p = static_cast<const float4*>(base) + site;
+        const rsrc_t r = make_rsrc(base, 96 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            float4 d = p[k * S];
+            const float4 d = bload<float4>(r, o, (uint32_t)(k * S * 16));
             v.s[(2 * k) / 3][(2 * k) % 3] = {d.x, d.y};
             v.s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {d.z, d.w};
         }
     }
+    template <int AUX = 0>
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v)
     {
-        float4* p = static_cast<float4*>(base) + site;
+        const rsrc_t r = make_rsrc(base, 96 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const cplx<R> a = v.s[(2 * k) / 3][(2 * k) % 3];
-            const cplx<R> b = v.s[(2 * k + 1) / 3][(2 * k + 1) % 3];
-            p[k * S] = make_float4(a.x, a.y, b.x, b.y);
+            const cplx<R> c = v.s[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            bstore<AUX>(r, o, (uint32_t)(k * S * 16), make_float4(a.x, a.y, c.x, c.y));
         }
     }
 };
@@ -142,12 +201,13 @@ struct SpinorIO<16> {
     }
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v)
     {
-        const uint4* p = static_cast<const uint4*>(base) + site;
-        const float scale = reinterpret_cast<const float*>(static_cast<const uint4*>(base) + 3 * S)[site];
+        const rsrc_t r = make_rsrc(base, 52 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+        const float scale = bload<float>(r, static_cast<uint32_t>(site) * 4u, (uint32_t)(3 * S * 16));
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            uint4 d = p[k * S];
-            uint32_t w[4] = {d.x, d.y, d.z, d.w};
+            const uint4 d = bload<uint4>(r, o, (uint32_t)(k * S * 16));
+            const uint32_t w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = 4 * k + j;
@@ -155,6 +215,7 @@ struct SpinorIO<16> {
             }
         }
     }
+    template <int AUX = 0>
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v)
     {
         float m = 0.f;
@@ -163,7 +224,8 @@ struct SpinorIO<16> {
 #pragma unroll
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.s[a][c].x), fabsf(v.s[a][c].y)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        uint4* p = static_cast<uint4*>(base) + site;
+        const rsrc_t r = make_rsrc(base, 52 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             uint32_t w[4];
@@ -172,9 +234,9 @@ struct SpinorIO<16> {
                 const int c = 4 * k + j;
                 w[j] = f2h2(v.s[c / 3][c % 3].x * inv, v.s[c / 3][c % 3].y * inv);
             }
-            p[k * S] = make_uint4(w[0], w[1], w[2], w[3]);
+            bstore<AUX>(r, o, (uint32_t)(k * S * 16), make_uint4(w[0], w[1], w[2], w[3]));
         }
-        reinterpret_cast<float*>(static_cast<uint4*>(base) + 3 * S)[site] = m;
+        bstore<AUX>(r, static_cast<uint32_t>(site) * 4u, (uint32_t)(3 * S * 16), m);
     }
 };
 
@@ -204,26 +266,30 @@ __device__ __forceinline__ void reconstruct_row2(Link<R>& U)
 template <int PREC, int RECON>
 struct LinkIO;
 
+// Generic plane-per-element link storage: kPlanes planes of W bytes per
+// link block (mu, parity), each holding complex entries of the link.
 template <>
 struct LinkIO<64, 18> {
     using R = double;
     static constexpr int kPlanes = 9;
-    static constexpr int kPlaneBytes = 16;
     static constexpr int kBytesPerLink = 144;
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
-        const double2* p = static_cast<const double2*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double2 d = p[k * S];
+            const double2 d = bload<double2, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 16));
             U.u[k / 3][k % 3] = {d.x, d.y};
         }
     }
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t blk, int64_t site, const Link<R>& U)
     {
-        double2* p = static_cast<double2*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) p[k * S] = make_double2(U.u[k / 3][k % 3].x, U.u[k / 3][k % 3].y);
+        for (int k = 0; k < 9; ++k)
+            bstore(r, o, (uint32_t)(k * S * 16), make_double2(U.u[k / 3][k % 3].x, U.u[k / 3][k % 3].y));
     }
 };
 
@@ -231,23 +297,25 @@ template <>
 struct LinkIO<64, 12> {
     using R = double;
     static constexpr int kPlanes = 6;
-    static constexpr int kPlaneBytes = 16;
     static constexpr int kBytesPerLink = 96;
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
-        const double2* p = static_cast<const double2*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            double2 d = p[k * S];
+            const double2 d = bload<double2, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 16));
             U.u[k / 3][k % 3] = {d.x, d.y};
         }
         reconstruct_row2(U);
     }
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t blk, int64_t site, const Link<R>& U)
     {
-        double2* p = static_cast<double2*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) p[k * S] = make_double2(U.u[k / 3][k % 3].x, U.u[k / 3][k % 3].y);
+        for (int k = 0; k < 6; ++k)
+            bstore(r, o, (uint32_t)(k * S * 16), make_double2(U.u[k / 3][k % 3].x, U.u[k / 3][k % 3].y));
     }
 };
 
@@ -255,23 +323,25 @@ template <>
 struct LinkIO<32, 18> {
     using R = float;
     static constexpr int kPlanes = 9;
-    static constexpr int kPlaneBytes = 8;
     static constexpr int kBytesPerLink = 72;
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
-        const float2* p = static_cast<const float2*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 8, kPlanes * S * 8);
+        const uint32_t o = static_cast<uint32_t>(site) * 8u;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            float2 d = p[k * S];
+            const float2 d = bload<float2, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 8));
             U.u[k / 3][k % 3] = {d.x, d.y};
         }
     }
     template <class Rin>
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t blk, int64_t site, const Link<Rin>& U)
     {
-        float2* p = static_cast<float2*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<char*>(base) + blk * kPlanes * S * 8, kPlanes * S * 8);
+        const uint32_t o = static_cast<uint32_t>(site) * 8u;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) p[k * S] = make_float2((float)U.u[k / 3][k % 3].x, (float)U.u[k / 3][k % 3].y);
+        for (int k = 0; k < 9; ++k)
+            bstore(r, o, (uint32_t)(k * S * 8), make_float2((float)U.u[k / 3][k % 3].x, (float)U.u[k / 3][k % 3].y));
     }
 };
 
@@ -279,14 +349,14 @@ template <>
 struct LinkIO<32, 12> {
     using R = float;
     static constexpr int kPlanes = 3;
-    static constexpr int kPlaneBytes = 16;
     static constexpr int kBytesPerLink = 48;
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
-        const float4* p = static_cast<const float4*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float4 d = p[k * S];
+            const float4 d = bload<float4, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 16));
             U.u[(2 * k) / 3][(2 * k) % 3] = {d.x, d.y};
             U.u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {d.z, d.w};
         }
@@ -295,28 +365,29 @@ struct LinkIO<32, 12> {
     template <class Rin>
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t blk, int64_t site, const Link<Rin>& U)
     {
-        float4* p = static_cast<float4*>(base) + blk * kPlanes * S + site;
+        const rsrc_t r = make_rsrc(static_cast<char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const auto a = U.u[(2 * k) / 3][(2 * k) % 3];
-            const auto b = U.u[(2 * k + 1) / 3][(2 * k + 1) % 3];
-            p[k * S] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+            const auto c = U.u[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            bstore(r, o, (uint32_t)(k * S * 16), make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y));
         }
     }
 };
 
-// FP16 links: SU(3) entries lie in [-1, 1], so no scale is needed.
+// FP16 links: SU(3) entries lie in [-1, 1], so no scale is needed.  A link
+// block is 24*S bytes: a plane of 8 halves (16*S bytes: row 0 and element
+// (1,0)) followed by a plane of 4 halves (8*S bytes: elements (1,1), (1,2)).
 template <>
 struct LinkIO<16, 12> {
     using R = float;
-    static constexpr int kPlanes = 0;  // mixed plane widths, see offsets below
     static constexpr int kBytesPerLink = 24;
-    // block blk occupies 24*S bytes: 16*S (uint4 plane) then 8*S (uint2 plane)
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
-        const char* b = static_cast<const char*>(base) + blk * 24 * S;
-        const uint4 d = reinterpret_cast<const uint4*>(b)[site];
-        const uint2 e = reinterpret_cast<const uint2*>(b + 16 * S)[site];
+        const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * 24 * S, 24 * S);
+        const uint4 d = bload<uint4, LQCD_LINK16_AUX>(r, static_cast<uint32_t>(site) * 16u, 0u);
+        const uint2 e = bload<uint2, LQCD_LINK16_AUX>(r, static_cast<uint32_t>(site) * 8u, (uint32_t)(16 * S));
         const uint32_t w[6] = {d.x, d.y, d.z, d.w, e.x, e.y};
 #pragma unroll
         for (int k = 0; k < 6; ++k)
@@ -326,13 +397,13 @@ struct LinkIO<16, 12> {
     template <class Rin>
     __device__ static __forceinline__ void store(void* base, int64_t S, int64_t blk, int64_t site, const Link<Rin>& U)
     {
-        char* b = static_cast<char*>(base) + blk * 24 * S;
+        const rsrc_t r = make_rsrc(static_cast<char*>(base) + blk * 24 * S, 24 * S);
         uint32_t w[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             w[k] = SpinorIO<16>::f2h2((float)U.u[k / 3][k % 3].x, (float)U.u[k / 3][k % 3].y);
-        reinterpret_cast<uint4*>(b)[site] = make_uint4(w[0], w[1], w[2], w[3]);
-        reinterpret_cast<uint2*>(b + 16 * S)[site] = make_uint2(w[4], w[5]);
+        bstore(r, static_cast<uint32_t>(site) * 16u, 0u, make_uint4(w[0], w[1], w[2], w[3]));
+        bstore(r, static_cast<uint32_t>(site) * 8u, (uint32_t)(16 * S), make_uint2(w[4], w[5]));
     }
 };
 
@@ -344,11 +415,9 @@ __host__ __device__ inline int64_t link_bytes(int prec, int recon)
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reductions.  Every thread holds N partial sums in FP64; the
-// wavefront folds them with butterfly shuffles, waves are combined in LDS in
-// wave order, and each block writes its N partials.  The last block to
-// arrive (device-scope counter) sums the block partials in block order, so
-// the result depends only on the grid shape, never on scheduling.
+// Deterministic reductions.  Every thread holds N partial sums in FP64 and
+// each block writes N partials; the totals are formed in a fixed order (see
+// block_reduce_store), so they depend only on the grid shape.
 
 template <int N>
 __device__ __forceinline__ void wave_reduce(double (&v)[N])
@@ -359,13 +428,17 @@ __device__ __forceinline__ void wave_reduce(double (&v)[N])
         for (int j = 0; j < N; ++j) v[j] += __shfl_xor(v[j], off, 64);
 }
 
-// Returns true in the (single) last block; on return in that block, thread 0
-// holds the grand totals in v.  Block size must be a multiple of 64, <= 1024.
+// Block-level part of a reduction: the wavefront folds its N sums with
+// butterfly shuffles, the waves are combined in LDS in wave order, and
+// thread 0 writes the block's N partial sums to partials[bid * N + j].
+// A separate one-block-per-right-hand-side kernel (k_finalize) sums the
+// partials in block order after the kernel boundary has made them visible,
+// so totals depend only on the grid shape, never on scheduling, and no
+// device-wide fence is needed.  Block size: a multiple of 64, <= 1024.
 template <int N>
-__device__ bool block_reduce_last(double (&v)[N], double* partials, unsigned int* counter, int nblocks, int bid)
+__device__ void block_reduce_store(double (&v)[N], double* partials, int bid)
 {
     __shared__ double sm[N][16];
-    __shared__ int am_last;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -379,37 +452,9 @@ __device__ bool block_reduce_last(double (&v)[N], double* partials, unsigned int
         for (int j = 0; j < N; ++j) {
             double s = 0.0;
             for (int w = 0; w < nwaves; ++w) s += sm[j][w];
-            __hip_atomic_store(&partials[(int64_t)bid * N + j], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            partials[(int64_t)bid * N + j] = s;
         }
-        __threadfence();
-        const unsigned int prev = atomicAdd(counter, 1u);
-        am_last = (prev == (unsigned int)(nblocks - 1));
     }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
-#pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-            v[j] += __hip_atomic_load(&partials[(int64_t)b * N + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wave_reduce<N>(v);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int j = 0; j < N; ++j) sm[j][wave] = v[j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            double s = 0.0;
-            for (int w = 0; w < nwaves; ++w) s += sm[j][w];
-            v[j] = s;
-        }
-        *counter = 0u;  // ready for the next launch (stream order)
-    }
-    return true;
 }
 
 // Block index remap that hands each XCD a contiguous range of logical

@@ -81,7 +81,6 @@ struct Ctl {
 
 struct RedArgs {
     double* partials;       // [nrhs][nblocks][N]
-    unsigned int* counter;  // [nrhs]
     int fin;                // Fin
 };
 
@@ -106,13 +105,26 @@ struct DslashArgs {
     RedArgs r;
     Ctl* ctl;               // per right-hand side, or null
     int swizzle;
+    // Block order.  rows = 0: block b covers eo sites [b*B, (b+1)*B) in
+    // memory order.  rows = R > 0: a block covers R whole x-rows at one
+    // (z, t) (a contiguous chunk of sites) and blocks run t fastest, then z,
+    // then the y-chunk, so the t and z neighbours a block reads were loaded
+    // by blocks that ran just before it on the same XCD.
+    int rows;
+    int nyc;                // y-chunks of R rows (rows > 0)
 };
 
 // Launch configuration picked per kernel (autotuned).
 struct Launch {
     int block = 128;
     int swizzle = 1;
+    int order = 0;  // 0: memory order, 1: t-fastest tiles of whole x-rows (Dslash)
 };
+
+// Sum N block partials per right-hand side in block order and run the
+// solver's scalar step (Fin) on the totals; one block per right-hand side.
+hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, Ctl* ctl, int pred, int nrhs,
+                           hipStream_t s);
 
 // ---- launchers (return hipError_t) ----
 hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& a, int nrhs,

@@ -12,7 +12,9 @@ import ctypes
 import math
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "liblqcd.so")
+# LQCD_LIBRARY selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("LQCD_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib",
+                                                          "liblqcd.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOCONV, EBREAKDOWN, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
 PREC_64, PREC_32, PREC_16 = 64, 32, 16
@@ -24,7 +26,8 @@ ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV
                EBREAKDOWN: "EBREAKDOWN", ENONFINITE: "ENONFINITE", EHIP: "EHIP"}
 
 # Every symbol the header declares.
-SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_pack_gauge",
+SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_set_launch",
+           "lqcd_get_launch", "lqcd_pack_gauge",
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
            "bicgstab_solve"]
 
@@ -45,9 +48,17 @@ class SolveParams(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("swizzle", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
+KERNEL_DSLASH, KERNEL_BLAS = 0, 1
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
-                ("restarts", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("restarts", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("hops_outer", ctypes.c_double), ("hops_inner", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,6 +82,8 @@ def _load():
         "lqcd_version": ([], ctypes.c_char_p),
         "lqcd_field_bytes": ([G, i32, i32, i32, szp], ctypes.c_int),
         "lqcd_workspace_bytes": ([G, O, P, szp], ctypes.c_int),
+        "lqcd_set_launch": ([i32, i32, ctypes.POINTER(Launch)], ctypes.c_int),
+        "lqcd_get_launch": ([i32, i32, ctypes.POINTER(Launch)], ctypes.c_int),
         "lqcd_pack_gauge": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "lqcd_pack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "lqcd_unpack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
@@ -149,6 +162,17 @@ def lqcd_workspace_bytes(g, o, params=None) -> int:
     p = ctypes.byref(params) if params is not None else None
     _check(_lib.lqcd_workspace_bytes(ctypes.byref(g), ctypes.byref(o), p, ctypes.byref(n)))
     return n.value
+
+
+def lqcd_set_launch(kernel, prec, block, swizzle=1, order=0):
+    return _check(_lib.lqcd_set_launch(int(kernel), int(prec),
+                                       ctypes.byref(Launch(int(block), int(swizzle), int(order)))))
+
+
+def lqcd_get_launch(kernel, prec):
+    l = Launch()
+    _check(_lib.lqcd_get_launch(int(kernel), int(prec), ctypes.byref(l)))
+    return {"block": l.block, "swizzle": l.swizzle, "order": l.order}
 
 
 def lqcd_pack_gauge(g, prec, recon, U_canonical, U_out, stream=None):

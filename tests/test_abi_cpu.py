@@ -32,7 +32,8 @@ def test_library_exports_every_declared_symbol():
 def test_field_sizes():
     from paper_1411_5219_amd import lqcd as L
     g = L.geom((4, 4, 4, 4))
-    S = 256  # 128 sites per parity, padded to 256
+    # 128 sites per parity; the plane stride is an odd multiple of 16 sites
+    S = 144
     assert L.lqcd_field_bytes(g, L.FIELD_SPINOR_PARITY, 64) == 192 * S
     assert L.lqcd_field_bytes(g, L.FIELD_SPINOR_FULL, 32) == 2 * 96 * S
     assert L.lqcd_field_bytes(g, L.FIELD_SPINOR_PARITY, 16) == 52 * S

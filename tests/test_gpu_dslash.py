@@ -28,6 +28,12 @@ LATTICES = [
 ]
 
 
+# launch configurations every full-M case is checked in: memory order with
+# and without the XCD remap, and row tiles in t-fastest order
+LAUNCHES = [dict(block=128, swizzle=1, order=0), dict(block=64, swizzle=0, order=0),
+            dict(block=192, swizzle=1, order=1), dict(block=64, swizzle=0, order=1)]
+
+
 @pytest.fixture(scope="module")
 def mods():
     import torch
@@ -53,12 +59,17 @@ def test_full_M(mods, L4, theta, prec, recon, dagger):
     lat = fields.Lattice(L4, theta)
     Ud = lat.gauge(U, prec, recon)
     inp = lat.spinor(psi, prec)
-    out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec)
-    lqcd.dslash_apply(lat.g, lqcd.op(kappa, mu, prec, recon), Ud, inp, out, dagger=dagger)
-    got = lat.unpack(out, prec)
     ref = W.apply_M(U, psi, L4, theta, kappa, mu, dagger=bool(dagger))
-    err = site_rel_err(got, ref)
-    assert err <= TOL[prec], err
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+    try:
+        for cfg in LAUNCHES:
+            lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **cfg)
+            out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec)
+            lqcd.dslash_apply(lat.g, lqcd.op(kappa, mu, prec, recon), Ud, inp, out, dagger=dagger)
+            err = site_rel_err(lat.unpack(out, prec), ref)
+            assert err <= TOL[prec], (cfg, err)
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
 
 
 @pytest.mark.parametrize("L4,theta", LATTICES[1:3])
