@@ -90,6 +90,26 @@ def cpu_baseline(U, b, L, theta, kappa, mu, budget_s):
             "cpu_model": cpu_model()}
 
 
+def recorded_traffic(workload):
+    """HBM bytes per launch of the FP64 hop from the committed counter passes
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for
+    a 1 GiB copy), or None when they were taken on other kernel sources."""
+    from paper_1411_5219_amd.profiling import kernel_source_digest
+
+    path = os.path.join(ROOT, "profiles", f"dslash_fp64_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None, "no counter passes recorded for this workload"
+    vals = {}
+    for line in open(path):
+        if " = " in line:
+            k, v = line.split(" = ", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != kernel_source_digest():
+        return None, "counters were taken on an older kernel"
+    t = float(vals["read_bytes"]) + float(vals["write_bytes"])
+    return t, f"{os.path.relpath(path, ROOT)}: read {float(vals['read_bytes']):.4g} B + write {float(vals['write_bytes']):.4g} B"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,7 +119,8 @@ def main():
     ap.add_argument("--hops", type=int, default=40, help="Dslash hops per precision per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--skip-solves", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--profile-hops", action="store_true",
+                    help="only run the Dslash hops of each precision and a 1 GiB copy (for counter passes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -155,8 +176,6 @@ def main():
             e1.record(stream)
             rec["hops"].setdefault(k, []).append((e0, e1))
             byts += args.hops * Vh * HOP_BYTES[k]
-        if args.skip_solves:
-            return byts
         for n, p in solves.items():
             fn = lqcd.cg_solve
             rc, info = fn(lat.g, o64, Ug[(64, 18)], bd, xs[n], p, ws[n], stream=stream)
@@ -169,6 +188,20 @@ def main():
             if p.inner_prec != 64:
                 byts += i["hops_inner"] * Vh * HOP_BYTES[inner]
         return byts
+
+    if args.profile_hops:
+        # the roofline kernels, then a plain copy of known size that calibrates the byte counters
+        for k, Uk in Ug.items():
+            for _ in range(5):
+                lqcd.dslash_eo_apply(lat.g, ops[k], Uk, hop_in[k], hop_out[k], 0, lqcd.OP_HOP, 0, stream=stream)
+        a = torch.empty((1 << 30) // 4, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_hops": True, "workload": list(L), "copy_bytes": 1 << 30}), flush=True)
+        return
 
     log(f"warmup {args.warmup} step(s)")
     for _ in range(args.warmup):
@@ -195,6 +228,7 @@ def main():
         hop_stats[f"fp{k[0]}_{k[1]}"] = {"avg_launch_us": ms * 1e3, "bytes_per_launch": bpl, "GBps": gbs,
                                          "frac_hbm_peak": gbs / HBM_PEAK_GBS}
     main_k = hop_stats["fp64_18"]
+    traffic, traffic_note = recorded_traffic(args.workload)
     solve_stats = {}
     for n, infos in rec["solves"].items():
         secs = [i["seconds"] for i in infos]
@@ -226,7 +260,8 @@ def main():
                    "hops_per_precision_per_step": args.hops},
         "roofline": {"bound": "hbm", "kernel": "k_dslash_eo<64,18> (FP64 even-odd hop)",
                      "achieved": main_k["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": main_k["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": main_k["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_note": traffic_note,
                      "bytes_per_launch": main_k["bytes_per_launch"], "avg_launch_us": main_k["avg_launch_us"]},
         "dslash": hop_stats,
         "solves": solve_stats,

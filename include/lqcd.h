@@ -164,6 +164,16 @@ LQCD_API int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, cons
 LQCD_API int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg);
 LQCD_API int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg);
 
+/* Autotuner: time every Dslash launch configuration (block 64..256, XCD
+ * remap on/off, memory or row-tile order) on this geometry with HIP events,
+ * `reps` launches each after two warm-up launches, and install the fastest
+ * as the process-wide setting for op->prec.  U, in, out are as for
+ * dslash_eo_apply with op_kind = LQCD_OP_HOP, out_parity 0, nrhs 1 (in and out
+ * are scratch; out is overwritten).  best / best_us (optional) receive the
+ * choice and its mean launch time in microseconds.  Synchronises stream. */
+LQCD_API int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                                  int32_t reps, void* stream, lqcd_launch* best, double* best_us);
+
 /* Canonical complex128 gauge field (device) -> internal layout at prec/recon. */
 LQCD_API int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,
                     void* stream);

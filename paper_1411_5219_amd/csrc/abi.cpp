@@ -155,12 +155,24 @@ struct Arena {
 // stream order, so one set of partials is enough).
 struct RedScratch {
     double* partials = nullptr;
+    int capacity = 0;  // blocks per right-hand side
     Ctl* ctl = nullptr;
 };
 
+// Most blocks any reducing launch uses: memory order with the smallest
+// block over both parities, or row tiles of one x-row each over both
+// parities (one block per (y, z, t)).
+int64_t max_blocks(const Geom& g)
+{
+    const int64_t linear = 2 * ((g.Vh + kMinBlock - 1) / kMinBlock);
+    const int64_t tiled = 2 * (int64_t)g.L[1] * g.L[2] * g.L[3];
+    return linear > tiled ? linear : tiled;
+}
+
 void plan_reductions(Arena& ar, const Geom& g, int nrhs, RedScratch* rs)
 {
-    const int64_t nblk = (2 * (int64_t)g.Vh + kMinBlock - 1) / kMinBlock;
+    const int64_t nblk = max_blocks(g);
+    rs->capacity = (int)nblk;
     rs->partials = static_cast<double*>(ar.take(sizeof(double) * 3 * nblk * nrhs));
     rs->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs));
 }
@@ -187,6 +199,7 @@ struct Op {
         a.st_in = a.st_out = a.st_site = a.st_add = a.st_aux = pb;
         a.par_bytes = pb;
         a.r.partials = rs.partials;
+        a.r.capacity = rs.capacity;
         a.ctl = rs.ctl;
         return a;
     }
@@ -272,6 +285,7 @@ struct Op {
         const int64_t st = nsub * pb;
         a.st_x = a.st_y = a.st_z = a.st_w = a.st_v = a.st_r0 = st;
         a.r.partials = rs.partials;
+        a.r.capacity = rs.capacity;
         a.ctl = rs.ctl;
         return a;
     }
@@ -865,6 +879,75 @@ int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
     cfg->block = l.block;
     cfg->swizzle = l.swizzle;
     cfg->order = l.order;
+    return LQCD_OK;
+}
+
+int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                         int32_t reps, void* stream, lqcd_launch* best, double* best_us)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (reps < 1 || reps > 10000) return set_error(LQCD_EINVAL, "reps %d out of range", reps);
+    Op o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.kappa = op->kappa;
+    o.mu = op->mu;
+    o.nrhs = 1;
+    o.pb = parity_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    LQCD_HIP(hipEventCreate(&e0));
+    LQCD_HIP(hipEventCreate(&e1));
+    Launch win{};
+    float win_ms = 0.f;
+    bool have = false;
+    int result = LQCD_OK;
+    for (int order = 0; order < 2 && !result; ++order)
+        for (int sw = 0; sw < 2 && !result; ++sw)
+            for (int blk = 64; blk <= 256 && !result; blk += 64) {
+                o.dcfg = Launch{blk, sw, order};
+                hipError_t e = hipSuccess;
+                for (int i = 0; i < 2 && e == hipSuccess; ++i)
+                    e = o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
+                              PRED_ALWAYS);
+                if (e == hipSuccess) e = hipEventRecord(e0, o.s);
+                for (int i = 0; i < reps && e == hipSuccess; ++i)
+                    e = o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
+                              PRED_ALWAYS);
+                if (e == hipSuccess) e = hipEventRecord(e1, o.s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    result = set_error(LQCD_EHIP, "autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                if (!have || ms < win_ms) {
+                    have = true;
+                    win_ms = ms;
+                    win = o.dcfg;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result) return result;
+    {
+        std::lock_guard<std::mutex> lk(g_launch_mu);
+        g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)] = win;
+    }
+    if (best) {
+        best->block = win.block;
+        best->swizzle = win.swizzle;
+        best->order = win.order;
+    }
+    if (best_us) *best_us = 1e3 * win_ms / reps;
     return LQCD_OK;
 }
 

@@ -204,6 +204,8 @@ hipError_t launch_blas(int prec, int op, const BlasArgs& a, int nrhs, const Laun
     const int blk = cfg.block;
     const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
     dim3 grid(nbs * a.nsub, nrhs), block(blk);
+    const bool reduces = op == BLAS_CG_XR || op == BLAS_NORM || op == BLAS_BI_XR || op == BLAS_NORM_DOT;
+    if (reduces && (int)grid.x > a.r.capacity) return hipErrorInvalidValue;  // partials too small
     hipError_t e;
     if (prec == 64) e = blas_op<64>(op, a, grid, block, s);
     else if (prec == 32) e = blas_op<32>(op, a, grid, block, s);

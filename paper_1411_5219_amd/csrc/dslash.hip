@@ -319,13 +319,17 @@ hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const Dslash
             R = 1;
             B = (Lxh + 63) / 64 * 64;
         }
-        a.rows = R;
-        a.nyc = (Ly + R - 1) / R;
-        blk = B;
-        nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
+        // row tiles only where they keep at least 3/4 of the lanes busy
+        if (4 * R * Lxh >= 3 * B) {
+            a.rows = R;
+            a.nyc = (Ly + R - 1) / R;
+            blk = B;
+            nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
+        }
     }
     dim3 block(blk);
     dim3 grid(nbh * (a.full ? 2u : 1u), nrhs);
+    if (red != RED_NONE && (int)grid.x > a.r.capacity) return hipErrorInvalidValue;  // partials too small
     hipError_t e;
     if (prec == 64 && recon == 18) e = launch_dag<64, 18>(dagger, red, a, grid, block, s);
     else if (prec == 64 && recon == 12) e = launch_dag<64, 12>(dagger, red, a, grid, block, s);

@@ -81,6 +81,7 @@ struct Ctl {
 
 struct RedArgs {
     double* partials;       // [nrhs][nblocks][N]
+    int capacity;           // blocks the partials hold per right-hand side (N = 3)
     int fin;                // Fin
 };
 

@@ -27,7 +27,7 @@ ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV
 
 # Every symbol the header declares.
 SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_set_launch",
-           "lqcd_get_launch", "lqcd_pack_gauge",
+           "lqcd_get_launch", "lqcd_autotune_dslash", "lqcd_pack_gauge",
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
            "bicgstab_solve"]
 
@@ -84,6 +84,8 @@ def _load():
         "lqcd_workspace_bytes": ([G, O, P, szp], ctypes.c_int),
         "lqcd_set_launch": ([i32, i32, ctypes.POINTER(Launch)], ctypes.c_int),
         "lqcd_get_launch": ([i32, i32, ctypes.POINTER(Launch)], ctypes.c_int),
+        "lqcd_autotune_dslash": ([G, O, vp, vp, vp, i32, vp, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)],
+                                 ctypes.c_int),
         "lqcd_pack_gauge": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "lqcd_pack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "lqcd_unpack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
@@ -173,6 +175,15 @@ def lqcd_get_launch(kernel, prec):
     l = Launch()
     _check(_lib.lqcd_get_launch(int(kernel), int(prec), ctypes.byref(l)))
     return {"block": l.block, "swizzle": l.swizzle, "order": l.order}
+
+
+def lqcd_autotune_dslash(g, o, U, inp, out, reps=10, stream=None):
+    """Returns ({block, swizzle, order}, mean launch microseconds) and installs the winner."""
+    best = Launch()
+    us = ctypes.c_double()
+    _check(_lib.lqcd_autotune_dslash(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(reps),
+                                     _stream(stream), ctypes.byref(best), ctypes.byref(us)))
+    return {"block": best.block, "swizzle": best.swizzle, "order": best.order}, us.value
 
 
 def lqcd_pack_gauge(g, prec, recon, U_canonical, U_out, stream=None):

@@ -188,3 +188,34 @@ def test_full_size_fp64(mods, L4):
         assert err <= TOL[prec]
         del Ud, inp, out
         torch.cuda.empty_cache()
+
+
+def test_autotune_configs_agree(mods):
+    """Every launch configuration computes each site with the same code, so
+    the FP64 results of all 16 configurations are bitwise identical; the
+    autotuner installs one of them."""
+    torch, fields, lqcd = mods
+    L4, theta = (8, 6, 10, 4), (0.0, 0.0, 0.0, math.pi)
+    U, psi = _setup(L4, theta, seed=9, kind="exp")
+    lat = fields.Lattice(L4, theta)
+    o = lqcd.op(0.16, 0.005)
+    Ud = lat.gauge(U)
+    src = lat.parity_view(lat.spinor(psi), 1)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64)
+    try:
+        outs = []
+        for order in (0, 1):
+            for sw in (0, 1):
+                for blk in (64, 128, 192, 256):
+                    lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, blk, sw, order)
+                    out = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
+                    lqcd.dslash_eo_apply(lat.g, o, Ud, src, out, 0)
+                    outs.append(out)
+        torch.cuda.synchronize()
+        for out in outs[1:]:
+            assert torch.equal(out, outs[0])
+        scratch = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
+        best, us = lqcd.lqcd_autotune_dslash(lat.g, o, Ud, src, scratch, reps=3)
+        assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64) == best and us > 0
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, **saved)
