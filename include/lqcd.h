@@ -133,11 +133,18 @@ typedef struct {
  *           1: a block covers whole x-rows at one (z, t) and blocks run
  *           t fastest, then z, so neighbour spinors are reused from the
  *           XCD's L2 cache.
+ *   rhs_tile Dslash only: right-hand sides one work-item applies each link
+ *           to (1, 2 or 4; FP64 at most 2), so links are loaded once per tile.
+ *   rhs_group Dslash only: 0, or G in 2..16: with several right-hand-side
+ *           tiles, G tiles run back to back on each spatial block, so the
+ *           links loaded for the first are re-read from L2 by the others.
  * Process-wide; the defaults come from measurements on MI355X. */
 typedef struct {
     int32_t block;
     int32_t swizzle;
     int32_t order;
+    int32_t rhs_tile;
+    int32_t rhs_group;
 } lqcd_launch;
 
 enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1 };

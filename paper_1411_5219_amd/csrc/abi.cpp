@@ -126,7 +126,10 @@ std::mutex g_launch_mu;
 // Defaults measured on MI355X at 24^3x8 .. 64^3x16: whole x-rows per block
 // in t-fastest order with the XCD remap for the Dslash; plain 256-wide
 // blocks for the site-local kernels.
-Launch g_launch[2][3] = {{{256, 1, 1}, {256, 1, 1}, {256, 1, 1}}, {{256, 0, 0}, {256, 0, 0}, {256, 0, 0}}};
+// Several right-hand sides: FP64 tiles of 2 in groups of 2, FP32 single
+// right-hand sides in groups of 4, FP16 tiles of 2 in groups of 4.
+Launch g_launch[2][3] = {{{256, 1, 1, 2, 2}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
+                         {{256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}}};
 
 int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
 
@@ -864,8 +867,12 @@ int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
     if (cfg->swizzle != 0 && cfg->swizzle != 1) return set_error(LQCD_EINVAL, "swizzle must be 0 or 1");
     if (cfg->order != 0 && cfg->order != 1) return set_error(LQCD_EINVAL, "order must be 0 or 1");
     if (cfg->order == 1 && kernel != LQCD_KERNEL_DSLASH) return set_error(LQCD_EINVAL, "order 1 applies to the Dslash only");
+    if (cfg->rhs_tile != 1 && cfg->rhs_tile != 2 && cfg->rhs_tile != 4)
+        return set_error(LQCD_EINVAL, "rhs_tile %d not in {1, 2, 4}", cfg->rhs_tile);
+    if (cfg->rhs_group != 0 && (cfg->rhs_group < 2 || cfg->rhs_group > 16))
+        return set_error(LQCD_EINVAL, "rhs_group %d not 0 or in [2, 16]", cfg->rhs_group);
     std::lock_guard<std::mutex> lk(g_launch_mu);
-    g_launch[kernel][k] = Launch{cfg->block, cfg->swizzle, cfg->order};
+    g_launch[kernel][k] = Launch{cfg->block, cfg->swizzle, cfg->order, cfg->rhs_tile, cfg->rhs_group};
     return LQCD_OK;
 }
 
@@ -879,6 +886,8 @@ int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
     cfg->block = l.block;
     cfg->swizzle = l.swizzle;
     cfg->order = l.order;
+    cfg->rhs_tile = l.rhs_tile;
+    cfg->rhs_group = l.rhs_group;
     return LQCD_OK;
 }
 
@@ -912,7 +921,7 @@ int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U
     for (int order = 0; order < 2 && !result; ++order)
         for (int sw = 0; sw < 2 && !result; ++sw)
             for (int blk = 64; blk <= 256 && !result; blk += 64) {
-                o.dcfg = Launch{blk, sw, order};
+                o.dcfg = Launch{blk, sw, order, 1, 0};
                 hipError_t e = hipSuccess;
                 for (int i = 0; i < 2 && e == hipSuccess; ++i)
                     e = o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
@@ -939,13 +948,18 @@ int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U
     (void)hipEventDestroy(e1);
     if (result) return result;
     {
+        // the right-hand-side tile is kept: it only matters for nrhs > 1
         std::lock_guard<std::mutex> lk(g_launch_mu);
+        win.rhs_tile = g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)].rhs_tile;
+        win.rhs_group = g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)].rhs_group;
         g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)] = win;
     }
     if (best) {
         best->block = win.block;
         best->swizzle = win.swizzle;
         best->order = win.order;
+        best->rhs_tile = win.rhs_tile;
+        best->rhs_group = win.rhs_group;
     }
     if (best_us) *best_us = 1e3 * win_ms / reps;
     return LQCD_OK;

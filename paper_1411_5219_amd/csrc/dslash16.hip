@@ -1,0 +1,13 @@
+// FP16-storage instantiations of the even-odd Dslash kernels.
+#include "dslash_impl.h"
+
+namespace lqcd {
+
+hipError_t launch_dslash_16(int recon, int nr, bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block,
+                               hipStream_t s)
+{
+    if (recon == 12) return launch_tile<16, 12>(nr, dag, red, a, grid, block, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lqcd

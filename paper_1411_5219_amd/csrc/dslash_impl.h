@@ -1,0 +1,381 @@
+// Even-odd Wilson / twisted-mass Dslash for gfx950 (kernel templates; each
+// storage precision is instantiated in its own translation unit).
+//
+// One work-item per output site of parity p.  For each of the 8 hops it
+// loads the neighbour spinor of parity 1-p, projects it to a 2x3 half
+// spinor with (1 -+ gamma_mu), multiplies by the link (or its adjoint),
+// applies the boundary phase on hops that cross the boundary, and rebuilds
+// the lower spin components from the upper ones.  The site-diagonal
+// twisted-mass terms are fused into the store (out = add + a*site + c*hop)
+// together with FP64 reductions, so a Schur-complement application or a
+// residual never needs a separate vector pass.
+//
+// In the chiral basis gamma_mu = [[0, B_mu], [B_mu^+, 0]] with
+//   B_x = -i sigma_1, B_y = -i sigma_2, B_z = -i sigma_3, B_t = 1,
+// so (1 - s gamma_mu) psi = (h ; -s B_mu^+ h) with h = psi_up - s B_mu psi_lo;
+// only h is multiplied by the link.
+#pragma once
+
+#include "lqcd.h"
+#include "lqcd_device.h"
+#include "lqcd_fin.h"
+#include "lqcd_kernels.h"
+
+namespace lqcd {
+
+// h = u - SIG * B_MU l   (u = spins 0,1; l = spins 2,3)
+template <class R, int MU, int SIG>
+__device__ __forceinline__ void project(const Spinor<R>& p, cplx<R> (&h)[2][3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cplx<R> u0 = p.s[0][c], u1 = p.s[1][c], l0 = p.s[2][c], l1 = p.s[3][c];
+        cplx<R> b0, b1;
+        if (MU == 0) { b0 = mti(l1); b1 = mti(l0); }        // -i sigma_1
+        else if (MU == 1) { b0 = -l1; b1 = l0; }            // -i sigma_2
+        else if (MU == 2) { b0 = mti(l0); b1 = ti(l1); }    // -i sigma_3
+        else { b0 = l0; b1 = l1; }                          // 1
+        if (SIG > 0) { h[0][c] = u0 - b0; h[1][c] = u1 - b1; }
+        else { h[0][c] = u0 + b0; h[1][c] = u1 + b1; }
+    }
+}
+
+// acc += (w ; -SIG * B_MU^+ w)
+template <class R, int MU, int SIG>
+__device__ __forceinline__ void accumulate(Spinor<R>& acc, const cplx<R> (&w)[2][3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cplx<R> w0 = w[0][c], w1 = w[1][c];
+        acc.s[0][c] = acc.s[0][c] + w0;
+        acc.s[1][c] = acc.s[1][c] + w1;
+        cplx<R> d0, d1;  // B^+ w
+        if (MU == 0) { d0 = ti(w1); d1 = ti(w0); }          // i sigma_1
+        else if (MU == 1) { d0 = w1; d1 = -w0; }            // i sigma_2
+        else if (MU == 2) { d0 = ti(w0); d1 = mti(w1); }    // i sigma_3
+        else { d0 = w0; d1 = w1; }
+        if (SIG > 0) { acc.s[2][c] = acc.s[2][c] - d0; acc.s[3][c] = acc.s[3][c] - d1; }
+        else { acc.s[2][c] = acc.s[2][c] + d0; acc.s[3][c] = acc.s[3][c] + d1; }
+    }
+}
+
+// w = U h (ADJ = false) or U^+ h (ADJ = true), on both spin components.
+template <class R, bool ADJ>
+__device__ __forceinline__ void link_mul(const Link<R>& U, const cplx<R> (&h)[2][3], cplx<R> (&w)[2][3])
+{
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cplx<R> t;
+            if (!ADJ) t = U.u[a][0] * h[s][0] + U.u[a][1] * h[s][1] + U.u[a][2] * h[s][2];
+            else t = cmulc(U.u[0][a], h[s][0]) + cmulc(U.u[1][a], h[s][1]) + cmulc(U.u[2][a], h[s][2]);
+            w[s][a] = t;
+        }
+}
+
+template <class R>
+__device__ __forceinline__ void phase_mul(cplx<R> (&w)[2][3], cplx<R> ph)
+{
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[s][a] = ph * w[s][a];
+}
+
+// One hop for a tile of NR right-hand sides: the link is loaded once and
+// applied to the neighbour spinor of every active right-hand side.
+template <int PREC, int RECON, int MU, bool FWD, int SIG, int NR>
+__device__ __forceinline__ void hop(const char* const (&in)[NR], const bool (&act)[NR], const void* U, int64_t S,
+                                    int64_t nb, int64_t lblk, int64_t lsite, bool cross, bool link_nt,
+                                    cplx<typename SpinorIO<PREC>::R> ph, Spinor<typename SpinorIO<PREC>::R> (&acc)[NR])
+{
+    using R = typename SpinorIO<PREC>::R;
+    Link<R> L;
+    if (link_nt) LinkIO<PREC, RECON>::template load<>(U, S, lblk, lsite, L);
+    else LinkIO<PREC, RECON>::template load<0>(U, S, lblk, lsite, L);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (!act[r]) continue;
+        Spinor<R> p;
+        SpinorIO<PREC>::load(in[r], S, nb, p);
+        cplx<R> h[2][3];
+        project<R, MU, SIG>(p, h);
+        cplx<R> w[2][3];
+        link_mul<R, !FWD>(L, h, w);
+        if (cross) phase_mul(w, FWD ? ph : conj(ph));
+        accumulate<R, MU, SIG>(acc[r], w);
+    }
+}
+
+template <int RED>
+struct RedN {
+    static constexpr int N = RED == RED_NONE ? 1 : RED == RED_NORM ? 1 : RED == RED_DOT_AUX ? 2 : 3;
+};
+
+// Block part of the reductions of a right-hand-side tile: NR x N sums per
+// work-item, folded per wavefront and over waves in wave order; thread 0
+// writes partials[rhs][bid][j] for each right-hand side of the tile.
+template <int NR, int N>
+__device__ void block_reduce_tile(double (&v)[NR][N], double* partials, int nb, int rhs0, int nrhs, int bid)
+{
+    __shared__ double sm[NR * N][16];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int j = 0; j < N; ++j) v[r][j] += __shfl_xor(v[r][j], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int j = 0; j < N; ++j) sm[r * N + j][wave] = v[r][j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < NR; ++r) {
+            if (rhs0 + r >= nrhs) break;
+            double* out = partials + ((int64_t)(rhs0 + r) * nb + bid) * N;
+            for (int j = 0; j < N; ++j) {
+                double s = 0.0;
+                for (int w = 0; w < nwaves; ++w) s += sm[r * N + j][w];
+                out[j] = s;
+            }
+        }
+    }
+}
+
+template <int PREC, int RECON, bool DAG, int RED, int NR>
+__global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
+{
+    using R = typename SpinorIO<PREC>::R;
+    constexpr int N = RedN<RED>::N;
+    const int nb = gridDim.x;
+    int bid = a.swizzle ? xcd_swizzle(blockIdx.x, nb) : (int)blockIdx.x;
+    int p = a.parity;
+    int64_t poff = 0, ioff = 0;  // parity offsets of output-side / neighbour fields
+    if (a.full) {  // both parities in one launch: the first nb/2 blocks even, the rest odd
+        const int nbh = nb >> 1;
+        p = bid >= nbh;
+        bid -= p * nbh;
+        poff = p * a.par_bytes;
+        ioff = (1 - p) * a.par_bytes;
+    }
+    // right-hand-side tile of this block and its spatial block
+    int tile = blockIdx.y;
+    int nsp = a.full ? nb >> 1 : nb;  // spatial blocks per parity (per tile)
+    if (a.rhs_group > 0) {
+        const int G = a.rhs_group;
+        const int ti = bid % G;
+        const int rest = bid / G;
+        nsp = a.nsp;
+        const int sp = rest % nsp;
+        tile = (rest / nsp) * G + ti;
+        bid = sp;
+    }
+    const int rhs0 = tile * NR;
+    const int pslot = bid + p * nsp;        // partials slot of this block within its right-hand side
+    const int nslots = nsp * (a.full ? 2 : 1);
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int rr = rhs0 + r;
+        act[r] = tile < a.ntiles && rr < a.nrhs && !pred_skip(a.pred, a.ctl ? a.ctl + rr : nullptr);
+        any = any || act[r];
+    }
+    if (!any) return;
+    const int Lx = a.g.L[0], Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
+    const int Lxh = a.g.Lxh;
+    int h, xh, y, z, t;
+    bool valid;
+    if (a.rows == 0) {
+        h = bid * blockDim.x + threadIdx.x;
+        valid = h < a.g.Vh;
+        xh = h % Lxh;
+        int r = h / Lxh;
+        y = r % Ly;
+        r /= Ly;
+        z = r % Lz;
+        t = r / Lz;
+    } else {
+        t = bid % Lt;
+        const int r = bid / Lt;
+        z = r % Lz;
+        const int yc = r / Lz;
+        const int yr = threadIdx.x / Lxh;
+        xh = threadIdx.x - yr * Lxh;
+        y = yc * a.rows + yr;
+        valid = yr < a.rows && y < Ly;
+        h = xh + Lxh * (y + Ly * (z + Lz * t));
+    }
+    const int64_t S = a.g.S;
+
+    double tot[NR][N];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int j = 0; j < N; ++j) tot[r][j] = 0.0;
+
+    if (valid) {
+        const int x = 2 * xh + ((y + z + t + p) & 1);
+        const int64_t hy = Lxh, hz = (int64_t)Lxh * Ly, ht = hz * Lz;
+        const int64_t base = h - xh;
+
+        const char* in[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) in[r] = static_cast<const char*>(a.in) + (int64_t)(rhs0 + r) * a.st_in + ioff;
+        constexpr int SF = DAG ? -1 : 1;  // projector sign of forward hops: (1 - SF gamma)
+        Spinor<R> acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[r].s[s][c] = {R(0), R(0)};
+
+        const cplx<R> ph0 = {R(a.g.ph[0][0]), R(a.g.ph[0][1])};
+        const cplx<R> ph1 = {R(a.g.ph[1][0]), R(a.g.ph[1][1])};
+        const cplx<R> ph2 = {R(a.g.ph[2][0]), R(a.g.ph[2][1])};
+        const cplx<R> ph3 = {R(a.g.ph[3][0]), R(a.g.ph[3][1])};
+        const int q = 1 - p;
+        const bool lnt = a.ntiles == 1;  // links re-read by other tiles are loaded normally
+        // x
+        {
+            const int xp = x == Lx - 1 ? 0 : x + 1;
+            const int xm = x == 0 ? Lx - 1 : x - 1;
+            const int64_t nf = base + (xp >> 1), nbk = base + (xm >> 1);
+            hop<PREC, RECON, 0, true, SF, NR>(in, act, a.U, S, nf, 0 * 2 + p, h, x == Lx - 1, lnt, ph0, acc);
+            hop<PREC, RECON, 0, false, -SF, NR>(in, act, a.U, S, nbk, 0 * 2 + q, nbk, x == 0, lnt, ph0, acc);
+        }
+        // y
+        {
+            const int64_t nf = y == Ly - 1 ? h - (Ly - 1) * hy : h + hy;
+            const int64_t nbk = y == 0 ? h + (Ly - 1) * hy : h - hy;
+            hop<PREC, RECON, 1, true, SF, NR>(in, act, a.U, S, nf, 1 * 2 + p, h, y == Ly - 1, lnt, ph1, acc);
+            hop<PREC, RECON, 1, false, -SF, NR>(in, act, a.U, S, nbk, 1 * 2 + q, nbk, y == 0, lnt, ph1, acc);
+        }
+        // z
+        {
+            const int64_t nf = z == Lz - 1 ? h - (Lz - 1) * hz : h + hz;
+            const int64_t nbk = z == 0 ? h + (Lz - 1) * hz : h - hz;
+            hop<PREC, RECON, 2, true, SF, NR>(in, act, a.U, S, nf, 2 * 2 + p, h, z == Lz - 1, lnt, ph2, acc);
+            hop<PREC, RECON, 2, false, -SF, NR>(in, act, a.U, S, nbk, 2 * 2 + q, nbk, z == 0, lnt, ph2, acc);
+        }
+        // t
+        {
+            const int64_t nf = t == Lt - 1 ? h - (Lt - 1) * ht : h + ht;
+            const int64_t nbk = t == 0 ? h + (Lt - 1) * ht : h - ht;
+            hop<PREC, RECON, 3, true, SF, NR>(in, act, a.U, S, nf, 3 * 2 + p, h, t == Lt - 1, lnt, ph3, acc);
+            hop<PREC, RECON, 3, false, -SF, NR>(in, act, a.U, S, nbk, 3 * 2 + q, nbk, t == 0, lnt, ph3, acc);
+        }
+
+        // epilogue per right-hand side: out = add + a * site + c * acc
+        const cplx<R> cu = {R(a.c.up[0]), R(a.c.up[1])}, cl = {R(a.c.lo[0]), R(a.c.lo[1])};
+        const cplx<R> au = {R(a.a.up[0]), R(a.a.up[1])}, al = {R(a.a.lo[0]), R(a.a.lo[1])};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!act[r]) continue;
+            const int64_t rr = rhs0 + r;
+            Spinor<R> o;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.s[s][c] = (s < 2 ? cu : cl) * acc[r].s[s][c];
+            Spinor<R> st;
+            if (a.site) {
+                SpinorIO<PREC>::load(static_cast<const char*>(a.site) + rr * a.st_site + poff, S, h, st);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) o.s[s][c] = o.s[s][c] + (s < 2 ? au : al) * st.s[s][c];
+            }
+            if (a.add) {
+                Spinor<R> ad;
+                SpinorIO<PREC>::load(static_cast<const char*>(a.add) + rr * a.st_add + poff, S, h, ad);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) o.s[s][c] = o.s[s][c] + ad.s[s][c];
+            }
+            if (a.out)
+                SpinorIO<PREC>::template store<LQCD_OUT_AUX>(static_cast<char*>(a.out) + rr * a.st_out + poff, S, h, o);
+
+            if (RED == RED_NORM || RED == RED_NORM_DS) {
+                double n2 = 0.0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) n2 += (double)norm2(o.s[s][c]);
+                tot[r][0] = n2;
+            }
+            if (RED == RED_NORM_DS) {  // <out, site>
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const cplx<R> v = cmulc(o.s[s][c], st.s[s][c]);
+                        re += (double)v.x;
+                        im += (double)v.y;
+                    }
+                tot[r][N - 2] = re;
+                tot[r][N - 1] = im;
+            }
+            if (RED == RED_DOT_AUX) {  // <aux, out>
+                Spinor<R> ax;
+                SpinorIO<PREC>::load(static_cast<const char*>(a.aux) + rr * a.st_aux + poff, S, h, ax);
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const cplx<R> v = cmulc(ax.s[s][c], o.s[s][c]);
+                        re += (double)v.x;
+                        im += (double)v.y;
+                    }
+                tot[r][N - 2] = re;
+                tot[r][N - 1] = im;
+            }
+        }
+    }
+
+    if (RED != RED_NONE) block_reduce_tile<NR, N>(tot, a.r.partials, nslots, rhs0, a.nrhs, pslot);
+}
+
+template <int PREC, int RECON, bool DAG, int NR>
+static hipError_t launch_red(int red, const DslashArgs& a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (red) {
+    case RED_NONE: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_NONE, NR>), grid, block, 0, s, a); break;
+    case RED_NORM: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_NORM, NR>), grid, block, 0, s, a); break;
+    case RED_NORM_DS: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_NORM_DS, NR>), grid, block, 0, s, a); break;
+    case RED_DOT_AUX: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_DOT_AUX, NR>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int PREC, int RECON, int NR>
+static hipError_t launch_dag(bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block, hipStream_t s)
+{
+    return dag ? launch_red<PREC, RECON, true, NR>(red, a, grid, block, s)
+               : launch_red<PREC, RECON, false, NR>(red, a, grid, block, s);
+}
+
+// Right-hand-side tiles compiled per storage: 1, 2 and 4 for FP32 and FP16
+// (the multi-RHS inner solves), 1 and 2 for FP64.
+template <int PREC, int RECON>
+inline hipError_t launch_tile(int nr, bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (nr == 1) return launch_dag<PREC, RECON, 1>(dag, red, a, grid, block, s);
+    if (nr == 2) return launch_dag<PREC, RECON, 2>(dag, red, a, grid, block, s);
+    if constexpr (PREC != 64)
+        if (nr == 4) return launch_dag<PREC, RECON, 4>(dag, red, a, grid, block, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lqcd

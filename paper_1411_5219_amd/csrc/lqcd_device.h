@@ -80,9 +80,11 @@ using rsrc_t = __amdgpu_buffer_rsrc_t;
 // hardware: 32-bit data format, no swizzling.
 constexpr int kRsrcWord3 = 0x00020000;
 
-// Cache-policy bits of link loads: links are read once per application, so
-// FP64 and FP32 links are loaded non-temporally (bit 1) to spare the cached
-// neighbour spinors.  FP16 links measured faster without the hint.
+// Cache-policy bits of link loads.  With one right-hand side a link is read
+// once per application, so FP64 and FP32 links are loaded non-temporally
+// (bit 1) to spare the cached neighbour spinors; FP16 links measured faster
+// without the hint.  With several right-hand sides the links are re-read by
+// the following blocks and are loaded normally (the kernel chooses).
 #ifndef LQCD_LINK_AUX
 #define LQCD_LINK_AUX 2
 #endif
@@ -273,13 +275,14 @@ struct LinkIO<64, 18> {
     using R = double;
     static constexpr int kPlanes = 9;
     static constexpr int kBytesPerLink = 144;
+    template <int AUX = LQCD_LINK_AUX>
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
         const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
         const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const double2 d = bload<double2, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 16));
+            const double2 d = bload<double2, AUX>(r, o, (uint32_t)(k * S * 16));
             U.u[k / 3][k % 3] = {d.x, d.y};
         }
     }
@@ -298,13 +301,14 @@ struct LinkIO<64, 12> {
     using R = double;
     static constexpr int kPlanes = 6;
     static constexpr int kBytesPerLink = 96;
+    template <int AUX = LQCD_LINK_AUX>
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
         const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
         const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const double2 d = bload<double2, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 16));
+            const double2 d = bload<double2, AUX>(r, o, (uint32_t)(k * S * 16));
             U.u[k / 3][k % 3] = {d.x, d.y};
         }
         reconstruct_row2(U);
@@ -324,13 +328,14 @@ struct LinkIO<32, 18> {
     using R = float;
     static constexpr int kPlanes = 9;
     static constexpr int kBytesPerLink = 72;
+    template <int AUX = LQCD_LINK_AUX>
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
         const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 8, kPlanes * S * 8);
         const uint32_t o = static_cast<uint32_t>(site) * 8u;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const float2 d = bload<float2, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 8));
+            const float2 d = bload<float2, AUX>(r, o, (uint32_t)(k * S * 8));
             U.u[k / 3][k % 3] = {d.x, d.y};
         }
     }
@@ -350,13 +355,14 @@ struct LinkIO<32, 12> {
     using R = float;
     static constexpr int kPlanes = 3;
     static constexpr int kBytesPerLink = 48;
+    template <int AUX = LQCD_LINK_AUX>
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
         const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * kPlanes * S * 16, kPlanes * S * 16);
         const uint32_t o = static_cast<uint32_t>(site) * 16u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float4 d = bload<float4, LQCD_LINK_AUX>(r, o, (uint32_t)(k * S * 16));
+            const float4 d = bload<float4, AUX>(r, o, (uint32_t)(k * S * 16));
             U.u[(2 * k) / 3][(2 * k) % 3] = {d.x, d.y};
             U.u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {d.z, d.w};
         }
@@ -383,11 +389,12 @@ template <>
 struct LinkIO<16, 12> {
     using R = float;
     static constexpr int kBytesPerLink = 24;
+    template <int AUX = LQCD_LINK16_AUX>
     __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t blk, int64_t site, Link<R>& U)
     {
         const rsrc_t r = make_rsrc(static_cast<const char*>(base) + blk * 24 * S, 24 * S);
-        const uint4 d = bload<uint4, LQCD_LINK16_AUX>(r, static_cast<uint32_t>(site) * 16u, 0u);
-        const uint2 e = bload<uint2, LQCD_LINK16_AUX>(r, static_cast<uint32_t>(site) * 8u, (uint32_t)(16 * S));
+        const uint4 d = bload<uint4, AUX>(r, static_cast<uint32_t>(site) * 16u, 0u);
+        const uint2 e = bload<uint2, AUX>(r, static_cast<uint32_t>(site) * 8u, (uint32_t)(16 * S));
         const uint32_t w[6] = {d.x, d.y, d.z, d.w, e.x, e.y};
 #pragma unroll
         for (int k = 0; k < 6; ++k)

@@ -27,8 +27,7 @@ struct SpinCoef {
 //   RED_NORM    : ||out||^2
 //   RED_NORM_DS : ||out||^2, <out, site>          (re, im)
 //   RED_DOT_AUX : <aux, out>                      (re, im)
-//   RED_NORM_DA : ||out||^2, <aux, out>           (re, im)
-enum Red { RED_NONE = 0, RED_NORM = 1, RED_NORM_DS = 2, RED_DOT_AUX = 3, RED_NORM_DA = 4 };
+enum Red { RED_NONE = 0, RED_NORM = 1, RED_NORM_DS = 2, RED_DOT_AUX = 3 };
 
 // What the last block does with the totals of a reduction.
 enum Fin {
@@ -113,14 +112,29 @@ struct DslashArgs {
     // by blocks that ran just before it on the same XCD.
     int rows;
     int nyc;                // y-chunks of R rows (rows > 0)
+    int nrhs;               // right-hand sides (set by the launcher)
+    // Right-hand-side tiles in the block order.  rhs_group = 0: tile index
+    // is blockIdx.y.  rhs_group = G > 0: grid.y = 1 and the tiles are
+    // interleaved into blockIdx.x, G tiles fastest over the same spatial
+    // block, then the spatial blocks, then the groups of G tiles, so a link
+    // loaded for one tile is re-read from L2 by the next G - 1 blocks.
+    int rhs_group;
+    int ntiles;             // right-hand-side tiles (ceil(nrhs / tile))
+    int nsp;                // spatial blocks per parity (rhs_group > 0)
 };
 
 // Launch configuration picked per kernel (autotuned).
 struct Launch {
     int block = 128;
     int swizzle = 1;
-    int order = 0;  // 0: memory order, 1: t-fastest tiles of whole x-rows (Dslash)
+    int order = 0;     // 0: memory order, 1: t-fastest tiles of whole x-rows (Dslash)
+    int rhs_tile = 4;  // right-hand sides one Dslash work-item handles (links loaded once)
+    int rhs_group = 4; // right-hand-side tiles interleaved per spatial block (0: grid.y)
 };
+
+// Right-hand-side tile the Dslash uses for a request (clamped to the tiles
+// compiled for the precision and to nrhs).
+int dslash_rhs_tile(int prec, int want, int nrhs);
 
 // Sum N block partials per right-hand side in block order and run the
 // solver's scalar step (Fin) on the totals; one block per right-hand side.

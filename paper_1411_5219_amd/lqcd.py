@@ -49,7 +49,8 @@ class SolveParams(ctypes.Structure):
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("swizzle", ctypes.c_int32), ("order", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("swizzle", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("rhs_tile", ctypes.c_int32), ("rhs_group", ctypes.c_int32)]
 
 
 KERNEL_DSLASH, KERNEL_BLAS = 0, 1
@@ -166,15 +167,16 @@ def lqcd_workspace_bytes(g, o, params=None) -> int:
     return n.value
 
 
-def lqcd_set_launch(kernel, prec, block, swizzle=1, order=0):
-    return _check(_lib.lqcd_set_launch(int(kernel), int(prec),
-                                       ctypes.byref(Launch(int(block), int(swizzle), int(order)))))
+def lqcd_set_launch(kernel, prec, block, swizzle=1, order=0, rhs_tile=1, rhs_group=0):
+    cfg = Launch(int(block), int(swizzle), int(order), int(rhs_tile), int(rhs_group))
+    return _check(_lib.lqcd_set_launch(int(kernel), int(prec), ctypes.byref(cfg)))
 
 
 def lqcd_get_launch(kernel, prec):
     l = Launch()
     _check(_lib.lqcd_get_launch(int(kernel), int(prec), ctypes.byref(l)))
-    return {"block": l.block, "swizzle": l.swizzle, "order": l.order}
+    return {"block": l.block, "swizzle": l.swizzle, "order": l.order, "rhs_tile": l.rhs_tile,
+            "rhs_group": l.rhs_group}
 
 
 def lqcd_autotune_dslash(g, o, U, inp, out, reps=10, stream=None):
@@ -183,7 +185,8 @@ def lqcd_autotune_dslash(g, o, U, inp, out, reps=10, stream=None):
     us = ctypes.c_double()
     _check(_lib.lqcd_autotune_dslash(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(reps),
                                      _stream(stream), ctypes.byref(best), ctypes.byref(us)))
-    return {"block": best.block, "swizzle": best.swizzle, "order": best.order}, us.value
+    return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
+             "rhs_group": best.rhs_group}, us.value)
 
 
 def lqcd_pack_gauge(g, prec, recon, U_canonical, U_out, stream=None):

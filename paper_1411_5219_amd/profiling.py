@@ -28,7 +28,7 @@ import sys
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/dslash.hip", "csrc/lqcd_device.h", "csrc/lqcd_kernels.h"]
+KERNEL_SOURCES = ["csrc/dslash_impl.h", "csrc/dslash.hip", "csrc/lqcd_device.h", "csrc/lqcd_kernels.h"]
 
 
 def kernel_source_digest() -> str:
@@ -101,7 +101,7 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
-    t.add_argument("--kernel", default="k_dslash_eo<64, 18, false, 0>")
+    t.add_argument("--kernel", default="k_dslash_eo<64, 18, false, 0, 1>")
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     a = ap.parse_args(argv)
     if a.cmd == "stats":

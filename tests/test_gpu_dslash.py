@@ -119,23 +119,36 @@ def test_schur(mods, L4, theta, dagger, prec, recon):
     assert site_rel_err(got[ev], ref[ev]) <= TOL[prec]
 
 
-def test_multi_rhs_equals_single(mods):
+@pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
+@pytest.mark.parametrize("tile,group", [(1, 0), (2, 0), (4, 0), (1, 4), (2, 2), (4, 2), (1, 16)])
+def test_multi_rhs_equals_single(mods, prec, recon, tile, group):
+    """A right-hand-side tile applies each link to several right-hand sides
+    with the same per-RHS operations, so every RHS of a batch (5 RHS: full
+    tiles plus a ragged one) equals its single-RHS application to rounding:
+    different template instances may contract multiply-adds differently, which
+    can flip the last bit of an FP32 result or the rounding of a stored half."""
     torch, fields, lqcd = mods
     L4, theta = (6, 4, 6, 10), (0.0, 0.0, 0.0, math.pi)
     U, psi = _setup(L4, theta, seed=3, kind="exp", nrhs=5)
-    print("\n[case] multi-rhs full M nrhs=5", flush=True)
+    print(f"\n[case] multi-rhs full M nrhs=5 prec={prec} tile={tile} group={group}", flush=True)
     lat = fields.Lattice(L4, theta)
-    o = lqcd.op(0.16, 0.005)
-    Ud = lat.gauge(U)
-    inp = lat.spinor(psi)
-    out = lat.empty(lqcd.FIELD_SPINOR_FULL, 64, nrhs=5)
-    lqcd.dslash_apply(lat.g, o, Ud, inp, out, nrhs=5)
-    got = lat.unpack(out, 64, nrhs=5)
-    for k in range(5):
-        one = lat.spinor(psi[k])
-        o1 = lat.empty(lqcd.FIELD_SPINOR_FULL, 64)
-        lqcd.dslash_apply(lat.g, o, Ud, one, o1)
-        assert np.array_equal(lat.unpack(o1), got[k])
+    o = lqcd.op(0.16, 0.005, prec, recon)
+    Ud = lat.gauge(U, prec, recon)
+    inp = lat.spinor(psi, prec)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+    try:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **dict(saved, rhs_tile=tile, rhs_group=group))
+        out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec, nrhs=5)
+        lqcd.dslash_apply(lat.g, o, Ud, inp, out, nrhs=5)
+        got = lat.unpack(out, prec, nrhs=5)
+        for k in range(5):
+            one = lat.spinor(psi[k], prec)
+            o1 = lat.empty(lqcd.FIELD_SPINOR_FULL, prec)
+            lqcd.dslash_apply(lat.g, o, Ud, one, o1)
+            err = site_rel_err(got[k], lat.unpack(o1, prec))
+            assert err <= {64: 1e-15, 32: 1e-6, 16: 2e-3}[prec], (k, err)
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
 
 
 def test_pack_roundtrip(mods):
