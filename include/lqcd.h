@@ -219,6 +219,21 @@ LQCD_API int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void
                    const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* Batched CGNR over nsys independent systems (1..16), e.g. lattices of
+ * different volumes with their own kappa, mu and links: system s is solved as
+ * cg_solve would with geoms[s], ops[s], U[s], b[s], x[s] and the shared
+ * params (nrhs right-hand sides each).  Every kernel of an iteration is
+ * launched once for all systems (per-system arguments come from tables in
+ * the workspace), and with params->use_graph the iterations are replayed from
+ * a captured HIP graph; each system stops on its own FP64 true residual.
+ * info: nsys * nrhs entries, system-major.  ws: lqcd_workspace_bytes_batch
+ * bytes of device memory. */
+LQCD_API int lqcd_workspace_bytes_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops,
+                                        const lqcd_solve_params* params, size_t* bytes);
+LQCD_API int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,
+                            const void* const* b, void* const* x, const lqcd_solve_params* params,
+                            lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,8 @@ int set_error(int code, const char* fmt, ...)
 #endif
 
 constexpr int kMaxRhs = 16;
+constexpr int kMaxSys = 16;                    // systems in one batched solve
+constexpr int kPinned = kMaxRhs * kMaxSys;     // control blocks read back at once
 constexpr int kMinBlock = 64;  // smallest block size any launcher uses (partials sizing)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -319,7 +321,7 @@ struct Op {
 
 // Pinned host mirror of the control blocks (per thread, allocated once).
 struct Pinned {
-    Ctl* buf = nullptr;  // 2 * kMaxRhs
+    Ctl* buf = nullptr;  // 2 * kPinned
     ~Pinned()
     {
         if (buf) (void)hipHostFree(buf);
@@ -329,7 +331,7 @@ thread_local Pinned g_pinned;
 
 int pinned_ctl(Ctl** out)
 {
-    if (!g_pinned.buf) LQCD_HIP(hipHostMalloc((void**)&g_pinned.buf, sizeof(Ctl) * 2 * kMaxRhs, hipHostMallocDefault));
+    if (!g_pinned.buf) LQCD_HIP(hipHostMalloc((void**)&g_pinned.buf, sizeof(Ctl) * 2 * kPinned, hipHostMallocDefault));
     *out = g_pinned.buf;
     return LQCD_OK;
 }
@@ -393,14 +395,19 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Runs `enqueue(k)` for chunks of iterations until every right-hand side is
-// done; the status of chunk n is read while chunk n+1 runs.
+// Runs enqueue_iter() in chunks of `chunk` iterations until every solve is
+// done: the control blocks ctl[s * stride + r] (s < nsys, r < nrhs) are read
+// back after each chunk, and the read-back of chunk n is waited for while
+// chunk n + 1 runs.  With use_graph the chunk is captured once as a HIP graph
+// and replayed.
 template <class F>
-int drive(const Op& o, int nrhs, int chunk, int maxiter, bool use_graph, F&& enqueue_iter)
+int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int chunk, int maxiter, bool use_graph,
+          F&& enqueue_iter)
 {
     Ctl* pin = nullptr;
     int rc = pinned_ctl(&pin);
     if (rc) return rc;
+    const int count = nsys * stride;
     hipEvent_t ev[2];
     LQCD_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     LQCD_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -410,17 +417,17 @@ int drive(const Op& o, int nrhs, int chunk, int maxiter, bool use_graph, F&& enq
     auto enqueue_chunk = [&]() -> int {
         if (use_graph) {
             if (!exec) {
-                LQCD_HIP(hipStreamBeginCapture(o.s, hipStreamCaptureModeThreadLocal));
+                LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 int r = LQCD_OK;
                 for (int k = 0; k < chunk && r == LQCD_OK; ++k) r = enqueue_iter();
                 hipGraph_t gph = nullptr;
-                hipError_t e = hipStreamEndCapture(o.s, &gph);
+                hipError_t e = hipStreamEndCapture(st, &gph);
                 if (r) return r;
                 if (e != hipSuccess) return set_error(LQCD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
                 graph = gph;
                 LQCD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             }
-            LQCD_HIP(hipGraphLaunch(exec, o.s));
+            LQCD_HIP(hipGraphLaunch(exec, st));
             return LQCD_OK;
         }
         for (int k = 0; k < chunk; ++k) {
@@ -430,13 +437,12 @@ int drive(const Op& o, int nrhs, int chunk, int maxiter, bool use_graph, F&& enq
         return LQCD_OK;
     };
     const int max_chunks = maxiter / chunk + 2;
-    int n = 0;
-    for (;; ++n) {
+    for (int n = 0;; ++n) {
         if (n < max_chunks) {
             result = enqueue_chunk();
             if (result) break;
-            hipError_t e = hipMemcpyAsync(pin + (n & 1) * kMaxRhs, o.rs.ctl, sizeof(Ctl) * nrhs, hipMemcpyDeviceToHost, o.s);
-            if (e == hipSuccess) e = hipEventRecord(ev[n & 1], o.s);
+            hipError_t e = hipMemcpyAsync(pin + (n & 1) * kPinned, ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(ev[n & 1], st);
             if (e != hipSuccess) { result = set_error(LQCD_EHIP, "status read-back: %s", hipGetErrorString(e)); break; }
         }
         if (n == 0) continue;
@@ -444,10 +450,11 @@ int drive(const Op& o, int nrhs, int chunk, int maxiter, bool use_graph, F&& enq
         hipError_t e = hipEventSynchronize(ev[m]);
         if (e != hipSuccess) { result = set_error(LQCD_EHIP, "stream: %s", hipGetErrorString(e)); break; }
         bool all = true;
-        for (int i = 0; i < nrhs; ++i) all = all && pin[m * kMaxRhs + i].done;
+        for (int sy = 0; sy < nsys; ++sy)
+            for (int i = 0; i < nrhs; ++i) all = all && pin[m * kPinned + sy * stride + i].done;
         if (all || n >= max_chunks) break;
     }
-    (void)hipStreamSynchronize(o.s);
+    (void)hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipEventDestroy(ev[0]);
@@ -455,323 +462,29 @@ int drive(const Op& o, int nrhs, int chunk, int maxiter, bool use_graph, F&& enq
     return result;
 }
 
-int read_ctl(const Op& o, int nrhs, std::vector<Ctl>& out)
+int read_ctls(hipStream_t st, const Ctl* ctl, int count, std::vector<Ctl>& out)
 {
-    out.resize(nrhs);
-    LQCD_HIP(hipMemcpyAsync(out.data(), o.rs.ctl, sizeof(Ctl) * nrhs, hipMemcpyDeviceToHost, o.s));
-    LQCD_HIP(hipStreamSynchronize(o.s));
+    out.resize(count);
+    LQCD_HIP(hipMemcpyAsync(out.data(), ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
+    LQCD_HIP(hipStreamSynchronize(st));
     return LQCD_OK;
 }
 
-// The solver proper (CGNR or BiCGStab, FP64 or mixed, eo or full lattice).
-int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, const void* b, void* x,
-          const lqcd_solve_params* prm, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+// Bookkeeping shared by the solvers: which right-hand sides to reopen after
+// the true-residual check, and the per-right-hand-side info.
+unsigned reopen_mask(const Ctl* ctl, int nrhs, const lqcd_solve_params* prm)
 {
-    const double t0 = now_s();
-    g_err[0] = 0;
-    Geom g;
-    int rc = make_geom(geom, &g);
-    if (rc) return rc;
-    if ((rc = check_op(opi))) return rc;
-    if (opi->prec != 64) return set_error(LQCD_EINVAL, "solvers take FP64 fields (op->prec = 64)");
-    if ((rc = check_params(prm, method))) return rc;
-    if (!U || !b || !x || !info) return set_error(LQCD_EINVAL, "NULL field or info pointer");
-    if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
-    if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
-    SolverPlan sp;
-    plan_solver(g, opi, prm, method, ws, &sp);
-    if (ws_bytes < sp.bytes)
-        return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, sp.bytes);
-
-    const int nrhs = prm->nrhs;
-    const bool eo = prm->eo != 0;
-    const bool mixed = prm->inner_prec != 64;
-    const int chunk = prm->check_every > 0 ? prm->check_every : 8;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-
-    Op o;
-    o.g = g;
-    o.prec = 64;
-    o.recon = opi->recon;
-    o.U = U;
-    o.kappa = opi->kappa;
-    o.mu = opi->mu;
-    o.nrhs = nrhs;
-    o.pb = parity_bytes(g, 64);
-    o.s = s;
-    o.rs = sp.rs;
-    o.tune();
-    const int64_t pb = o.pb;
-    const int64_t fb = 2 * pb;  // full field
-    char* bc = static_cast<char*>(const_cast<void*>(b));
-    char* xc = static_cast<char*>(x);
-    const double k = opi->kappa, m = opi->mu;
-
-    LQCD_K(launch_ctl_init(sp.rs.ctl, nrhs, prm->tol, mixed ? prm->delta_reliable : 0.0, prm->maxiter, s));
-    // ||b||^2 over the full lattice -> bb, thresh
-    {
-        BlasArgs a = o.blas_base(2);
-        a.pred = PRED_ALWAYS;
-        a.x = bc;
-        a.r.fin = FIN_BB_FULL;
-        LQCD_K(launch_blas(64, BLAS_NORM, a, nrhs, o.bcfg, s));
+    unsigned mask = 0;
+    for (int i = 0; i < nrhs; ++i) {
+        const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
+        if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) mask |= 1u << i;
     }
+    return mask;
+}
 
-    // Field roles.  Even-odd: parity fields (stride pb) except b and x
-    // (full fields, stride fb, even part first).
-    void* bhat = nullptr;
-    void* xe = xc;  // even half of x
-    void* r = sp.v[0];
-    if (eo) {
-        bhat = method == M_CG ? (mixed ? sp.v[2] : sp.v[5]) : sp.v[7];
-        void* t = method == M_CG ? (mixed ? sp.v[1] : sp.v[4]) : sp.v[6];
-        // t = A^-1 b_o ; bhat = b_e + kappa H_eo t
-        BlasArgs a = o.blas_base(1);
-        a.pred = PRED_ALWAYS;
-        a.x = bc + pb;
-        a.y = t;
-        a.st_x = fb;
-        a.coef = coef_Ainv(k, m, false);
-        LQCD_K(launch_blas(64, BLAS_SPIN_SCALE, a, nrhs, o.bcfg, s));
-        DslashArgs d = o.base();
-        d.parity = 0;
-        d.pred = PRED_ALWAYS;
-        d.in = t;
-        d.out = bhat;
-        d.add = bc;
-        d.st_add = fb;
-        d.c = coef_real(k);
-        LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
-        // x_e = 0
-        BlasArgs z = o.blas_base(1);
-        z.pred = PRED_ALWAYS;
-        z.y = xe;
-        z.st_y = fb;
-        LQCD_K(launch_blas(64, BLAS_ZERO, z, nrhs, o.bcfg, s));
-    } else {
-        LQCD_K(o.blas(BLAS_ZERO, 2, PRED_ALWAYS, FIN_STORE, nullptr, xc));
-    }
-
-    // Helpers with the right strides for x (full field) in eo mode.
-    const int nsub = eo ? 1 : 2;
-    auto blas_x = [&](int op, int pred, int fin, void* X, void* Y, void* Z, void* W, void* V, const void* R0) {
-        BlasArgs a = o.blas_base(nsub);
-        a.pred = pred;
-        a.x = X;
-        a.y = Y;
-        a.z = Z;
-        a.w = W;
-        a.v = V;
-        a.r0 = R0;
-        a.st_x = eo ? fb : fb;  // X is always the solution field here
-        a.r.fin = fin;
-        return launch_blas(64, op, a, nrhs, o.bcfg, s);
-    };
-    // r = rhs - Op x   (rhs = bhat for eo, b for full)
-    auto residual = [&](int red, int fin, int pred) -> hipError_t {
-        if (eo) {
-            void* t = method == M_CG ? (mixed ? sp.v[1] : sp.v[4]) : sp.v[6];
-            return o.schur(xe, r, t, false, -1.0, bhat, red, fin, pred, nullptr, fb, pb);
-        }
-        return o.full_M(xc, r, false, -1.0, bc, red, fin, pred);
-    };
-    auto apply = [&](const void* in, void* out, bool dag, int red, int fin, int pred, const void* aux) -> hipError_t {
-        if (eo) {
-            void* t = method == M_CG ? sp.v[4] : sp.v[6];
-            return o.schur(in, out, t, dag, 1.0, nullptr, red, fin, pred, aux);
-        }
-        return o.full_M(in, out, dag, 1.0, nullptr, red, fin, pred, aux);
-    };
-
-    std::vector<Ctl> ctl;
-    int restarts = 0;
-    unsigned open_mask = (nrhs >= 32) ? ~0u : ((1u << nrhs) - 1u);
-
-    if (method == M_CG && !mixed) {
-        void *p = sp.v[1], *w = sp.v[2], *z = sp.v[3];
-        auto start = [&]() -> int {
-            // r = rhs - Op x ; z = Op^+ r ; zz ; p = z
-            LQCD_K(residual(RED_NONE, FIN_STORE, PRED_ACTIVE));
-            LQCD_K(apply(r, z, true, RED_NORM, FIN_CG_ZZ, PRED_ACTIVE, nullptr));
-            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, z, p));
-            return LQCD_OK;
-        };
-        auto iter = [&]() -> int {
-            LQCD_K(apply(p, w, false, RED_NORM, FIN_CG_ALPHA, PRED_ACTIVE, nullptr));
-            LQCD_K(blas_x(BLAS_CG_XR, PRED_ACTIVE, FIN_CG_RR, xc, p, r, w, nullptr, nullptr));
-            LQCD_K(apply(r, z, true, RED_NORM, FIN_CG_BETA, PRED_ACTIVE, nullptr));
-            LQCD_K(o.blas(BLAS_CG_P, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p, z));
-            return LQCD_OK;
-        };
-        for (;;) {
-            if ((rc = start())) return rc;
-            if ((rc = drive(o, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
-            // reconstruct and check the true residual
-            if (eo) {
-                DslashArgs d = o.base();
-                d.parity = 1;
-                d.pred = PRED_ALWAYS;
-                d.in = xe;
-                d.st_in = fb;
-                d.out = xc + pb;
-                d.st_out = fb;
-                d.site = bc + pb;
-                d.st_site = fb;
-                d.a = coef_Ainv(k, m, false);
-                d.c = coef_Ainv(k, m, false, k);
-                LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
-            }
-            LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
-            if ((rc = read_ctl(o, nrhs, ctl))) return rc;
-            unsigned reopen = 0;
-            for (int i = 0; i < nrhs; ++i) {
-                const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
-                if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) reopen |= 1u << i;
-            }
-            if (!reopen || restarts >= 20) break;
-            ++restarts;
-            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
-        }
-    } else if (method == M_CG && mixed) {
-        // FP64: r (v0), t64 (v1), bhat (v2); low: xl rl pl wl zl tl
-        const int lp = prm->inner_prec, lr = prm->inner_recon;
-        Op lo = o;
-        lo.prec = lp;
-        lo.recon = lr;
-        lo.U = sp.Ulo;
-        lo.pb = parity_bytes(g, lp);
-        lo.tune();
-        void *xl = sp.lo[0], *rl = sp.lo[1], *pl = sp.lo[2], *wl = sp.lo[3], *zl = sp.lo[4], *tl = sp.lo[5];
-        void* t64 = sp.v[1];
-        if (opi->recon != 18) return set_error(LQCD_EUNSUPPORTED, "mixed precision reads FP64/18 links");
-        LQCD_K(launch_convert_gauge(lp, lr, g, U, sp.Ulo, s));
-        auto to_low = [&](void* dst, const void* src, int pred) {
-            ConvertArgs c{};
-            c.Vh = g.Vh;
-            c.S = g.S;
-            c.nsub = 1;
-            c.dst = dst;
-            c.src = const_cast<void*>(src);
-            c.rhs_stride_dst = lo.pb;
-            c.rhs_stride_src = pb;
-            c.pred = pred;
-            c.ctl = sp.rs.ctl;
-            return launch_convert(lp, 64, c, nrhs, s);
-        };
-        auto fold = [&](int pred) {  // x_e += x_low ; x_low = 0
-            ConvertArgs c{};
-            c.Vh = g.Vh;
-            c.S = g.S;
-            c.nsub = 1;
-            c.dst = xe;
-            c.src = xl;
-            c.rhs_stride_dst = fb;
-            c.rhs_stride_src = lo.pb;
-            c.accumulate = 1;
-            c.zero_src = 1;
-            c.pred = pred;
-            c.ctl = sp.rs.ctl;
-            return launch_convert(64, lp, c, nrhs, s);
-        };
-        auto start = [&]() -> int {
-            // r = bhat - Mhat x (FP64) ; rr_max ; r_low ; x_low = 0 ; z = Mhat^+ r_low ; p = z
-            LQCD_K(o.schur(xe, r, t64, false, -1.0, bhat, RED_NORM, FIN_RR_INIT, PRED_ACTIVE, nullptr, fb, pb));
-            LQCD_K(to_low(rl, r, PRED_ACTIVE));
-            LQCD_K(lo.blas(BLAS_ZERO, 1, PRED_ACTIVE, FIN_STORE, nullptr, xl));
-            LQCD_K(lo.schur(rl, zl, tl, true, 1.0, nullptr, RED_NORM, FIN_CG_ZZ, PRED_ACTIVE));
-            LQCD_K(lo.blas(BLAS_COPY, 1, PRED_ACTIVE, FIN_STORE, zl, pl));
-            return LQCD_OK;
-        };
-        auto iter = [&]() -> int {
-            LQCD_K(lo.schur(pl, wl, tl, false, 1.0, nullptr, RED_NORM, FIN_CG_ALPHA, PRED_ACTIVE));
-            LQCD_K(lo.blas(BLAS_CG_XR, 1, PRED_ACTIVE, FIN_CG_RR, xl, pl, rl, wl));
-            // reliable update (runs only when FIN_CG_RR requested it)
-            LQCD_K(fold(PRED_UPDATE));
-            LQCD_K(o.schur(xe, r, t64, false, -1.0, bhat, RED_NORM, FIN_RU_RR, PRED_UPDATE, nullptr, fb, pb));
-            LQCD_K(to_low(rl, r, PRED_UPDATE));
-            LQCD_K(lo.schur(rl, zl, tl, true, 1.0, nullptr, RED_NORM, FIN_CG_BETA, PRED_ACTIVE));
-            LQCD_K(lo.blas(BLAS_CG_P, 1, PRED_ACTIVE, FIN_STORE, nullptr, pl, zl));
-            return LQCD_OK;
-        };
-        for (;;) {
-            if ((rc = start())) return rc;
-            if ((rc = drive(o, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
-            LQCD_K(fold(PRED_ALWAYS));
-            DslashArgs d = o.base();
-            d.parity = 1;
-            d.pred = PRED_ALWAYS;
-            d.in = xe;
-            d.st_in = fb;
-            d.out = xc + pb;
-            d.st_out = fb;
-            d.site = bc + pb;
-            d.st_site = fb;
-            d.a = coef_Ainv(k, m, false);
-            d.c = coef_Ainv(k, m, false, k);
-            LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
-            LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
-            if ((rc = read_ctl(o, nrhs, ctl))) return rc;
-            unsigned reopen = 0;
-            for (int i = 0; i < nrhs; ++i) {
-                const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
-                if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) reopen |= 1u << i;
-            }
-            if (!reopen || restarts >= 20) break;
-            ++restarts;
-            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
-        }
-    } else {
-        // BiCGStab: r r0 p v s t (tmp bhat)
-        void *r0 = sp.v[1], *p = sp.v[2], *v = sp.v[3], *sv = sp.v[4], *t = sp.v[5];
-        auto start = [&]() -> int {
-            LQCD_K(residual(RED_NONE, FIN_STORE, PRED_ACTIVE));
-            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, r, r0));
-            LQCD_K(o.blas(BLAS_NORM_DOT, nsub, PRED_ACTIVE, FIN_BI_INIT, r, nullptr, nullptr, nullptr, nullptr, r0));
-            LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p));
-            LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, v));
-            return LQCD_OK;
-        };
-        auto iter = [&]() -> int {
-            LQCD_K(o.blas(BLAS_BI_P, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p, r, nullptr, v));
-            LQCD_K(apply(p, v, false, RED_DOT_AUX, FIN_BI_ALPHA, PRED_ACTIVE, r0));
-            LQCD_K(o.blas(BLAS_BI_S, nsub, PRED_ACTIVE, FIN_STORE, nullptr, nullptr, r, sv, v));
-            LQCD_K(apply(sv, t, false, RED_NORM_DS, FIN_BI_OMEGA, PRED_ACTIVE, nullptr));
-            LQCD_K(blas_x(BLAS_BI_XR, PRED_ACTIVE, FIN_BI_RHO, xc, p, r, sv, t, r0));
-            return LQCD_OK;
-        };
-        for (;;) {
-            if ((rc = start())) return rc;
-            if ((rc = drive(o, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
-            if (eo) {
-                DslashArgs d = o.base();
-                d.parity = 1;
-                d.pred = PRED_ALWAYS;
-                d.in = xe;
-                d.st_in = fb;
-                d.out = xc + pb;
-                d.st_out = fb;
-                d.site = bc + pb;
-                d.st_site = fb;
-                d.a = coef_Ainv(k, m, false);
-                d.c = coef_Ainv(k, m, false, k);
-                LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
-            }
-            LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
-            if ((rc = read_ctl(o, nrhs, ctl))) return rc;
-            unsigned reopen = 0;
-            for (int i = 0; i < nrhs; ++i) {
-                const double tr = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
-                if (ctl[i].status == 0 && tr > prm->tol && ctl[i].iter < prm->maxiter) reopen |= 1u << i;
-            }
-            if (!reopen || restarts >= 20) break;
-            ++restarts;
-            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
-        }
-    }
-    (void)open_mask;
-
-    const double secs = now_s() - t0;
-    int worst = LQCD_OK;
+void fill_info(const Ctl* ctl, int nrhs, int method, bool eo, bool mixed, int restarts, double secs,
+               const lqcd_solve_params* prm, lqcd_solve_info* info, int* worst)
+{
     for (int i = 0; i < nrhs; ++i) {
         lqcd_solve_info& in = info[i];
         in.iters = ctl[i].iter;
@@ -796,9 +509,575 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
         if (st == LQCD_OK && in.true_resid > prm->tol) st = LQCD_ENOCONV;
         if (st == LQCD_OK && !std::isfinite(in.true_resid)) st = LQCD_ENONFINITE;
         in.status = st;
-        if (st != LQCD_OK && worst == LQCD_OK) worst = st;
+        if (st != LQCD_OK && *worst == LQCD_OK) *worst = st;
     }
+}
+
+// Set-up shared by the solvers: control blocks, ||b||^2, and (even-odd) the
+// prepared source bhat = b_e + kappa H_eo A^-1 b_o with x_e = 0 (t is an odd
+// scratch field); full lattice: x = 0.
+int solver_setup(const Op& o, const lqcd_solve_params* prm, bool eo, bool mixed, char* bc, char* xc, void* bhat,
+                 void* t)
+{
+    const int nrhs = o.nrhs;
+    const int64_t pb = o.pb, fb = 2 * pb;
+    hipStream_t s = o.s;
+    LQCD_K(launch_ctl_init(o.rs.ctl, nrhs, prm->tol, mixed ? prm->delta_reliable : 0.0, prm->maxiter, s));
+    {
+        BlasArgs a = o.blas_base(2);
+        a.pred = PRED_ALWAYS;
+        a.x = bc;
+        a.r.fin = FIN_BB_FULL;
+        LQCD_K(launch_blas(64, BLAS_NORM, a, nrhs, o.bcfg, s));
+    }
+    if (eo) {
+        BlasArgs a = o.blas_base(1);
+        a.pred = PRED_ALWAYS;
+        a.x = bc + pb;
+        a.y = t;
+        a.st_x = fb;
+        a.coef = coef_Ainv(o.kappa, o.mu, false);
+        LQCD_K(launch_blas(64, BLAS_SPIN_SCALE, a, nrhs, o.bcfg, s));
+        DslashArgs d = o.base();
+        d.parity = 0;
+        d.pred = PRED_ALWAYS;
+        d.in = t;
+        d.out = bhat;
+        d.add = bc;
+        d.st_add = fb;
+        d.c = coef_real(o.kappa);
+        LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
+        BlasArgs z = o.blas_base(1);
+        z.pred = PRED_ALWAYS;
+        z.y = xc;
+        z.st_y = fb;
+        LQCD_K(launch_blas(64, BLAS_ZERO, z, nrhs, o.bcfg, s));
+    } else {
+        LQCD_K(o.blas(BLAS_ZERO, 2, PRED_ALWAYS, FIN_STORE, nullptr, xc));
+    }
+    return LQCD_OK;
+}
+
+// Solution, reconstruction and true residual: x_o = A^-1 (b_o + kappa H_oe x_e)
+// (even-odd), then ||b - M x||^2 in FP64 on the full lattice.
+int solver_finish(const Op& o, bool eo, char* bc, char* xc)
+{
+    const int64_t pb = o.pb, fb = 2 * pb;
+    if (eo) {
+        DslashArgs d = o.base();
+        d.parity = 1;
+        d.pred = PRED_ALWAYS;
+        d.in = xc;
+        d.st_in = fb;
+        d.out = xc + pb;
+        d.st_out = fb;
+        d.site = bc + pb;
+        d.st_site = fb;
+        d.a = coef_Ainv(o.kappa, o.mu, false);
+        d.c = coef_Ainv(o.kappa, o.mu, false, o.kappa);
+        LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, o.nrhs, o.dcfg, o.s));
+    }
+    LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
+    return LQCD_OK;
+}
+
+// One CGNR system: plain FP64 (even-odd or full lattice) or mixed precision
+// with FP64 reliable updates (even-odd).  setup / start / iter / finish
+// enqueue the kernels of each phase, so one system can be driven on its own
+// and several can be recorded and replayed as batched launches.
+struct CgSystem {
+    const lqcd_solve_params* prm = nullptr;
+    SolverPlan sp;
+    Op o, lo;
+    bool eo = true, mixed = false;
+    int nrhs = 1, nsub = 1;
+    int64_t pb = 0, fb = 0;
+    char* bc = nullptr;
+    char* xc = nullptr;
+    void *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr, *t = nullptr, *bhat = nullptr;  // FP64
+    void *t64 = nullptr, *xl = nullptr, *rl = nullptr, *pl = nullptr, *wl = nullptr, *zl = nullptr, *tl = nullptr;
+
+    int init(const Geom& g, const lqcd_op* opi, const void* U, const void* b, void* x, const lqcd_solve_params* prm_,
+             const SolverPlan& plan, hipStream_t s)
+    {
+        prm = prm_;
+        sp = plan;
+        eo = prm->eo != 0;
+        mixed = prm->inner_prec != 64;
+        nrhs = prm->nrhs;
+        nsub = eo ? 1 : 2;
+        o.g = g;
+        o.prec = 64;
+        o.recon = opi->recon;
+        o.U = U;
+        o.kappa = opi->kappa;
+        o.mu = opi->mu;
+        o.nrhs = nrhs;
+        o.pb = parity_bytes(g, 64);
+        o.s = s;
+        o.rs = sp.rs;
+        o.tune();
+        pb = o.pb;
+        fb = 2 * pb;
+        bc = static_cast<char*>(const_cast<void*>(b));
+        xc = static_cast<char*>(x);
+        r = sp.v[0];
+        if (!mixed) {
+            p = sp.v[1];
+            w = sp.v[2];
+            z = sp.v[3];
+            t = eo ? sp.v[4] : nullptr;
+            bhat = eo ? sp.v[5] : nullptr;
+        } else {
+            if (opi->recon != 18) return set_error(LQCD_EUNSUPPORTED, "mixed precision reads FP64/18 links");
+            t64 = sp.v[1];
+            bhat = sp.v[2];
+            lo = o;
+            lo.prec = prm->inner_prec;
+            lo.recon = prm->inner_recon;
+            lo.U = sp.Ulo;
+            lo.pb = parity_bytes(g, lo.prec);
+            lo.tune();
+            xl = sp.lo[0];
+            rl = sp.lo[1];
+            pl = sp.lo[2];
+            wl = sp.lo[3];
+            zl = sp.lo[4];
+            tl = sp.lo[5];
+        }
+        return LQCD_OK;
+    }
+
+    int setup()
+    {
+        int rc = solver_setup(o, prm, eo, mixed, bc, xc, bhat, mixed ? t64 : t);
+        if (rc) return rc;
+        if (mixed) LQCD_K(launch_convert_gauge(lo.prec, lo.recon, o.g, o.U, sp.Ulo, o.s));
+        return LQCD_OK;
+    }
+
+    // x_e / x as the first operand of a BLAS step (full field stride)
+    hipError_t blas_x(int op, int pred, int fin, void* X, void* Y, void* Z, void* W) const
+    {
+        BlasArgs a = o.blas_base(nsub);
+        a.pred = pred;
+        a.x = X;
+        a.y = Y;
+        a.z = Z;
+        a.w = W;
+        a.st_x = fb;
+        a.r.fin = fin;
+        return launch_blas(64, op, a, nrhs, o.bcfg, o.s);
+    }
+    // r = rhs - Op x (rhs = bhat for even-odd, b for the full lattice), FP64
+    hipError_t residual(void* out, int red, int fin, int pred) const
+    {
+        if (eo) return o.schur(xc, out, mixed ? t64 : t, false, -1.0, bhat, red, fin, pred, nullptr, fb, pb);
+        return o.full_M(xc, out, false, -1.0, bc, red, fin, pred);
+    }
+    hipError_t apply(const void* in, void* out, bool dag, int red, int fin, int pred) const
+    {
+        if (eo) return o.schur(in, out, t, dag, 1.0, nullptr, red, fin, pred);
+        return o.full_M(in, out, dag, 1.0, nullptr, red, fin, pred);
+    }
+    hipError_t to_low(void* dst, const void* src, int pred) const
+    {
+        ConvertArgs c{};
+        c.Vh = o.g.Vh;
+        c.S = o.g.S;
+        c.nsub = 1;
+        c.dst = dst;
+        c.src = const_cast<void*>(src);
+        c.rhs_stride_dst = lo.pb;
+        c.rhs_stride_src = pb;
+        c.pred = pred;
+        c.ctl = sp.rs.ctl;
+        return launch_convert(lo.prec, 64, c, nrhs, o.s);
+    }
+    hipError_t fold(int pred) const  // x_e += x_low ; x_low = 0
+    {
+        ConvertArgs c{};
+        c.Vh = o.g.Vh;
+        c.S = o.g.S;
+        c.nsub = 1;
+        c.dst = xc;
+        c.src = xl;
+        c.rhs_stride_dst = fb;
+        c.rhs_stride_src = lo.pb;
+        c.accumulate = 1;
+        c.zero_src = 1;
+        c.pred = pred;
+        c.ctl = sp.rs.ctl;
+        return launch_convert(64, lo.prec, c, nrhs, o.s);
+    }
+
+    int start()
+    {
+        if (!mixed) {
+            // r = rhs - Op x ; z = Op^+ r ; zz ; p = z
+            LQCD_K(residual(r, RED_NONE, FIN_STORE, PRED_ACTIVE));
+            LQCD_K(apply(r, z, true, RED_NORM, FIN_CG_ZZ, PRED_ACTIVE));
+            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, z, p));
+            return LQCD_OK;
+        }
+        // r = bhat - Mhat x (FP64) ; rr_max ; r_low ; x_low = 0 ; z = Mhat^+ r_low ; p = z
+        LQCD_K(residual(r, RED_NORM, FIN_RR_INIT, PRED_ACTIVE));
+        LQCD_K(to_low(rl, r, PRED_ACTIVE));
+        LQCD_K(lo.blas(BLAS_ZERO, 1, PRED_ACTIVE, FIN_STORE, nullptr, xl));
+        LQCD_K(lo.schur(rl, zl, tl, true, 1.0, nullptr, RED_NORM, FIN_CG_ZZ, PRED_ACTIVE));
+        LQCD_K(lo.blas(BLAS_COPY, 1, PRED_ACTIVE, FIN_STORE, zl, pl));
+        return LQCD_OK;
+    }
+
+    int iter()
+    {
+        if (!mixed) {
+            LQCD_K(apply(p, w, false, RED_NORM, FIN_CG_ALPHA, PRED_ACTIVE));
+            LQCD_K(blas_x(BLAS_CG_XR, PRED_ACTIVE, FIN_CG_RR, xc, p, r, w));
+            LQCD_K(apply(r, z, true, RED_NORM, FIN_CG_BETA, PRED_ACTIVE));
+            LQCD_K(o.blas(BLAS_CG_P, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p, z));
+            return LQCD_OK;
+        }
+        LQCD_K(lo.schur(pl, wl, tl, false, 1.0, nullptr, RED_NORM, FIN_CG_ALPHA, PRED_ACTIVE));
+        LQCD_K(lo.blas(BLAS_CG_XR, 1, PRED_ACTIVE, FIN_CG_RR, xl, pl, rl, wl));
+        // reliable update (runs only when FIN_CG_RR requested it)
+        LQCD_K(fold(PRED_UPDATE));
+        LQCD_K(residual(r, RED_NORM, FIN_RU_RR, PRED_UPDATE));
+        LQCD_K(to_low(rl, r, PRED_UPDATE));
+        LQCD_K(lo.schur(rl, zl, tl, true, 1.0, nullptr, RED_NORM, FIN_CG_BETA, PRED_ACTIVE));
+        LQCD_K(lo.blas(BLAS_CG_P, 1, PRED_ACTIVE, FIN_STORE, nullptr, pl, zl));
+        return LQCD_OK;
+    }
+
+    int finish()
+    {
+        if (mixed) LQCD_K(fold(PRED_ALWAYS));
+        return solver_finish(o, eo, bc, xc);
+    }
+};
+
+int validate_solve(const lqcd_geom* geom, const lqcd_op* opi, const void* U, const void* b, void* x,
+                   const lqcd_solve_params* prm, const void* info, int method, Geom* g)
+{
+    int rc = make_geom(geom, g);
+    if (rc) return rc;
+    if ((rc = check_op(opi))) return rc;
+    if (opi->prec != 64) return set_error(LQCD_EINVAL, "solvers take FP64 fields (op->prec = 64)");
+    if ((rc = check_params(prm, method))) return rc;
+    if (!U || !b || !x || !info) return set_error(LQCD_EINVAL, "NULL field or info pointer");
+    return LQCD_OK;
+}
+
+// The single-system solver (CGNR or BiCGStab, FP64 or mixed, eo or full lattice).
+int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, const void* b, void* x,
+          const lqcd_solve_params* prm, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+{
+    const double t0 = now_s();
+    g_err[0] = 0;
+    Geom g;
+    int rc = validate_solve(geom, opi, U, b, x, prm, info, method, &g);
+    if (rc) return rc;
+    if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
+    if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
+    SolverPlan sp;
+    plan_solver(g, opi, prm, method, ws, &sp);
+    if (ws_bytes < sp.bytes)
+        return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, sp.bytes);
+
+    const int nrhs = prm->nrhs;
+    const bool eo = prm->eo != 0;
+    const bool mixed = prm->inner_prec != 64;
+    const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<Ctl> ctl;
+    int restarts = 0;
+
+    if (method == M_CG) {
+        CgSystem cs;
+        if ((rc = cs.init(g, opi, U, b, x, prm, sp, s))) return rc;
+        if ((rc = cs.setup())) return rc;
+        for (;;) {
+            if ((rc = cs.start())) return rc;
+            rc = drive(s, sp.rs.ctl, 1, nrhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0,
+                       [&]() -> int { return cs.iter(); });
+            if (rc) return rc;
+            if ((rc = cs.finish())) return rc;
+            if ((rc = read_ctls(s, sp.rs.ctl, nrhs, ctl))) return rc;
+            const unsigned reopen = reopen_mask(ctl.data(), nrhs, prm);
+            if (!reopen || restarts >= 20) break;
+            ++restarts;
+            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
+        }
+    } else {
+        // BiCGStab: r r0 p v s t (tmp bhat)
+        Op o;
+        o.g = g;
+        o.prec = 64;
+        o.recon = opi->recon;
+        o.U = U;
+        o.kappa = opi->kappa;
+        o.mu = opi->mu;
+        o.nrhs = nrhs;
+        o.pb = parity_bytes(g, 64);
+        o.s = s;
+        o.rs = sp.rs;
+        o.tune();
+        const int64_t pb = o.pb, fb = 2 * pb;
+        const int nsub = eo ? 1 : 2;
+        char* bc = static_cast<char*>(const_cast<void*>(b));
+        char* xc = static_cast<char*>(x);
+        void *r = sp.v[0], *r0 = sp.v[1], *p = sp.v[2], *v = sp.v[3], *sv = sp.v[4], *t = sp.v[5];
+        void *tmp = sp.v[6], *bhat = sp.v[7];
+        if ((rc = solver_setup(o, prm, eo, false, bc, xc, bhat, tmp))) return rc;
+        auto apply = [&](const void* in, void* out, int red, int fin, const void* aux) -> hipError_t {
+            if (eo) return o.schur(in, out, tmp, false, 1.0, nullptr, red, fin, PRED_ACTIVE, aux);
+            return o.full_M(in, out, false, 1.0, nullptr, red, fin, PRED_ACTIVE, aux);
+        };
+        auto start = [&]() -> int {
+            if (eo) LQCD_K(o.schur(xc, r, tmp, false, -1.0, bhat, RED_NONE, FIN_STORE, PRED_ACTIVE, nullptr, fb, pb));
+            else LQCD_K(o.full_M(xc, r, false, -1.0, bc, RED_NONE, FIN_STORE, PRED_ACTIVE));
+            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, r, r0));
+            LQCD_K(o.blas(BLAS_NORM_DOT, nsub, PRED_ACTIVE, FIN_BI_INIT, r, nullptr, nullptr, nullptr, nullptr, r0));
+            LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p));
+            LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, v));
+            return LQCD_OK;
+        };
+        auto iter = [&]() -> int {
+            LQCD_K(o.blas(BLAS_BI_P, nsub, PRED_ACTIVE, FIN_STORE, nullptr, p, r, nullptr, v));
+            LQCD_K(apply(p, v, RED_DOT_AUX, FIN_BI_ALPHA, r0));
+            LQCD_K(o.blas(BLAS_BI_S, nsub, PRED_ACTIVE, FIN_STORE, nullptr, nullptr, r, sv, v));
+            LQCD_K(apply(sv, t, RED_NORM_DS, FIN_BI_OMEGA, nullptr));
+            BlasArgs a = o.blas_base(nsub);
+            a.pred = PRED_ACTIVE;
+            a.x = xc;
+            a.y = p;
+            a.z = r;
+            a.w = sv;
+            a.v = t;
+            a.r0 = r0;
+            a.st_x = fb;
+            a.r.fin = FIN_BI_RHO;
+            LQCD_K(launch_blas(64, BLAS_BI_XR, a, nrhs, o.bcfg, s));
+            return LQCD_OK;
+        };
+        for (;;) {
+            if ((rc = start())) return rc;
+            if ((rc = drive(s, sp.rs.ctl, 1, nrhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
+            if ((rc = solver_finish(o, eo, bc, xc))) return rc;
+            if ((rc = read_ctls(s, sp.rs.ctl, nrhs, ctl))) return rc;
+            const unsigned reopen = reopen_mask(ctl.data(), nrhs, prm);
+            if (!reopen || restarts >= 20) break;
+            ++restarts;
+            LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, reopen, s));
+        }
+    }
+
+    int worst = LQCD_OK;
+    fill_info(ctl.data(), nrhs, method, eo, mixed, restarts, now_s() - t0, prm, info, &worst);
     if (worst != LQCD_OK) set_error(worst, "solve did not converge for every right-hand side (status %d)", worst);
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves: several systems (lattices of any sizes, own kappa, mu and
+// links) run the same CGNR program; each iteration's kernels are launched
+// once for all systems, with per-system arguments in device tables.
+
+constexpr size_t kStepTableBytes = 16 * 1024;  // per recorded step: arguments, offsets, finalizes of <= 16 systems
+constexpr int kMaxSteps = 32;
+
+struct BatchLayout {
+    Ctl* ctl = nullptr;               // nsys x kMaxRhs control blocks
+    std::vector<SolverPlan> plans;
+    char* tables = nullptr;           // kMaxSteps x kStepTableBytes
+    size_t bytes = 0;
+};
+
+int plan_batch(int nsys, const Geom* g, const lqcd_op* ops, const lqcd_solve_params* prm, void* ws, BatchLayout* L)
+{
+    Arena ar{static_cast<char*>(ws), 0, 0};
+    L->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs * nsys));
+    L->tables = static_cast<char*>(ar.take(kStepTableBytes * kMaxSteps));
+    L->plans.resize(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        ar.off = align_up(ar.off, 256);
+        void* base = ws ? static_cast<char*>(ws) + ar.off : nullptr;
+        plan_solver(g[s], &ops[s], prm, M_CG, base, &L->plans[s]);
+        L->plans[s].rs.ctl = L->ctl ? L->ctl + s * kMaxRhs : nullptr;
+        ar.off += L->plans[s].bytes;
+    }
+    L->bytes = align_up(ar.off, 256);
+    return LQCD_OK;
+}
+
+bool same_kernel(const Step& a, const Step& b)
+{
+    if (a.kind != b.kind) return false;
+    if (a.kind == STEP_DSLASH)
+        return a.d.prec == b.d.prec && a.d.recon == b.d.recon && a.d.nr == b.d.nr && a.d.red == b.d.red &&
+               a.d.dag == b.d.dag && a.d.a.nrhs == b.d.a.nrhs && a.d.grid.y == b.d.grid.y;
+    if (a.kind == STEP_BLAS)
+        return a.b.prec == b.b.prec && a.b.op == b.b.op && a.b.nrhs == b.b.nrhs && a.b.block.x == b.b.block.x;
+    return a.c.pd == b.c.pd && a.c.ps == b.c.ps && a.c.a.accumulate == b.c.a.accumulate && a.c.grid.y == b.c.grid.y;
+}
+
+// The recorded iteration of every system, zipped into batched launches.
+struct BatchProgram {
+    int nsys = 0;
+    std::vector<std::vector<Step>> steps;  // [system][step]
+    std::vector<const char*> tab, offs, fin;  // device tables per step
+    std::vector<int> total;                   // padded blocks per step
+
+    int build(const std::vector<Recorder>& rec, char* dev_tables, hipStream_t s)
+    {
+        nsys = (int)rec.size();
+        const size_t nst = rec[0].steps.size();
+        if (nst > (size_t)kMaxSteps) return set_error(LQCD_EINVAL, "iteration has too many steps to batch");
+        steps.assign(nsys, {});
+        for (int i = 0; i < nsys; ++i) {
+            if (rec[i].steps.size() != nst) return set_error(LQCD_EINVAL, "systems recorded different programs");
+            steps[i] = rec[i].steps;
+        }
+        std::vector<char> host(kStepTableBytes * nst, 0);
+        tab.resize(nst);
+        offs.resize(nst);
+        fin.resize(nst);
+        total.resize(nst);
+        for (size_t k = 0; k < nst; ++k) {
+            for (int i = 1; i < nsys; ++i)
+                if (!same_kernel(steps[0][k], steps[i][k])) return set_error(LQCD_EINVAL, "systems disagree at step %zu", k);
+            char* h = host.data() + k * kStepTableBytes;
+            size_t argsz = 0;
+            const int kind = steps[0][k].kind;
+            argsz = kind == STEP_DSLASH ? sizeof(DslashArgs) : kind == STEP_BLAS ? sizeof(BlasArgs) : sizeof(ConvertArgs);
+            const size_t off_offs = align_up(argsz * nsys, 256);
+            const size_t off_fin = align_up(off_offs + sizeof(int) * (nsys + 1), 256);
+            if (off_fin + sizeof(FinArgs) * nsys > kStepTableBytes) return set_error(LQCD_EINVAL, "batch tables too large");
+            int* o = reinterpret_cast<int*>(h + off_offs);
+            FinArgs* f = reinterpret_cast<FinArgs*>(h + off_fin);
+            int acc = 0;
+            for (int i = 0; i < nsys; ++i) {
+                const Step& st = steps[i][k];
+                o[i] = acc;
+                int gx = 0;
+                if (kind == STEP_DSLASH) {
+                    std::memcpy(h + i * argsz, &st.d.a, argsz);
+                    gx = (int)st.d.grid.x;
+                    f[i] = FinArgs{st.d.a.r.partials, st.d.slots, st.d.a.r.fin, st.d.a.ctl, st.d.a.pred};
+                } else if (kind == STEP_BLAS) {
+                    std::memcpy(h + i * argsz, &st.b.a, argsz);
+                    gx = (int)st.b.grid.x;
+                    f[i] = FinArgs{st.b.a.r.partials, st.b.slots, st.b.a.r.fin, st.b.a.ctl, st.b.a.pred};
+                } else {
+                    std::memcpy(h + i * argsz, &st.c.a, argsz);
+                    gx = (int)st.c.grid.x;
+                }
+                acc += (gx + 7) / 8 * 8;  // each system starts on a multiple of 8 (XCD remap)
+            }
+            o[nsys] = acc;
+            total[k] = acc;
+            const char* d = dev_tables + k * kStepTableBytes;
+            tab[k] = d;
+            offs[k] = d + off_offs;
+            fin[k] = d + off_fin;
+        }
+        LQCD_HIP(hipMemcpyAsync(dev_tables, host.data(), host.size(), hipMemcpyHostToDevice, s));
+        LQCD_HIP(hipStreamSynchronize(s));
+        return LQCD_OK;
+    }
+
+    int run(hipStream_t s) const
+    {
+        const size_t nst = steps[0].size();
+        std::vector<DslashPlan> dp(nsys);
+        std::vector<BlasPlan> bp(nsys);
+        std::vector<ConvertPlan> cp(nsys);
+        for (size_t k = 0; k < nst; ++k) {
+            const int kind = steps[0][k].kind;
+            hipError_t e;
+            if (kind == STEP_DSLASH) {
+                for (int i = 0; i < nsys; ++i) dp[i] = steps[i][k].d;
+                e = exec_dslash_batch(dp.data(), nsys, reinterpret_cast<const DslashArgs*>(tab[k]),
+                                      reinterpret_cast<const int*>(offs[k]), total[k],
+                                      reinterpret_cast<const FinArgs*>(fin[k]), s);
+            } else if (kind == STEP_BLAS) {
+                for (int i = 0; i < nsys; ++i) bp[i] = steps[i][k].b;
+                e = exec_blas_batch(bp.data(), nsys, reinterpret_cast<const BlasArgs*>(tab[k]),
+                                    reinterpret_cast<const int*>(offs[k]), total[k],
+                                    reinterpret_cast<const FinArgs*>(fin[k]), s);
+            } else {
+                for (int i = 0; i < nsys; ++i) cp[i] = steps[i][k].c;
+                e = exec_convert_batch(cp.data(), nsys, reinterpret_cast<const ConvertArgs*>(tab[k]),
+                                       reinterpret_cast<const int*>(offs[k]), total[k], s);
+            }
+            if (e != hipSuccess) return set_error(LQCD_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+        }
+        return LQCD_OK;
+    }
+};
+
+int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U, const void* const* b,
+                void* const* x, const lqcd_solve_params* prm, lqcd_solve_info* info, void* ws, size_t ws_bytes,
+                void* stream)
+{
+    const double t0 = now_s();
+    g_err[0] = 0;
+    if (nsys < 1 || nsys > kMaxSys) return set_error(LQCD_EINVAL, "nsys %d not in [1, %d]", nsys, kMaxSys);
+    if (!geoms || !ops || !U || !b || !x || !info) return set_error(LQCD_EINVAL, "NULL array argument");
+    std::vector<Geom> g(nsys);
+    int rc;
+    for (int s = 0; s < nsys; ++s)
+        if ((rc = validate_solve(&geoms[s], &ops[s], U[s], b[s], x[s], prm, info, M_CG, &g[s]))) return rc;
+    if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
+    if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
+    BatchLayout L;
+    plan_batch(nsys, g.data(), ops, prm, ws, &L);
+    if (ws_bytes < L.bytes) return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nrhs = prm->nrhs;
+    const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+
+    std::vector<CgSystem> sys(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        if ((rc = sys[s].init(g[s], &ops[s], U[s], b[s], x[s], prm, L.plans[s], st))) return rc;
+        if ((rc = sys[s].setup())) return rc;
+    }
+    // record one iteration per system and zip the recordings into batched launches
+    std::vector<Recorder> rec(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        set_recorder(&rec[s]);
+        rc = sys[s].iter();
+        set_recorder(nullptr);
+        if (rc) return rc;
+    }
+    BatchProgram prog;
+    if ((rc = prog.build(rec, L.tables, st))) return rc;
+
+    std::vector<Ctl> ctl;
+    int restarts = 0;
+    for (;;) {
+        for (int s = 0; s < nsys; ++s)
+            if ((rc = sys[s].start())) return rc;
+        rc = drive(st, L.ctl, nsys, kMaxRhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0,
+                   [&]() -> int { return prog.run(st); });
+        if (rc) return rc;
+        for (int s = 0; s < nsys; ++s)
+            if ((rc = sys[s].finish())) return rc;
+        if ((rc = read_ctls(st, L.ctl, nsys * kMaxRhs, ctl))) return rc;
+        bool any = false;
+        std::vector<unsigned> masks(nsys);
+        for (int s = 0; s < nsys; ++s) any = (masks[s] = reopen_mask(ctl.data() + s * kMaxRhs, nrhs, prm)) || any;
+        if (!any || restarts >= 20) break;
+        ++restarts;
+        for (int s = 0; s < nsys; ++s)
+            if (masks[s]) LQCD_K(launch_ctl_reopen(L.ctl + s * kMaxRhs, nrhs, masks[s], st));
+    }
+    int worst = LQCD_OK;
+    const double secs = now_s() - t0;
+    for (int s = 0; s < nsys; ++s)
+        fill_info(ctl.data() + s * kMaxRhs, nrhs, M_CG, prm->eo != 0, prm->inner_prec != 64, restarts, secs, prm,
+                  info + s * nrhs, &worst);
+    if (worst != LQCD_OK) set_error(worst, "batched solve did not converge for every system (status %d)", worst);
     return worst;
 }
 
@@ -1078,6 +1357,31 @@ int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, cons
                    void* stream)
 {
     return solve(M_BICG, geom, op, U, b, x, params, info, ws, ws_bytes, stream);
+}
+
+int lqcd_workspace_bytes_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops,
+                               const lqcd_solve_params* params, size_t* bytes)
+{
+    if (nsys < 1 || nsys > kMaxSys) return set_error(LQCD_EINVAL, "nsys %d not in [1, %d]", nsys, kMaxSys);
+    if (!geoms || !ops || !bytes) return set_error(LQCD_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_params(params, M_CG))) return rc;
+    std::vector<Geom> g(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        if ((rc = make_geom(&geoms[s], &g[s]))) return rc;
+        if ((rc = check_op(&ops[s]))) return rc;
+    }
+    BatchLayout L;
+    plan_batch(nsys, g.data(), ops, params, nullptr, &L);
+    *bytes = L.bytes;
+    return LQCD_OK;
+}
+
+int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,
+                   const void* const* b, void* const* x, const lqcd_solve_params* params, lqcd_solve_info* info,
+                   void* ws, size_t ws_bytes, void* stream)
+{
+    return solve_batch(nsys, geoms, ops, U, b, x, params, info, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -20,21 +20,22 @@ struct BlasRed {
 template <class R>
 __device__ __forceinline__ cplx<R> cval(const double* d) { return {R(d[0]), R(d[1])}; }
 
+// The work of block bx of nbx (x) and by (right-hand side) of a launch.
 template <int PREC, int OP>
-__global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
+__device__ __forceinline__ void blas_block(const BlasArgs& a, int bx, int nbx, int by)
 {
     using IO = SpinorIO<PREC>;
     using R = typename IO::R;
     constexpr int N = BlasRed<OP>::N;
     constexpr int NN = N > 0 ? N : 1;
-    const int rhs = blockIdx.y;
+    const int rhs = by;
     Ctl* ctl = a.ctl ? a.ctl + rhs : nullptr;
     if (pred_skip(a.pred, ctl)) return;
 
     // each sub-field covers nbs whole blocks, so the sub-field is uniform per block
-    const int nbs = gridDim.x / a.nsub;
-    const int sub = blockIdx.x / nbs;
-    const int64_t h = (int64_t)(blockIdx.x - sub * nbs) * blockDim.x + threadIdx.x;
+    const int nbs = nbx / a.nsub;
+    const int sub = bx / nbs;
+    const int64_t h = (int64_t)(bx - sub * nbs) * blockDim.x + threadIdx.x;
     const int64_t soff = (int64_t)sub * a.sub_stride;
     const int64_t r64 = rhs;
     const int64_t S = a.S;
@@ -173,15 +174,48 @@ __global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
         }
     }
 
-    if (N > 0) block_reduce_store<NN>(red, a.r.partials + (int64_t)rhs * gridDim.x * NN, blockIdx.x);
+    if (N > 0) block_reduce_store<NN>(red, a.r.partials + (int64_t)rhs * nbx * NN, bx);
+}
+
+template <int PREC, int OP>
+__global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
+{
+    blas_block<PREC, OP>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+template <int PREC, int OP>
+__global__ void __launch_bounds__(256) k_blas_batch(const BlasArgs* __restrict__ tab, const int* __restrict__ offs,
+                                                   int nsys)
+{
+    const int x = blockIdx.x;
+    int s = 0;
+    while (s + 1 < nsys && x >= offs[s + 1]) ++s;
+    const int bx = x - offs[s];
+    if (bx >= tab[s].gx) return;  // padding of the system's range
+    blas_block<PREC, OP>(tab[s], bx, tab[s].gx, blockIdx.y);
+}
+
+struct BlasLaunch {
+    const BlasArgs* a;
+    const BlasArgs* tab;
+    const int* offs;
+    int nsys;
+};
+
+template <int PREC, int OP>
+static hipError_t blas_one(const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (L.tab) hipLaunchKernelGGL((k_blas_batch<PREC, OP>), grid, block, 0, s, L.tab, L.offs, L.nsys);
+    else hipLaunchKernelGGL((k_blas<PREC, OP>), grid, block, 0, s, *L.a);
+    return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t blas_op(int op, const BlasArgs& a, dim3 grid, dim3 block, hipStream_t s)
+static hipError_t blas_op(int op, const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (op) {
 #define LQCD_BLAS_CASE(OP) \
-    case OP: hipLaunchKernelGGL((k_blas<PREC, OP>), grid, block, 0, s, a); break;
+    case OP: return blas_one<PREC, OP>(L, grid, block, s);
         LQCD_BLAS_CASE(BLAS_CG_XR)
         LQCD_BLAS_CASE(BLAS_CG_P)
         LQCD_BLAS_CASE(BLAS_COPY)
@@ -196,25 +230,71 @@ static hipError_t blas_op(int op, const BlasArgs& a, dim3 grid, dim3 block, hipS
 #undef LQCD_BLAS_CASE
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+static hipError_t blas_prec(int prec, int op, const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (prec == 64) return blas_op<64>(op, L, grid, block, s);
+    if (prec == 32) return blas_op<32>(op, L, grid, block, s);
+    if (prec == 16) return blas_op<16>(op, L, grid, block, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t plan_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, BlasPlan* out)
+{
+    if (prec != 64 && prec != 32 && prec != 16) return hipErrorInvalidValue;
+    BlasPlan& p = *out;
+    p.a = a;
+    p.prec = prec;
+    p.op = op;
+    p.nrhs = nrhs;
+    const int blk = cfg.block;
+    const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
+    p.grid = dim3(nbs * a.nsub, nrhs);
+    p.a.gx = (int)p.grid.x;
+    p.block = dim3(blk);
+    p.nfin = (op == BLAS_CG_XR || op == BLAS_NORM) ? 1 : (op == BLAS_BI_XR || op == BLAS_NORM_DOT) ? 3 : 0;
+    p.slots = (int)p.grid.x;
+    if (p.nfin && p.slots > a.r.capacity) return hipErrorInvalidValue;  // partials too small
+    return hipSuccess;
+}
+
+hipError_t exec_blas(const BlasPlan& p, hipStream_t s)
+{
+    BlasLaunch L{&p.a, nullptr, nullptr, 1};
+    const hipError_t e = blas_prec(p.prec, p.op, L, p.grid, p.block, s);
+    if (e != hipSuccess || p.nfin == 0) return e;
+    return launch_finalize(p.nfin, p.a.r.partials, p.slots, p.a.r.fin, p.a.ctl, p.a.pred, p.nrhs, s);
+}
+
+hipError_t exec_blas_batch(const BlasPlan* plans, int n, const BlasArgs* tab, const int* offs, int total_blocks,
+                           const FinArgs* fin_tab, hipStream_t s)
+{
+    if (n < 1) return hipErrorInvalidValue;
+    const BlasPlan& p0 = plans[0];
+    BlasLaunch L{nullptr, tab, offs, n};
+    const hipError_t e = blas_prec(p0.prec, p0.op, L, dim3((unsigned)total_blocks, p0.grid.y), p0.block, s);
+    if (e != hipSuccess || p0.nfin == 0) return e;
+    return launch_finalize_batch(p0.nfin, fin_tab, n, p0.nrhs, s);
 }
 
 hipError_t launch_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, hipStream_t s)
 {
-    const int blk = cfg.block;
-    const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
-    dim3 grid(nbs * a.nsub, nrhs), block(blk);
-    const bool reduces = op == BLAS_CG_XR || op == BLAS_NORM || op == BLAS_BI_XR || op == BLAS_NORM_DOT;
-    if (reduces && (int)grid.x > a.r.capacity) return hipErrorInvalidValue;  // partials too small
-    hipError_t e;
-    if (prec == 64) e = blas_op<64>(op, a, grid, block, s);
-    else if (prec == 32) e = blas_op<32>(op, a, grid, block, s);
-    else if (prec == 16) e = blas_op<16>(op, a, grid, block, s);
-    else return hipErrorInvalidValue;
-    const int N = (op == BLAS_CG_XR || op == BLAS_NORM) ? 1 : (op == BLAS_BI_XR || op == BLAS_NORM_DOT) ? 3 : 0;
-    if (e != hipSuccess || N == 0) return e;
-    return launch_finalize(N, a.r.partials, (int)grid.x, a.r.fin, a.ctl, a.pred, nrhs, s);
+    BlasPlan p;
+    hipError_t e = plan_blas(prec, op, a, nrhs, cfg, &p);
+    if (e != hipSuccess) return e;
+    if (Recorder* r = active_recorder()) {
+        r->steps.push_back(Step{});
+        r->steps.back().kind = STEP_BLAS;
+        r->steps.back().b = p;
+        return hipSuccess;
+    }
+    return exec_blas(p, s);
 }
+
+thread_local Recorder* g_recorder = nullptr;
+Recorder* active_recorder() { return g_recorder; }
+void set_recorder(Recorder* r) { g_recorder = r; }
 
 template <int N>
 __global__ void __launch_bounds__(256) k_finalize(const double* partials, int nblocks, int fin, Ctl* ctl, int pred)
@@ -240,6 +320,42 @@ __global__ void __launch_bounds__(256) k_finalize(const double* partials, int nb
     }
 }
 
+// One block per (system, right-hand side): the finalize of every system of a batched launch.
+template <int N>
+__global__ void __launch_bounds__(256) k_finalize_batch(const FinArgs* __restrict__ tab, int nrhs)
+{
+    const FinArgs& f = tab[blockIdx.x / nrhs];
+    const int rhs = blockIdx.x % nrhs;
+    Ctl* c = f.ctl + rhs;
+    if (pred_skip(f.pred, c)) return;
+    const double* p = f.partials + (int64_t)rhs * f.nblocks * N;
+    double v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = 0.0;
+    for (int b = threadIdx.x; b < f.nblocks; b += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] += p[(int64_t)b * N + j];
+    __shared__ double tot[N];
+    block_reduce_store<N>(v, tot, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) t[j] = tot[j];
+        finalize<N>(f.fin, c, t);
+    }
+}
+
+hipError_t launch_finalize_batch(int N, const FinArgs* tab, int nsys, int nrhs, hipStream_t s)
+{
+    dim3 g((unsigned)(nsys * nrhs)), b(256);
+    if (N == 1) hipLaunchKernelGGL(k_finalize_batch<1>, g, b, 0, s, tab, nrhs);
+    else if (N == 2) hipLaunchKernelGGL(k_finalize_batch<2>, g, b, 0, s, tab, nrhs);
+    else if (N == 3) hipLaunchKernelGGL(k_finalize_batch<3>, g, b, 0, s, tab, nrhs);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, Ctl* ctl, int pred, int nrhs,
                            hipStream_t s)
 {
@@ -256,14 +372,14 @@ hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, 
 // Precision conversion
 
 template <int PD, int PS, bool ACC>
-__global__ void __launch_bounds__(256) k_convert(const ConvertArgs a)
+__device__ __forceinline__ void convert_block(const ConvertArgs& a, int bx, int nbx, int by)
 {
-    const int rhs = blockIdx.y;
+    const int rhs = by;
     Ctl* ctl = a.ctl ? a.ctl + rhs : nullptr;
     if (pred_skip(a.pred, ctl)) return;
-    const int nbs = gridDim.x / a.nsub;
-    const int sub = blockIdx.x / nbs;
-    const int64_t h = (int64_t)(blockIdx.x - sub * nbs) * blockDim.x + threadIdx.x;
+    const int nbs = nbx / a.nsub;
+    const int sub = bx / nbs;
+    const int64_t h = (int64_t)(bx - sub * nbs) * blockDim.x + threadIdx.x;
     if (h >= a.Vh) return;
     char* dst = static_cast<char*>(a.dst) + rhs * a.rhs_stride_dst + sub * a.sub_stride_dst;
     char* src = static_cast<char*>(a.src) + rhs * a.rhs_stride_src + sub * a.sub_stride_src;
@@ -291,22 +407,50 @@ __global__ void __launch_bounds__(256) k_convert(const ConvertArgs a)
     }
 }
 
-template <int PD, int PS>
-static hipError_t convert2(const ConvertArgs& a, dim3 g, dim3 b, hipStream_t s)
+template <int PD, int PS, bool ACC>
+__global__ void __launch_bounds__(256) k_convert(const ConvertArgs a)
 {
-    if (a.accumulate) hipLaunchKernelGGL((k_convert<PD, PS, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_convert<PD, PS, false>), g, b, 0, s, a);
+    convert_block<PD, PS, ACC>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+template <int PD, int PS, bool ACC>
+__global__ void __launch_bounds__(256) k_convert_batch(const ConvertArgs* __restrict__ tab,
+                                                      const int* __restrict__ offs, int nsys)
+{
+    const int x = blockIdx.x;
+    int s = 0;
+    while (s + 1 < nsys && x >= offs[s + 1]) ++s;
+    const int bx = x - offs[s];
+    if (bx >= tab[s].gx) return;  // padding of the system's range
+    convert_block<PD, PS, ACC>(tab[s], bx, tab[s].gx, blockIdx.y);
+}
+
+struct ConvertLaunch {
+    const ConvertArgs* a;
+    const ConvertArgs* tab;
+    const int* offs;
+    int nsys;
+};
+
+template <int PD, int PS, bool ACC>
+static hipError_t convert_one(const ConvertLaunch& L, dim3 g, dim3 b, hipStream_t s)
+{
+    if (L.tab) hipLaunchKernelGGL((k_convert_batch<PD, PS, ACC>), g, b, 0, s, L.tab, L.offs, L.nsys);
+    else hipLaunchKernelGGL((k_convert<PD, PS, ACC>), g, b, 0, s, *L.a);
     return hipGetLastError();
 }
 
-hipError_t launch_convert(int pd, int ps, const ConvertArgs& a, int nrhs, hipStream_t s)
+template <int PD, int PS>
+static hipError_t convert2(bool acc, const ConvertLaunch& L, dim3 g, dim3 b, hipStream_t s)
 {
-    const int blk = 256;
-    const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
-    dim3 g(nbs * a.nsub, nrhs), b(blk);
-    if (a.accumulate && pd != 64) return hipErrorInvalidValue;
+    return acc ? convert_one<PD, PS, true>(L, g, b, s) : convert_one<PD, PS, false>(L, g, b, s);
+}
+
+static hipError_t convert_any(int pd, int ps, bool acc, const ConvertLaunch& L, dim3 g, dim3 b, hipStream_t s)
+{
+    if (acc && pd != 64) return hipErrorInvalidValue;
 #define LQCD_CONV(D, S_)                               \
-    if (pd == D && ps == S_) return convert2<D, S_>(a, g, b, s);
+    if (pd == D && ps == S_) return convert2<D, S_>(acc, L, g, b, s);
     LQCD_CONV(64, 64)
     LQCD_CONV(64, 32)
     LQCD_CONV(64, 16)
@@ -318,6 +462,48 @@ hipError_t launch_convert(int pd, int ps, const ConvertArgs& a, int nrhs, hipStr
     LQCD_CONV(16, 16)
 #undef LQCD_CONV
     return hipErrorInvalidValue;
+}
+
+hipError_t plan_convert(int pd, int ps, const ConvertArgs& a, int nrhs, ConvertPlan* out)
+{
+    const int blk = 256;
+    const unsigned nbs = (unsigned)((a.Vh + blk - 1) / blk);
+    out->a = a;
+    out->pd = pd;
+    out->ps = ps;
+    out->grid = dim3(nbs * a.nsub, nrhs);
+    out->a.gx = (int)out->grid.x;
+    out->block = dim3(blk);
+    return hipSuccess;
+}
+
+hipError_t exec_convert(const ConvertPlan& p, hipStream_t s)
+{
+    ConvertLaunch L{&p.a, nullptr, nullptr, 1};
+    return convert_any(p.pd, p.ps, p.a.accumulate != 0, L, p.grid, p.block, s);
+}
+
+hipError_t exec_convert_batch(const ConvertPlan* plans, int n, const ConvertArgs* tab, const int* offs,
+                              int total_blocks, hipStream_t s)
+{
+    if (n < 1) return hipErrorInvalidValue;
+    const ConvertPlan& p0 = plans[0];
+    ConvertLaunch L{nullptr, tab, offs, n};
+    return convert_any(p0.pd, p0.ps, p0.a.accumulate != 0, L, dim3((unsigned)total_blocks, p0.grid.y), p0.block, s);
+}
+
+hipError_t launch_convert(int pd, int ps, const ConvertArgs& a, int nrhs, hipStream_t s)
+{
+    ConvertPlan p;
+    hipError_t e = plan_convert(pd, ps, a, nrhs, &p);
+    if (e != hipSuccess) return e;
+    if (Recorder* r = active_recorder()) {
+        r->steps.push_back(Step{});
+        r->steps.back().kind = STEP_CONVERT;
+        r->steps.back().c = p;
+        return hipSuccess;
+    }
+    return exec_convert(p, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,19 +6,18 @@
 
 namespace lqcd {
 
-hipError_t launch_dslash_64(int recon, int nr, bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block,
+hipError_t launch_dslash_64(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
-hipError_t launch_dslash_32(int recon, int nr, bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block,
+hipError_t launch_dslash_32(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
-hipError_t launch_dslash_16(int recon, int nr, bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block,
+hipError_t launch_dslash_16(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
 
-static hipError_t launch_dslash_prec(int prec, int recon, int nr, bool dag, int red, const DslashArgs& a, dim3 grid,
-                                     dim3 block, hipStream_t s)
+static hipError_t launch_dslash_prec(const DslashPlan& p, const DslashLaunch& L, dim3 grid, hipStream_t s)
 {
-    if (prec == 64) return launch_dslash_64(recon, nr, dag, red, a, grid, block, s);
-    if (prec == 32) return launch_dslash_32(recon, nr, dag, red, a, grid, block, s);
-    if (prec == 16) return launch_dslash_16(recon, nr, dag, red, a, grid, block, s);
+    if (p.prec == 64) return launch_dslash_64(p.recon, p.nr, p.dag, p.red, L, grid, p.block, s);
+    if (p.prec == 32) return launch_dslash_32(p.recon, p.nr, p.dag, p.red, L, grid, p.block, s);
+    if (p.prec == 16) return launch_dslash_16(p.recon, p.nr, p.dag, p.red, L, grid, p.block, s);
     return hipErrorInvalidValue;
 }
 
@@ -32,10 +31,19 @@ int dslash_rhs_tile(int prec, int want, int nrhs)
     return nr;
 }
 
-hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& args, int nrhs,
-                         const Launch& cfg, hipStream_t s)
+hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& args, int nrhs, const Launch& cfg,
+                       DslashPlan* out)
 {
-    DslashArgs a = args;
+    if (!((prec == 64 && (recon == 18 || recon == 12)) || (prec == 32 && (recon == 18 || recon == 12)) ||
+          (prec == 16 && recon == 12)))
+        return hipErrorInvalidValue;
+    DslashPlan& p = *out;
+    p.prec = prec;
+    p.recon = recon;
+    p.dag = dagger;
+    p.red = red;
+    DslashArgs& a = p.a;
+    a = args;
     a.swizzle = cfg.swizzle;
     a.nrhs = nrhs;
     int blk = cfg.block;
@@ -63,26 +71,66 @@ hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const Dslash
             nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
         }
     }
-    const int nr = dslash_rhs_tile(prec, cfg.rhs_tile, nrhs);
-    a.ntiles = (nrhs + nr - 1) / nr;
+    a.bdim = blk;
+    p.nr = dslash_rhs_tile(prec, cfg.rhs_tile, nrhs);
+    a.ntiles = (nrhs + p.nr - 1) / p.nr;
     a.nsp = (int)nbh;
     // interleave right-hand-side tiles into the block order when there are several
     a.rhs_group = (cfg.rhs_group > 1 && a.ntiles > 1) ? (cfg.rhs_group < a.ntiles ? cfg.rhs_group : a.ntiles) : 0;
-    dim3 block(blk);
-    dim3 grid;
+    p.block = dim3(blk);
     if (a.rhs_group > 0) {
         const unsigned groups = (unsigned)((a.ntiles + a.rhs_group - 1) / a.rhs_group);
-        grid = dim3(nbh * (unsigned)a.rhs_group * groups * (a.full ? 2u : 1u), 1);
+        p.grid = dim3(nbh * (unsigned)a.rhs_group * groups * (a.full ? 2u : 1u), 1);
     } else {
-        grid = dim3(nbh * (a.full ? 2u : 1u), (unsigned)a.ntiles);
+        p.grid = dim3(nbh * (a.full ? 2u : 1u), (unsigned)a.ntiles);
     }
+    a.gx = (int)p.grid.x;
     // partials hold one slot per spatial block and parity for each right-hand side
-    const int slots = (int)nbh * (a.full ? 2 : 1);
-    if (red != RED_NONE && slots > a.r.capacity) return hipErrorInvalidValue;  // partials too small
-    const hipError_t e = launch_dslash_prec(prec, recon, nr, dagger, red, a, grid, block, s);
-    if (e != hipSuccess || red == RED_NONE) return e;
-    return launch_finalize((red == RED_NORM ? 1 : red == RED_DOT_AUX ? 2 : 3), a.r.partials, slots, a.r.fin, a.ctl,
-                           a.pred, nrhs, s);
+    p.slots = (int)nbh * (a.full ? 2 : 1);
+    if (red != RED_NONE && p.slots > a.r.capacity) return hipErrorInvalidValue;  // partials too small
+    p.nfin = red == RED_NONE ? 0 : red == RED_NORM ? 1 : red == RED_DOT_AUX ? 2 : 3;
+    return hipSuccess;
+}
+
+hipError_t exec_dslash(const DslashPlan& p, hipStream_t s)
+{
+    DslashLaunch L{&p.a, nullptr, nullptr, 1};
+    const hipError_t e = launch_dslash_prec(p, L, p.grid, s);
+    if (e != hipSuccess || p.nfin == 0) return e;
+    return launch_finalize(p.nfin, p.a.r.partials, p.slots, p.a.r.fin, p.a.ctl, p.a.pred, p.a.nrhs, s);
+}
+
+hipError_t exec_dslash_batch(const DslashPlan* plans, int n, const DslashArgs* tab, const int* offs, int total_blocks,
+                             const FinArgs* fin_tab, hipStream_t s)
+{
+    if (n < 1) return hipErrorInvalidValue;
+    const DslashPlan& p0 = plans[0];
+    unsigned gy = p0.grid.y, bx = p0.block.x;
+    for (int i = 1; i < n; ++i) {
+        gy = plans[i].grid.y > gy ? plans[i].grid.y : gy;
+        bx = plans[i].block.x > bx ? plans[i].block.x : bx;
+    }
+    DslashPlan q = p0;
+    q.block = dim3(bx);
+    DslashLaunch L{nullptr, tab, offs, n};
+    const hipError_t e = launch_dslash_prec(q, L, dim3((unsigned)total_blocks, gy), s);
+    if (e != hipSuccess || p0.nfin == 0) return e;
+    return launch_finalize_batch(p0.nfin, fin_tab, n, p0.a.nrhs, s);
+}
+
+hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& args, int nrhs,
+                         const Launch& cfg, hipStream_t s)
+{
+    DslashPlan p;
+    hipError_t e = plan_dslash(prec, recon, dagger, red, args, nrhs, cfg, &p);
+    if (e != hipSuccess) return e;
+    if (Recorder* r = active_recorder()) {
+        r->steps.push_back(Step{});
+        r->steps.back().kind = STEP_DSLASH;
+        r->steps.back().d = p;
+        return hipSuccess;
+    }
+    return exec_dslash(p, s);
 }
 
 }  // namespace lqcd

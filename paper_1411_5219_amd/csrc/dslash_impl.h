@@ -148,13 +148,15 @@ __device__ void block_reduce_tile(double (&v)[NR][N], double* partials, int nb, 
     }
 }
 
+// The work of one block: block bx of nbx along x and by along y of the
+// launch that serves this set of arguments.
 template <int PREC, int RECON, bool DAG, int RED, int NR>
-__global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
+__device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nbx, int by)
 {
     using R = typename SpinorIO<PREC>::R;
     constexpr int N = RedN<RED>::N;
-    const int nb = gridDim.x;
-    int bid = a.swizzle ? xcd_swizzle(blockIdx.x, nb) : (int)blockIdx.x;
+    const int nb = nbx;
+    int bid = a.swizzle ? xcd_swizzle(bx, nb) : bx;
     int p = a.parity;
     int64_t poff = 0, ioff = 0;  // parity offsets of output-side / neighbour fields
     if (a.full) {  // both parities in one launch: the first nb/2 blocks even, the rest odd
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
         ioff = (1 - p) * a.par_bytes;
     }
     // right-hand-side tile of this block and its spatial block
-    int tile = blockIdx.y;
+    int tile = by;
     int nsp = a.full ? nb >> 1 : nb;  // spatial blocks per parity (per tile)
     if (a.rhs_group > 0) {
         const int G = a.rhs_group;
@@ -193,8 +195,8 @@ __global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
     int h, xh, y, z, t;
     bool valid;
     if (a.rows == 0) {
-        h = bid * blockDim.x + threadIdx.x;
-        valid = h < a.g.Vh;
+        h = bid * a.bdim + threadIdx.x;
+        valid = (int)threadIdx.x < a.bdim && h < a.g.Vh;
         xh = h % Lxh;
         int r = h / Lxh;
         y = r % Ly;
@@ -346,35 +348,65 @@ __global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
     if (RED != RED_NONE) block_reduce_tile<NR, N>(tot, a.r.partials, nslots, rhs0, a.nrhs, pslot);
 }
 
-template <int PREC, int RECON, bool DAG, int NR>
-static hipError_t launch_red(int red, const DslashArgs& a, dim3 grid, dim3 block, hipStream_t s)
+template <int PREC, int RECON, bool DAG, int RED, int NR>
+__global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
 {
-    switch (red) {
-    case RED_NONE: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_NONE, NR>), grid, block, 0, s, a); break;
-    case RED_NORM: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_NORM, NR>), grid, block, 0, s, a); break;
-    case RED_NORM_DS: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_NORM_DS, NR>), grid, block, 0, s, a); break;
-    case RED_DOT_AUX: hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED_DOT_AUX, NR>), grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    dslash_block<PREC, RECON, DAG, RED, NR>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+// Several systems (lattices of different sizes) in one launch: block x of the
+// flattened grid belongs to system s with offs[s] <= x < offs[s + 1]; each
+// system's arguments come from the device table tab.
+template <int PREC, int RECON, bool DAG, int RED, int NR>
+__global__ void __launch_bounds__(256) k_dslash_eo_batch(const DslashArgs* __restrict__ tab,
+                                                        const int* __restrict__ offs, int nsys)
+{
+    const int x = blockIdx.x;
+    int s = 0;
+    while (s + 1 < nsys && x >= offs[s + 1]) ++s;
+    // each system's range starts at a multiple of 8 (XCD remap); blocks past
+    // the system's own grid are padding
+    const int bx = x - offs[s];
+    if (bx >= tab[s].gx) return;  // (a tile index past ntiles finds no active right-hand side)
+    dslash_block<PREC, RECON, DAG, RED, NR>(tab[s], bx, tab[s].gx, blockIdx.y);
+}
+
+template <int PREC, int RECON, bool DAG, int RED, int NR>
+static hipError_t launch_one(const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (L.tab) hipLaunchKernelGGL((k_dslash_eo_batch<PREC, RECON, DAG, RED, NR>), grid, block, 0, s, L.tab, L.offs, L.nsys);
+    else hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED, NR>), grid, block, 0, s, *L.a);
     return hipGetLastError();
 }
 
-template <int PREC, int RECON, int NR>
-static hipError_t launch_dag(bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block, hipStream_t s)
+template <int PREC, int RECON, bool DAG, int NR>
+static hipError_t launch_red(int red, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    return dag ? launch_red<PREC, RECON, true, NR>(red, a, grid, block, s)
-               : launch_red<PREC, RECON, false, NR>(red, a, grid, block, s);
+    switch (red) {
+    case RED_NONE: return launch_one<PREC, RECON, DAG, RED_NONE, NR>(L, grid, block, s);
+    case RED_NORM: return launch_one<PREC, RECON, DAG, RED_NORM, NR>(L, grid, block, s);
+    case RED_NORM_DS: return launch_one<PREC, RECON, DAG, RED_NORM_DS, NR>(L, grid, block, s);
+    case RED_DOT_AUX: return launch_one<PREC, RECON, DAG, RED_DOT_AUX, NR>(L, grid, block, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int RECON, int NR>
+static hipError_t launch_dag(bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+{
+    return dag ? launch_red<PREC, RECON, true, NR>(red, L, grid, block, s)
+               : launch_red<PREC, RECON, false, NR>(red, L, grid, block, s);
 }
 
 // Right-hand-side tiles compiled per storage: 1, 2 and 4 for FP32 and FP16
 // (the multi-RHS inner solves), 1 and 2 for FP64.
 template <int PREC, int RECON>
-inline hipError_t launch_tile(int nr, bool dag, int red, const DslashArgs& a, dim3 grid, dim3 block, hipStream_t s)
+inline hipError_t launch_tile(int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (nr == 1) return launch_dag<PREC, RECON, 1>(dag, red, a, grid, block, s);
-    if (nr == 2) return launch_dag<PREC, RECON, 2>(dag, red, a, grid, block, s);
+    if (nr == 1) return launch_dag<PREC, RECON, 1>(dag, red, L, grid, block, s);
+    if (nr == 2) return launch_dag<PREC, RECON, 2>(dag, red, L, grid, block, s);
     if constexpr (PREC != 64)
-        if (nr == 4) return launch_dag<PREC, RECON, 4>(dag, red, a, grid, block, s);
+        if (nr == 4) return launch_dag<PREC, RECON, 4>(dag, red, L, grid, block, s);
     return hipErrorInvalidValue;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace lqcd {
 
 // Lattice geometry as the kernels see it.
@@ -121,6 +123,8 @@ struct DslashArgs {
     int rhs_group;
     int ntiles;             // right-hand-side tiles (ceil(nrhs / tile))
     int nsp;                // spatial blocks per parity (rhs_group > 0)
+    int bdim;               // work-items of a block that this argument set uses
+    int gx;                 // planned grid.x (batched launches pad each system's range)
 };
 
 // Launch configuration picked per kernel (autotuned).
@@ -144,6 +148,41 @@ hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, 
 // ---- launchers (return hipError_t) ----
 hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& a, int nrhs,
                          const Launch& cfg, hipStream_t s);
+
+// One Dslash launch, or a batch of nsys argument sets in device memory.
+struct DslashLaunch {
+    const DslashArgs* a;
+    const DslashArgs* tab;
+    const int* offs;
+    int nsys;
+};
+
+// Finalize of one reduction of one system (batched finalize tables).
+struct FinArgs {
+    const double* partials;
+    int nblocks;
+    int fin;
+    Ctl* ctl;
+    int pred;
+};
+
+// A planned Dslash launch (final arguments, grid, kernel selectors).
+struct DslashPlan {
+    DslashArgs a;
+    dim3 grid, block;
+    int prec, recon, nr, red;
+    bool dag;
+    int nfin;   // values per finalize (0: no reduction)
+    int slots;  // partial slots per right-hand side
+};
+hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& args, int nrhs, const Launch& cfg,
+                       DslashPlan* out);
+hipError_t exec_dslash(const DslashPlan& p, hipStream_t s);
+// plans[0..n) share kernel selectors; tab / offs / fin_tab are their device
+// tables (arguments, block offsets with offs[n] = total_blocks, finalizes).
+hipError_t exec_dslash_batch(const DslashPlan* plans, int n, const DslashArgs* tab, const int* offs, int total_blocks,
+                             const FinArgs* fin_tab, hipStream_t s);
+hipError_t launch_finalize_batch(int N, const FinArgs* tab, int nsys, int nrhs, hipStream_t s);
 
 // Site-local BLAS-1 on parity fields of precision prec (all operands the same).
 enum Blas {
@@ -177,9 +216,21 @@ struct BlasArgs {
     int64_t st_x, st_y, st_z, st_w, st_v, st_r0;
     RedArgs r;
     Ctl* ctl;
+    int gx;                 // planned grid.x (batched launches)
 };
 
 hipError_t launch_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, hipStream_t s);
+
+struct BlasPlan {
+    BlasArgs a;
+    dim3 grid, block;
+    int prec, op, nrhs;
+    int nfin, slots;
+};
+hipError_t plan_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch& cfg, BlasPlan* out);
+hipError_t exec_blas(const BlasPlan& p, hipStream_t s);
+hipError_t exec_blas_batch(const BlasPlan* plans, int n, const BlasArgs* tab, const int* offs, int total_blocks,
+                           const FinArgs* fin_tab, hipStream_t s);
 
 // Precision conversion of a parity field: dst(prec_dst) = src(prec_src);
 // with accumulate, dst += src (dst FP64).  Optional FP64 ||dst||^2 reduction.
@@ -195,8 +246,36 @@ struct ConvertArgs {
     int zero_src;           // src = 0 afterwards
     int pred;
     Ctl* ctl;
+    int gx;                 // planned grid.x (batched launches)
 };
 hipError_t launch_convert(int prec_dst, int prec_src, const ConvertArgs& a, int nrhs, hipStream_t s);
+
+struct ConvertPlan {
+    ConvertArgs a;
+    dim3 grid, block;
+    int pd, ps;
+};
+hipError_t plan_convert(int prec_dst, int prec_src, const ConvertArgs& a, int nrhs, ConvertPlan* out);
+hipError_t exec_convert(const ConvertPlan& p, hipStream_t s);
+hipError_t exec_convert_batch(const ConvertPlan* plans, int n, const ConvertArgs* tab, const int* offs, int total_blocks,
+                              hipStream_t s);
+
+// Recording: while a recorder is active on the calling thread, launch_dslash,
+// launch_blas and launch_convert append their plans instead of launching.
+// The solver uses it to record one iteration per system and replay the
+// recorded steps of all systems as batched launches.
+enum StepKind { STEP_DSLASH = 0, STEP_BLAS = 1, STEP_CONVERT = 2 };
+struct Step {
+    int kind;
+    DslashPlan d;
+    BlasPlan b;
+    ConvertPlan c;
+};
+struct Recorder {
+    std::vector<Step> steps;
+};
+Recorder* active_recorder();
+void set_recorder(Recorder* r);
 
 // Canonical complex128 <-> internal layouts.
 hipError_t launch_pack_spinor(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s);

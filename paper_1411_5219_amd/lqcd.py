@@ -29,7 +29,7 @@ ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV
 SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_set_launch",
            "lqcd_get_launch", "lqcd_autotune_dslash", "lqcd_pack_gauge",
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
-           "bicgstab_solve"]
+           "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch"]
 
 
 class Geom(ctypes.Structure):
@@ -94,6 +94,9 @@ def _load():
         "dslash_eo_apply": ([G, O, vp, vp, vp, i32, i32, i32, i32, vp, vp], ctypes.c_int),
         "cg_solve": ([G, O, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "bicgstab_solve": ([G, O, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "lqcd_workspace_bytes_batch": ([i32, G, O, P, szp], ctypes.c_int),
+        "cg_solve_batch": ([i32, G, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), P, I, vp,
+                            ctypes.c_size_t, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -232,3 +235,30 @@ def cg_solve(g, o, U, b, x, params, ws, stream=None):
 
 def bicgstab_solve(g, o, U, b, x, params, ws, stream=None):
     return _solve(_lib.bicgstab_solve, g, o, U, b, x, params, ws, stream)
+
+
+def lqcd_workspace_bytes_batch(geoms, ops, params) -> int:
+    n = len(geoms)
+    G = (Geom * n)(*geoms)
+    O = (Op * n)(*ops)
+    out = ctypes.c_size_t()
+    _check(_lib.lqcd_workspace_bytes_batch(n, G, O, ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def cg_solve_batch(geoms, ops, Us, bs, xs, params, ws, stream=None):
+    """Solve len(geoms) systems together.  Returns (status, [[info per rhs] per system])."""
+    n = len(geoms)
+    G = (Geom * n)(*geoms)
+    O = (Op * n)(*ops)
+    vp = ctypes.c_void_p
+    Up = (vp * n)(*[_ptr(u) for u in Us])
+    Bp = (vp * n)(*[_ptr(v) for v in bs])
+    Xp = (vp * n)(*[_ptr(v) for v in xs])
+    infos = (SolveInfo * (n * params.nrhs))()
+    nbytes = ws.numel() * ws.element_size() if hasattr(ws, "numel") else 0
+    rc = _lib.cg_solve_batch(n, G, O, Up, Bp, Xp, ctypes.byref(params), infos, _ptr(ws), nbytes, _stream(stream))
+    if rc in (EINVAL, EUNSUPPORTED, EHIP):
+        raise LqcdError(rc, lqcd_last_error())
+    flat = [i.as_dict() for i in infos]
+    return rc, [flat[s * params.nrhs:(s + 1) * params.nrhs] for s in range(n)]

@@ -90,3 +90,22 @@ def test_workspace_grows_with_rhs_and_mixed():
     b = L.lqcd_workspace_bytes(g, o, L.solve_params(nrhs=4))
     c = L.lqcd_workspace_bytes(g, o, L.solve_params(inner_prec=32))
     assert b > 3 * a > 0 and c > 0
+
+
+def test_batch_workspace_query_validates():
+    from paper_1411_5219_amd import lqcd as L
+    g = [L.geom((4, 4, 4, 4)), L.geom((6, 6, 6, 4))]
+    o = [L.op(0.15, 0.005), L.op(0.16, 0.005)]
+    p = L.solve_params(nrhs=4, inner_prec=32)
+    n2 = L.lqcd_workspace_bytes_batch(g, o, p)
+    n1 = L.lqcd_workspace_bytes_batch(g[:1], o[:1], p)
+    assert n2 > n1 > 0
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes_batch([], [], p)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes_batch([L.geom((4, 4, 5, 4))], o[:1], p)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes_batch(g * 9, o * 9, p)
+    assert e.value.code == L.EINVAL
