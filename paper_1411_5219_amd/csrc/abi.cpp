@@ -914,7 +914,7 @@ bool same_kernel(const Step& a, const Step& b)
 {
     if (a.kind != b.kind) return false;
     if (a.kind == STEP_DSLASH)
-        return a.d.prec == b.d.prec && a.d.recon == b.d.recon && a.d.nr == b.d.nr && a.d.red == b.d.red &&
+        return a.d.prec == b.d.prec && a.d.recon == b.d.recon && a.d.nr == b.d.nr && a.d.lnt == b.d.lnt && a.d.red == b.d.red &&
                a.d.dag == b.d.dag && a.d.a.nrhs == b.d.a.nrhs && a.d.grid.y == b.d.grid.y;
     if (a.kind == STEP_BLAS)
         return a.b.prec == b.b.prec && a.b.op == b.b.op && a.b.nrhs == b.b.nrhs && a.b.block.x == b.b.block.x;

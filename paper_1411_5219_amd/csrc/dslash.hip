@@ -6,18 +6,18 @@
 
 namespace lqcd {
 
-hipError_t launch_dslash_64(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
+hipError_t launch_dslash_64(int recon, int nr, bool lnt, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
-hipError_t launch_dslash_32(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
+hipError_t launch_dslash_32(int recon, int nr, bool lnt, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
-hipError_t launch_dslash_16(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
+hipError_t launch_dslash_16(int recon, int nr, bool lnt, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
 
 static hipError_t launch_dslash_prec(const DslashPlan& p, const DslashLaunch& L, dim3 grid, hipStream_t s)
 {
-    if (p.prec == 64) return launch_dslash_64(p.recon, p.nr, p.dag, p.red, L, grid, p.block, s);
-    if (p.prec == 32) return launch_dslash_32(p.recon, p.nr, p.dag, p.red, L, grid, p.block, s);
-    if (p.prec == 16) return launch_dslash_16(p.recon, p.nr, p.dag, p.red, L, grid, p.block, s);
+    if (p.prec == 64) return launch_dslash_64(p.recon, p.nr, p.lnt, p.dag, p.red, L, grid, p.block, s);
+    if (p.prec == 32) return launch_dslash_32(p.recon, p.nr, p.lnt, p.dag, p.red, L, grid, p.block, s);
+    if (p.prec == 16) return launch_dslash_16(p.recon, p.nr, p.lnt, p.dag, p.red, L, grid, p.block, s);
     return hipErrorInvalidValue;
 }
 
@@ -74,6 +74,8 @@ hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashAr
     a.bdim = blk;
     p.nr = dslash_rhs_tile(prec, cfg.rhs_tile, nrhs);
     a.ntiles = (nrhs + p.nr - 1) / p.nr;
+    // links are streamed past the caches when no other block of the launch reads them
+    p.lnt = p.nr == 1 && a.ntiles == 1;
     a.nsp = (int)nbh;
     // interleave right-hand-side tiles into the block order when there are several
     a.rhs_group = (cfg.rhs_group > 1 && a.ntiles > 1) ? (cfg.rhs_group < a.ntiles ? cfg.rhs_group : a.ntiles) : 0;

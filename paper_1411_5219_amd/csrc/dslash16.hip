@@ -3,10 +3,10 @@
 
 namespace lqcd {
 
-hipError_t launch_dslash_16(int recon, int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
+hipError_t launch_dslash_16(int recon, int nr, bool lnt, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                                hipStream_t s)
 {
-    if (recon == 12) return launch_tile<16, 12>(nr, dag, red, L, grid, block, s);
+    if (recon == 12) return launch_tile<16, 12>(nr, lnt, dag, red, L, grid, block, s);
     return hipErrorInvalidValue;
 }
 

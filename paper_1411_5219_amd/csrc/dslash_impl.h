@@ -83,30 +83,235 @@ __device__ __forceinline__ void phase_mul(cplx<R> (&w)[2][3], cplx<R> ph)
         for (int a = 0; a < 3; ++a) w[s][a] = ph * w[s][a];
 }
 
-// One hop for a tile of NR right-hand sides: the link is loaded once and
-// applied to the neighbour spinor of every active right-hand side.
-template <int PREC, int RECON, int MU, bool FWD, int SIG, int NR>
-__device__ __forceinline__ void hop(const char* const (&in)[NR], const bool (&act)[NR], const void* U, int64_t S,
-                                    int64_t nb, int64_t lblk, int64_t lsite, bool cross, bool link_nt,
-                                    cplx<typename SpinorIO<PREC>::R> ph, Spinor<typename SpinorIO<PREC>::R> (&acc)[NR])
+// Neighbour of an output site for hop K = 2 mu + (0 forward, 1 backward):
+// the neighbour's parity-local index, the link block (mu, parity) and the
+// parity-local site the link is stored at, and whether the hop crosses the
+// lattice boundary (and so takes the boundary phase).
+// Parity-local indices fit 32 bits (the library limits V/2 to 21 * 2^20),
+// which keeps them in one register each.
+struct Nbr {
+    int nb, lsite;
+    int lblk;
+    bool cross;
+};
+
+struct SiteGeo {
+    int x, y, z, t, p, Lx, Ly, Lz, Lt;
+    int h, base, hy, hz, ht;
+
+    template <int K>
+    __device__ __forceinline__ Nbr get() const
+    {
+        constexpr int MU = K >> 1;
+        constexpr bool FWD = (K & 1) == 0;
+        Nbr n;
+        if constexpr (MU == 0) {
+            if constexpr (FWD) {
+                n.cross = x == Lx - 1;
+                n.nb = base + ((n.cross ? 0 : x + 1) >> 1);
+            } else {
+                n.cross = x == 0;
+                n.nb = base + ((n.cross ? Lx - 1 : x - 1) >> 1);
+            }
+        } else {
+            const int c = MU == 1 ? y : MU == 2 ? z : t;
+            const int Lc = MU == 1 ? Ly : MU == 2 ? Lz : Lt;
+            const int hc = MU == 1 ? hy : MU == 2 ? hz : ht;
+            if constexpr (FWD) {
+                n.cross = c == Lc - 1;
+                n.nb = n.cross ? h - (Lc - 1) * hc : h + hc;
+            } else {
+                n.cross = c == 0;
+                n.nb = n.cross ? h + (Lc - 1) * hc : h - hc;
+            }
+        }
+        // U_mu(x) for forward hops, U_mu(x - mu) (stored at the neighbour) for backward ones
+        n.lblk = 2 * MU + (FWD ? p : 1 - p);
+        n.lsite = FWD ? h : n.nb;
+        return n;
+    }
+};
+
+// Operands of one hop for a tile of NR right-hand sides: the link (loaded
+// once for the tile) and the neighbour spinor of each right-hand side.
+template <int PREC, int NR>
+struct HopBuf {
+    Link<typename SpinorIO<PREC>::R> L;
+    Spinor<typename SpinorIO<PREC>::R> p[NR];
+};
+
+// LNT selects the streaming (non-temporal) cache policy for the link loads,
+// for launches in which no other block reads the same links.  A tile of one
+// right-hand side is active whenever its block runs, so NR = 1 carries no
+// per-hop branch that would keep the loads of consecutive hops apart.
+template <int PREC, int RECON, int NR, bool LNT>
+__device__ __forceinline__ void hop_load(const char* const (&in)[NR], const bool (&act)[NR], const void* U,
+                                         int64_t S, const Nbr& n, HopBuf<PREC, NR>& b)
 {
-    using R = typename SpinorIO<PREC>::R;
-    Link<R> L;
-    if (link_nt) LinkIO<PREC, RECON>::template load<>(U, S, lblk, lsite, L);
-    else LinkIO<PREC, RECON>::template load<0>(U, S, lblk, lsite, L);
+    if constexpr (LNT) LinkIO<PREC, RECON>::template load<>(U, S, n.lblk, n.lsite, b.L);
+    else LinkIO<PREC, RECON>::template load<0>(U, S, n.lblk, n.lsite, b.L);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        if (!act[r]) continue;
-        Spinor<R> p;
-        SpinorIO<PREC>::load(in[r], S, nb, p);
+        if (NR > 1 && !act[r]) continue;
+        SpinorIO<PREC>::load(in[r], S, n.nb, b.p[r]);
+    }
+}
+
+template <int PREC, int MU, bool FWD, int SIG, int NR>
+__device__ __forceinline__ void hop_apply(const HopBuf<PREC, NR>& b, const bool (&act)[NR], bool cross,
+                                          cplx<typename SpinorIO<PREC>::R> ph,
+                                          Spinor<typename SpinorIO<PREC>::R> (&acc)[NR])
+{
+    using R = typename SpinorIO<PREC>::R;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (NR > 1 && !act[r]) continue;
         cplx<R> h[2][3];
-        project<R, MU, SIG>(p, h);
+        project<R, MU, SIG>(b.p[r], h);
         cplx<R> w[2][3];
-        link_mul<R, !FWD>(L, h, w);
+        link_mul<R, !FWD>(b.L, h, w);
         if (cross) phase_mul(w, FWD ? ph : conj(ph));
         accumulate<R, MU, SIG>(acc[r], w);
     }
 }
+
+// One hop applied right after its loads (pipeline depth 1).  With one
+// right-hand side the neighbour spinor is loaded and projected to its half
+// spinor before the link is loaded, so the full spinor and the link are not
+// live together; a tile of several right-hand sides loads the link first and
+// then each neighbour spinor in turn.
+template <int PREC, int RECON, int MU, bool FWD, int SIG, int NR, bool LNT>
+__device__ __forceinline__ void hop_fused(const char* const (&in)[NR], const bool (&act)[NR], const void* U,
+                                          int64_t S, const Nbr& n, cplx<typename SpinorIO<PREC>::R> ph,
+                                          Spinor<typename SpinorIO<PREC>::R> (&acc)[NR])
+{
+    using R = typename SpinorIO<PREC>::R;
+    if constexpr (NR == 1) {
+        Spinor<R> p;
+        SpinorIO<PREC>::load(in[0], S, n.nb, p);
+        cplx<R> h[2][3];
+        project<R, MU, SIG>(p, h);
+        Link<R> L;
+        if constexpr (LNT) LinkIO<PREC, RECON>::template load<>(U, S, n.lblk, n.lsite, L);
+        else LinkIO<PREC, RECON>::template load<0>(U, S, n.lblk, n.lsite, L);
+        cplx<R> w[2][3];
+        link_mul<R, !FWD>(L, h, w);
+        if (n.cross) phase_mul(w, FWD ? ph : conj(ph));
+        accumulate<R, MU, SIG>(acc[0], w);
+        return;
+    }
+    Link<R> L;
+    if constexpr (LNT) LinkIO<PREC, RECON>::template load<>(U, S, n.lblk, n.lsite, L);
+    else LinkIO<PREC, RECON>::template load<0>(U, S, n.lblk, n.lsite, L);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (NR > 1 && !act[r]) continue;
+        Spinor<R> p;
+        SpinorIO<PREC>::load(in[r], S, n.nb, p);
+        cplx<R> h[2][3];
+        project<R, MU, SIG>(p, h);
+        cplx<R> w[2][3];
+        link_mul<R, !FWD>(L, h, w);
+        if (n.cross) phase_mul(w, FWD ? ph : conj(ph));
+        accumulate<R, MU, SIG>(acc[r], w);
+    }
+}
+
+// Per storage precision: waves per SIMD the register allocation must allow
+// (a block of 256 is one wave on each of a compute unit's four SIMDs), and
+// the depth of the software pipeline over the eight hops (the loads of hop
+// K + depth are issued right after hop K has been applied).  FP64 holds 84
+// registers of operands per hop and already needs about 250 registers for
+// two waves per SIMD with one hop in flight; FP32 and FP16 keep three waves
+// with two hops in flight.
+#ifndef LQCD_WAVES_64
+#define LQCD_WAVES_64 2
+#endif
+#ifndef LQCD_DEPTH_64
+#define LQCD_DEPTH_64 1
+#endif
+#ifndef LQCD_WAVES_32
+#define LQCD_WAVES_32 3
+#endif
+#ifndef LQCD_DEPTH_32
+#define LQCD_DEPTH_32 2
+#endif
+#ifndef LQCD_WAVES_16
+#define LQCD_WAVES_16 3
+#endif
+#ifndef LQCD_DEPTH_16
+#define LQCD_DEPTH_16 2
+#endif
+
+// Tiles of several right-hand sides hold NR accumulators and run at depth 1
+// with the register count the compiler chooses.
+template <int PREC, int NR>
+struct HopTune {
+    static constexpr int waves = NR > 1 ? 1 : PREC == 64 ? LQCD_WAVES_64 : PREC == 32 ? LQCD_WAVES_32 : LQCD_WAVES_16;
+    static constexpr int depth = NR > 1 ? 1 : PREC == 64 ? LQCD_DEPTH_64 : PREC == 32 ? LQCD_DEPTH_32 : LQCD_DEPTH_16;
+    static_assert(depth >= 1 && depth <= 4, "hop pipeline depth 1..4");
+    static_assert(waves >= 1 && waves <= 8, "waves per SIMD 1..8");
+};
+
+template <int PREC, int RECON, int NR, bool LNT, int SF, int D>
+struct HopPipe {
+    using R = typename SpinorIO<PREC>::R;
+    const char* const (&in)[NR];
+    const bool (&act)[NR];
+    const void* U;
+    int64_t S;
+    const SiteGeo& g;
+    const cplx<R> (&ph)[4];
+    Spinor<R> (&acc)[NR];
+    HopBuf<PREC, NR> buf[D > 1 ? D : 1];
+
+    template <int K>
+    __device__ __forceinline__ void load()
+    {
+        hop_load<PREC, RECON, NR, LNT>(in, act, U, S, g.template get<K>(), buf[K % D]);
+    }
+    template <int K>
+    __device__ __forceinline__ void step()
+    {
+        constexpr int MU = K >> 1;
+        constexpr bool FWD = (K & 1) == 0;
+        hop_apply<PREC, MU, FWD, FWD ? SF : -SF, NR>(buf[K % D], act, g.template get<K>().cross, ph[MU], acc);
+        if constexpr (K + D < 8) load<K + D>();
+    }
+    template <int K>
+    __device__ __forceinline__ void fused()
+    {
+        constexpr int MU = K >> 1;
+        constexpr bool FWD = (K & 1) == 0;
+        hop_fused<PREC, RECON, MU, FWD, FWD ? SF : -SF, NR, LNT>(in, act, U, S, g.template get<K>(), ph[MU], acc);
+    }
+    __device__ __forceinline__ void run()
+    {
+        if constexpr (D == 1) {
+            fused<0>();
+            fused<1>();
+            fused<2>();
+            fused<3>();
+            fused<4>();
+            fused<5>();
+            fused<6>();
+            fused<7>();
+            return;
+        }
+        load<0>();
+        if constexpr (D > 1) load<1>();
+        if constexpr (D > 2) load<2>();
+        if constexpr (D > 3) load<3>();
+        step<0>();
+        step<1>();
+        step<2>();
+        step<3>();
+        step<4>();
+        step<5>();
+        step<6>();
+        step<7>();
+    }
+};
 
 template <int RED>
 struct RedN {
@@ -150,7 +355,7 @@ __device__ void block_reduce_tile(double (&v)[NR][N], double* partials, int nb, 
 
 // The work of one block: block bx of nbx along x and by along y of the
 // launch that serves this set of arguments.
-template <int PREC, int RECON, bool DAG, int RED, int NR>
+template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
 __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nbx, int by)
 {
     using R = typename SpinorIO<PREC>::R;
@@ -239,48 +444,19 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc[r].s[s][c] = {R(0), R(0)};
 
-        const cplx<R> ph0 = {R(a.g.ph[0][0]), R(a.g.ph[0][1])};
-        const cplx<R> ph1 = {R(a.g.ph[1][0]), R(a.g.ph[1][1])};
-        const cplx<R> ph2 = {R(a.g.ph[2][0]), R(a.g.ph[2][1])};
-        const cplx<R> ph3 = {R(a.g.ph[3][0]), R(a.g.ph[3][1])};
-        const int q = 1 - p;
-        const bool lnt = a.ntiles == 1;  // links re-read by other tiles are loaded normally
-        // x
-        {
-            const int xp = x == Lx - 1 ? 0 : x + 1;
-            const int xm = x == 0 ? Lx - 1 : x - 1;
-            const int64_t nf = base + (xp >> 1), nbk = base + (xm >> 1);
-            hop<PREC, RECON, 0, true, SF, NR>(in, act, a.U, S, nf, 0 * 2 + p, h, x == Lx - 1, lnt, ph0, acc);
-            hop<PREC, RECON, 0, false, -SF, NR>(in, act, a.U, S, nbk, 0 * 2 + q, nbk, x == 0, lnt, ph0, acc);
-        }
-        // y
-        {
-            const int64_t nf = y == Ly - 1 ? h - (Ly - 1) * hy : h + hy;
-            const int64_t nbk = y == 0 ? h + (Ly - 1) * hy : h - hy;
-            hop<PREC, RECON, 1, true, SF, NR>(in, act, a.U, S, nf, 1 * 2 + p, h, y == Ly - 1, lnt, ph1, acc);
-            hop<PREC, RECON, 1, false, -SF, NR>(in, act, a.U, S, nbk, 1 * 2 + q, nbk, y == 0, lnt, ph1, acc);
-        }
-        // z
-        {
-            const int64_t nf = z == Lz - 1 ? h - (Lz - 1) * hz : h + hz;
-            const int64_t nbk = z == 0 ? h + (Lz - 1) * hz : h - hz;
-            hop<PREC, RECON, 2, true, SF, NR>(in, act, a.U, S, nf, 2 * 2 + p, h, z == Lz - 1, lnt, ph2, acc);
-            hop<PREC, RECON, 2, false, -SF, NR>(in, act, a.U, S, nbk, 2 * 2 + q, nbk, z == 0, lnt, ph2, acc);
-        }
-        // t
-        {
-            const int64_t nf = t == Lt - 1 ? h - (Lt - 1) * ht : h + ht;
-            const int64_t nbk = t == 0 ? h + (Lt - 1) * ht : h - ht;
-            hop<PREC, RECON, 3, true, SF, NR>(in, act, a.U, S, nf, 3 * 2 + p, h, t == Lt - 1, lnt, ph3, acc);
-            hop<PREC, RECON, 3, false, -SF, NR>(in, act, a.U, S, nbk, 3 * 2 + q, nbk, t == 0, lnt, ph3, acc);
-        }
+        const cplx<R> ph[4] = {{R(a.g.ph[0][0]), R(a.g.ph[0][1])},
+                               {R(a.g.ph[1][0]), R(a.g.ph[1][1])},
+                               {R(a.g.ph[2][0]), R(a.g.ph[2][1])},
+                               {R(a.g.ph[3][0]), R(a.g.ph[3][1])}};
+        const SiteGeo geo{x, y, z, t, p, Lx, Ly, Lz, Lt, h, (int)base, (int)hy, (int)hz, (int)ht};
+        HopPipe<PREC, RECON, NR, LNT, SF, HopTune<PREC, NR>::depth> pipe{in, act, a.U, S, geo, ph, acc};
+        pipe.run();
 
         // epilogue per right-hand side: out = add + a * site + c * acc
         const cplx<R> cu = {R(a.c.up[0]), R(a.c.up[1])}, cl = {R(a.c.lo[0]), R(a.c.lo[1])};
-        const cplx<R> au = {R(a.a.up[0]), R(a.a.up[1])}, al = {R(a.a.lo[0]), R(a.a.lo[1])};
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            if (!act[r]) continue;
+            if (NR > 1 && !act[r]) continue;
             const int64_t rr = rhs0 + r;
             Spinor<R> o;
 #pragma unroll
@@ -289,6 +465,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
                 for (int c = 0; c < 3; ++c) o.s[s][c] = (s < 2 ? cu : cl) * acc[r].s[s][c];
             Spinor<R> st;
             if (a.site) {
+                const cplx<R> au = {R(a.a.up[0]), R(a.a.up[1])}, al = {R(a.a.lo[0]), R(a.a.lo[1])};
                 SpinorIO<PREC>::load(static_cast<const char*>(a.site) + rr * a.st_site + poff, S, h, st);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -348,17 +525,19 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
     if (RED != RED_NONE) block_reduce_tile<NR, N>(tot, a.r.partials, nslots, rhs0, a.nrhs, pslot);
 }
 
-template <int PREC, int RECON, bool DAG, int RED, int NR>
-__global__ void __launch_bounds__(256) k_dslash_eo(const DslashArgs a)
+template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopTune<PREC, NR>::waves)))
+k_dslash_eo(const DslashArgs a)
 {
-    dslash_block<PREC, RECON, DAG, RED, NR>(a, blockIdx.x, gridDim.x, blockIdx.y);
+    dslash_block<PREC, RECON, DAG, RED, NR, LNT>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 // Several systems (lattices of different sizes) in one launch: block x of the
 // flattened grid belongs to system s with offs[s] <= x < offs[s + 1]; each
 // system's arguments come from the device table tab.
-template <int PREC, int RECON, bool DAG, int RED, int NR>
-__global__ void __launch_bounds__(256) k_dslash_eo_batch(const DslashArgs* __restrict__ tab,
+template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopTune<PREC, NR>::waves)))
+k_dslash_eo_batch(const DslashArgs* __restrict__ tab,
                                                         const int* __restrict__ offs, int nsys)
 {
     const int x = blockIdx.x;
@@ -368,45 +547,51 @@ __global__ void __launch_bounds__(256) k_dslash_eo_batch(const DslashArgs* __res
     // the system's own grid are padding
     const int bx = x - offs[s];
     if (bx >= tab[s].gx) return;  // (a tile index past ntiles finds no active right-hand side)
-    dslash_block<PREC, RECON, DAG, RED, NR>(tab[s], bx, tab[s].gx, blockIdx.y);
+    dslash_block<PREC, RECON, DAG, RED, NR, LNT>(tab[s], bx, tab[s].gx, blockIdx.y);
 }
 
-template <int PREC, int RECON, bool DAG, int RED, int NR>
+template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
 static hipError_t launch_one(const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (L.tab) hipLaunchKernelGGL((k_dslash_eo_batch<PREC, RECON, DAG, RED, NR>), grid, block, 0, s, L.tab, L.offs, L.nsys);
-    else hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED, NR>), grid, block, 0, s, *L.a);
+    if (L.tab)
+        hipLaunchKernelGGL((k_dslash_eo_batch<PREC, RECON, DAG, RED, NR, LNT>), grid, block, 0, s, L.tab, L.offs, L.nsys);
+    else hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED, NR, LNT>), grid, block, 0, s, *L.a);
     return hipGetLastError();
 }
 
-template <int PREC, int RECON, bool DAG, int NR>
+template <int PREC, int RECON, bool DAG, int NR, bool LNT>
 static hipError_t launch_red(int red, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (red) {
-    case RED_NONE: return launch_one<PREC, RECON, DAG, RED_NONE, NR>(L, grid, block, s);
-    case RED_NORM: return launch_one<PREC, RECON, DAG, RED_NORM, NR>(L, grid, block, s);
-    case RED_NORM_DS: return launch_one<PREC, RECON, DAG, RED_NORM_DS, NR>(L, grid, block, s);
-    case RED_DOT_AUX: return launch_one<PREC, RECON, DAG, RED_DOT_AUX, NR>(L, grid, block, s);
+    case RED_NONE: return launch_one<PREC, RECON, DAG, RED_NONE, NR, LNT>(L, grid, block, s);
+    case RED_NORM: return launch_one<PREC, RECON, DAG, RED_NORM, NR, LNT>(L, grid, block, s);
+    case RED_NORM_DS: return launch_one<PREC, RECON, DAG, RED_NORM_DS, NR, LNT>(L, grid, block, s);
+    case RED_DOT_AUX: return launch_one<PREC, RECON, DAG, RED_DOT_AUX, NR, LNT>(L, grid, block, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int PREC, int RECON, int NR>
+template <int PREC, int RECON, int NR, bool LNT>
 static hipError_t launch_dag(bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    return dag ? launch_red<PREC, RECON, true, NR>(red, L, grid, block, s)
-               : launch_red<PREC, RECON, false, NR>(red, L, grid, block, s);
+    return dag ? launch_red<PREC, RECON, true, NR, LNT>(red, L, grid, block, s)
+               : launch_red<PREC, RECON, false, NR, LNT>(red, L, grid, block, s);
 }
 
 // Right-hand-side tiles compiled per storage: 1, 2 and 4 for FP32 and FP16
-// (the multi-RHS inner solves), 1 and 2 for FP64.
+// (the multi-RHS inner solves), 1 and 2 for FP64.  Streaming link loads are
+// compiled for the one-tile case only: with several tiles (or a tile of
+// several right-hand sides sharing the loaded link) links stay cached.
 template <int PREC, int RECON>
-inline hipError_t launch_tile(int nr, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+inline hipError_t launch_tile(int nr, bool lnt, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
+                              hipStream_t s)
 {
-    if (nr == 1) return launch_dag<PREC, RECON, 1>(dag, red, L, grid, block, s);
-    if (nr == 2) return launch_dag<PREC, RECON, 2>(dag, red, L, grid, block, s);
+    if (nr == 1)
+        return lnt ? launch_dag<PREC, RECON, 1, true>(dag, red, L, grid, block, s)
+                   : launch_dag<PREC, RECON, 1, false>(dag, red, L, grid, block, s);
+    if (nr == 2) return launch_dag<PREC, RECON, 2, false>(dag, red, L, grid, block, s);
     if constexpr (PREC != 64)
-        if (nr == 4) return launch_dag<PREC, RECON, 4>(dag, red, L, grid, block, s);
+        if (nr == 4) return launch_dag<PREC, RECON, 4, false>(dag, red, L, grid, block, s);
     return hipErrorInvalidValue;
 }
 

@@ -172,6 +172,7 @@ struct DslashPlan {
     dim3 grid, block;
     int prec, recon, nr, red;
     bool dag;
+    bool lnt;   // streaming link loads (one right-hand-side tile of one)
     int nfin;   // values per finalize (0: no reduction)
     int slots;  // partial slots per right-hand side
 };
