@@ -2,12 +2,17 @@
 
     python -m paper_1411_5219_amd.profiling stats  <results.db> [name-filter]
     python -m paper_1411_5219_amd.profiling counters <results.db> [name-filter]
+    python -m paper_1411_5219_amd.profiling bursts <results.db> [--min-len N]
     python -m paper_1411_5219_amd.profiling traffic --fetch <db> --write <db> [--kernel K] [--copy-bytes N]
 
 ``stats`` lists calls, total and mean duration per kernel, and for each
 kernel also the mean over dispatches that did work: solver kernels whose
 control block says "converged" return at once (a few microseconds), and
 those predicated no-op launches are counted separately.
+
+``bursts`` picks out runs of at least N back-to-back dispatches of one
+kernel with one grid (the Dslash bursts that bench.py times with HIP
+events) and gives their mean duration per kernel.
 
 ``traffic`` turns FETCH_SIZE / WRITE_SIZE passes into bytes per dispatch of a
 kernel, each scaled by what the same counter reads for the plain copy of
@@ -62,6 +67,28 @@ def kernel_stats(db, name_filter="", busy_us=10.0):
     return out
 
 
+def bursts(db, min_len=20):
+    rows = _rows(db, "select name, grid_x, grid_y, workgroup_x, duration from kernels order by start")
+    runs, cur = [], []
+    for r in rows:
+        if cur and (r[0], r[1], r[2], r[3]) != cur[-1][:4]:
+            runs.append(cur)
+            cur = []
+        cur.append(r)
+    if cur:
+        runs.append(cur)
+    out = defaultdict(list)
+    for run in runs:
+        if len(run) >= min_len:
+            out[(run[0][0], run[0][1] // run[0][3], run[0][2], run[0][3])].append([x[4] / 1e3 for x in run])
+    res = []
+    for (name, blocks, gy, wx), rs in out.items():
+        du = [x for r in rs for x in r]
+        res.append({"name": name, "blocks": blocks, "grid_y": gy, "block": wx, "bursts": len(rs), "calls": len(du),
+                    "mean_us": sum(du) / len(du), "median_us": statistics.median(du)})
+    return res
+
+
 def counters(db, name_filter=""):
     d = defaultdict(lambda: defaultdict(list))
     q = "select dispatch_id, kernel_name, counter_name, value from counters_collection order by dispatch_id"
@@ -98,10 +125,13 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("db")
     c.add_argument("filter", nargs="?", default="")
+    b = sub.add_parser("bursts")
+    b.add_argument("db")
+    b.add_argument("--min-len", type=int, default=20)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
-    t.add_argument("--kernel", default="k_dslash_eo<64, 18, false, 0, 1>")
+    t.add_argument("--kernel", default="k_dslash_eo<64, 18, false, 0, 1, true>")
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -109,6 +139,11 @@ def main(argv=None):
         for r in kernel_stats(a.db, a.filter):
             print(f"{r['calls']:>6} {r['total_us']:>12.1f} {r['mean_us']:>10.2f} {r['busy_calls']:>10} "
                   f"{r['busy_mean_us']:>12.2f}  {r['name']}")
+    elif a.cmd == "bursts":
+        print(f"{'bursts':>6} {'calls':>6} {'mean_us':>9} {'median_us':>9} {'blocks':>7} {'block':>5}  kernel")
+        for r in bursts(a.db, a.min_len):
+            print(f"{r['bursts']:>6} {r['calls']:>6} {r['mean_us']:>9.2f} {r['median_us']:>9.2f} {r['blocks']:>7} "
+                  f"{r['block']:>5}  {r['name']}")
     elif a.cmd == "counters":
         for name, cs in counters(a.db, a.filter).items():
             for cn, vals in cs.items():
