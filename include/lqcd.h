@@ -132,7 +132,10 @@ typedef struct {
  *   order   Dslash only.  0: blocks walk the sites in memory order;
  *           1: a block covers whole x-rows at one (z, t) and blocks run
  *           t fastest, then z, so neighbour spinors are reused from the
- *           XCD's L2 cache.
+ *           XCD's L2 cache; k in 2..64: the same row blocks in z-slabs of
+ *           T planes (T the largest divisor of Lz not above k), z fastest
+ *           within a slab, then t, then the slab, which brings the z
+ *           neighbours closer in the block order.
  *   rhs_tile Dslash only: right-hand sides one work-item applies each link
  *           to (1, 2 or 4; FP64 at most 2), so links are loaded once per tile.
  *   rhs_group Dslash only: 0, or G in 2..16: with several right-hand-side

@@ -1,4 +1,6 @@
-"""Compile the oracle's C source into ``oracle/liboracle.so`` (gcc, OpenMP).
+"""Compile the oracle's C sources into shared libraries (gcc, OpenMP):
+``wilson_oracle.c`` -> ``oracle/liboracle.so`` and ``staggered_oracle.c`` ->
+``oracle/libstaggered_oracle.so``.
 
 Test infrastructure only: building the checker is not using it.
 """
@@ -11,6 +13,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "wilson_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+STAG_SRC = os.path.join(HERE, "staggered_oracle.c")
+STAG_LIB = os.path.join(HERE, "libstaggered_oracle.so")
 
 
 def build_oracle(force: bool = False, src: str = SRC, out: str = LIB) -> str:
@@ -23,5 +27,9 @@ def build_oracle(force: bool = False, src: str = SRC, out: str = LIB) -> str:
     return out
 
 
+def build_all(force: bool = False) -> list:
+    return [build_oracle(force), build_oracle(force, STAG_SRC, STAG_LIB)]
+
+
 if __name__ == "__main__":
-    print(build_oracle(force=True))
+    print(build_all(force=True))

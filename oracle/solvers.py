@@ -199,3 +199,149 @@ def solve(U, b, L, theta, kappa, mu, tol, maxiter=100000, method="cgnr", eo=True
     nbh = np.sqrt(_nrm2(bhat))
     info.eo_resid = float(np.sqrt(_nrm2(r_eo)) / nbh) if nbh > 0 else 0.0
     return x, info
+
+
+# ---------------------------------------------------------------------------
+# Staggered fermions: CG on the even-site normal operator, multi-shift CG
+
+
+def cg(A, b, tol, maxiter, stop_norm=None, residual=None, x0=None):
+    """Conjugate gradient (Hestenes-Stiefel) on a Hermitian positive definite A.
+
+    Stops when ||b - A x|| <= tol * stop_norm on the recursion, then confirms
+    with ``residual(x)`` (a relative true residual) and restarts from the
+    recomputed residual if that misses ``tol``.
+    """
+    info = SolveInfo()
+    sn = float(np.sqrt(_nrm2(b))) if stop_norm is None else float(stop_norm)
+    if residual is None:
+        residual = lambda x: float(np.sqrt(_nrm2(b - A(x)))) / sn  # noqa: E731
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    if sn == 0.0:
+        info.true_resid = 0.0
+        return x, info
+    if not np.all(np.isfinite(b)):
+        info.status = ENONFINITE
+        return x, info
+    r = b - A(x)
+    p = r.copy()
+    rr = _nrm2(r)
+    k = 0
+    while True:
+        if np.sqrt(rr) <= tol * sn:
+            tr = residual(x)
+            if tr <= tol:
+                info.true_resid = tr
+                break
+            info.restarts += 1
+            r = b - A(x)
+            p = r.copy()
+            rr = _nrm2(r)
+        if k >= maxiter:
+            info.status = ENOCONV
+            info.true_resid = residual(x)
+            break
+        w = A(p)
+        pw = _dot(p, w).real
+        alpha = rr / pw
+        x = x + alpha * p
+        r = r - alpha * w
+        rr_new = _nrm2(r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        k += 1
+        if not np.isfinite(rr):
+            info.status = ENONFINITE
+            break
+    info.iters = k
+    return x, info
+
+
+def multishift_cg(A, b, shifts, tol, maxiter):
+    """Solve (A + s_i) x_i = b for every shift s_i at once (A Hermitian
+    positive definite, every A + s_i too) with one Krylov space.
+
+    The base system is the smallest shift s0; the residuals of the other
+    systems stay collinear with the base residual, r_i = zeta_i r, and the
+    CG three-term recurrence gives (shift d = s_i - s0, CG coefficients
+    alpha_k, beta_k of the base system, zeta_{-1} = zeta_0 = 1,
+    alpha_{-1} = 1, beta_{-1} = 0):
+
+      zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1}
+                   / (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 + d alpha_k))
+      alpha^i_k = alpha_k zeta_{k+1} / zeta_k,   beta^i_k = beta_k (zeta_{k+1} / zeta_k)^2
+      x_i += alpha^i_k p_i,   p_i = zeta_{k+1} r_{k+1} + beta^i_k p_i
+
+    (Jegerlehner, "Krylov space solvers for shifted linear systems", 1996;
+    written here with the shift added to A).  System i is done when
+    |zeta_i| ||r|| <= tol ||b||; its x_i and p_i are then frozen.
+    Returns the solutions and per-shift (iterations, true relative residual).
+    """
+    shifts = [float(s) for s in shifts]
+    n = len(shifts)
+    base = int(np.argmin(shifts))
+    s0 = shifts[base]
+    bn = float(np.sqrt(_nrm2(b)))
+    xs = [np.zeros_like(b) for _ in range(n)]
+    if bn == 0.0:
+        return xs, [(0, 0.0)] * n
+    r = b.copy()
+    ps = [b.copy() for _ in range(n)]
+    rr = _nrm2(r)
+    zeta_prev = np.ones(n)
+    zeta = np.ones(n)
+    alpha_prev, beta_prev = 1.0, 0.0
+    active = np.ones(n, dtype=bool)
+    iters = np.zeros(n, dtype=int)
+    k = 0
+    while active.any() and k < maxiter:
+        w = A(ps[base]) + s0 * ps[base]
+        alpha = rr / _dot(ps[base], w).real
+        zeta_new = np.ones(n)
+        for i in range(n):
+            if not active[i]:
+                continue
+            d = shifts[i] - s0
+            den = alpha * beta_prev * (zeta_prev[i] - zeta[i]) + zeta_prev[i] * alpha_prev * (1.0 + d * alpha)
+            zeta_new[i] = zeta[i] * zeta_prev[i] * alpha_prev / den
+            xs[i] = xs[i] + (alpha * zeta_new[i] / zeta[i]) * ps[i]
+        r = r - alpha * w
+        rr_new = _nrm2(r)
+        beta = rr_new / rr
+        k += 1
+        for i in range(n):
+            if not active[i]:
+                continue
+            bi = beta * (zeta_new[i] / zeta[i]) ** 2
+            ps[i] = zeta_new[i] * r + bi * ps[i]
+            iters[i] = k
+            if abs(zeta_new[i]) * np.sqrt(rr_new) <= tol * bn:
+                active[i] = False
+        zeta_prev, zeta = zeta, zeta_new
+        alpha_prev, beta_prev = alpha, beta
+        rr = rr_new
+    out = []
+    for i in range(n):
+        ri = b - A(xs[i]) - shifts[i] * xs[i]
+        out.append((int(iters[i]), float(np.sqrt(_nrm2(ri)) / bn)))
+    return xs, out
+
+
+def stag_solve(U, b, L, theta, mass, tol, maxiter=100000):
+    """x = M^-1 b for M = m + D (staggered): CG on N = m^2 - D_eo D_oe for
+    x_e, then x_o = (b_o - D_oe x_e) / m.  The recursion residual r_e of N
+    relates to the full one by ||b - M x|| = ||r_e|| / m, so CG stops at
+    ||r_e|| <= tol * m * ||b||."""
+    from . import staggered as S
+
+    bn = float(np.sqrt(_nrm2(b)))
+    rhs = S.eo_source(U, b, L, theta, mass)
+    A = lambda v: S.normal_e(U, v, L, theta, mass)  # noqa: E731
+
+    def res(x_e):
+        return S.true_residual(U, S.eo_reconstruct(U, x_e, b, L, theta, mass), b, L, theta, mass)
+
+    x_e, info = cg(A, rhs, tol, maxiter, stop_norm=mass * bn, residual=res)
+    x = S.eo_reconstruct(U, x_e, b, L, theta, mass)
+    info.true_resid = S.true_residual(U, x, b, L, theta, mass)
+    return x, info

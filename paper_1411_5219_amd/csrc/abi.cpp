@@ -1144,8 +1144,8 @@ int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
     if (cfg->block < 64 || cfg->block > 256 || cfg->block % 64)
         return set_error(LQCD_EINVAL, "block %d not in {64, 128, 192, 256}", cfg->block);
     if (cfg->swizzle != 0 && cfg->swizzle != 1) return set_error(LQCD_EINVAL, "swizzle must be 0 or 1");
-    if (cfg->order != 0 && cfg->order != 1) return set_error(LQCD_EINVAL, "order must be 0 or 1");
-    if (cfg->order == 1 && kernel != LQCD_KERNEL_DSLASH) return set_error(LQCD_EINVAL, "order 1 applies to the Dslash only");
+    if (cfg->order < 0 || cfg->order > 64) return set_error(LQCD_EINVAL, "order must be in 0..64");
+    if (cfg->order >= 1 && kernel != LQCD_KERNEL_DSLASH) return set_error(LQCD_EINVAL, "order >= 1 applies to the Dslash only");
     if (cfg->rhs_tile != 1 && cfg->rhs_tile != 2 && cfg->rhs_tile != 4)
         return set_error(LQCD_EINVAL, "rhs_tile %d not in {1, 2, 4}", cfg->rhs_tile);
     if (cfg->rhs_group != 0 && (cfg->rhs_group < 2 || cfg->rhs_group > 16))

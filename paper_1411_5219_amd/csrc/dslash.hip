@@ -50,8 +50,9 @@ hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashAr
     unsigned nbh = (unsigned)((a.g.Vh + blk - 1) / blk);
     a.rows = 0;
     a.nyc = 0;
+    a.ztile = 1;
     const int Lxh = a.g.Lxh, Ly = a.g.L[1];
-    if (cfg.order == 1 && Lxh <= 256) {
+    if (cfg.order >= 1 && Lxh <= 256) {
         // R whole x-rows per block: the largest divisor of Ly with R*Lxh at
         // most the requested block size (at least one row); the block is
         // rounded up to whole wavefronts.
@@ -67,6 +68,9 @@ hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashAr
         if (4 * R * Lxh >= 3 * B) {
             a.rows = R;
             a.nyc = (Ly + R - 1) / R;
+            // z-slabs: the largest divisor of Lz not above the requested depth
+            for (int d = 1; d <= a.g.L[2] && d <= cfg.order; ++d)
+                if (a.g.L[2] % d == 0) a.ztile = d;
             blk = B;
             nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
         }

@@ -111,9 +111,13 @@ struct DslashArgs {
     // memory order.  rows = R > 0: a block covers R whole x-rows at one
     // (z, t) (a contiguous chunk of sites) and blocks run t fastest, then z,
     // then the y-chunk, so the t and z neighbours a block reads were loaded
-    // by blocks that ran just before it on the same XCD.
+    // by blocks that ran just before it on the same XCD.  ztile = T > 1
+    // (T divides Lz): z-slabs of T planes, z fastest within a slab, then t,
+    // then the slab, then the y-chunk; a spinor's z and t neighbours are then
+    // at most T blocks away except on slab faces.
     int rows;
     int nyc;                // y-chunks of R rows (rows > 0)
+    int ztile;              // z-planes per slab (rows > 0; 1: t fastest)
     int nrhs;               // right-hand sides (set by the launcher)
     // Right-hand-side tiles in the block order.  rhs_group = 0: tile index
     // is blockIdx.y.  rhs_group = G > 0: grid.y = 1 and the tiles are
@@ -131,7 +135,7 @@ struct DslashArgs {
 struct Launch {
     int block = 128;
     int swizzle = 1;
-    int order = 0;     // 0: memory order, 1: t-fastest tiles of whole x-rows (Dslash)
+    int order = 0;     // 0: memory order, 1: t-fastest tiles of whole x-rows, k > 1: z-slabs of k planes (Dslash)
     int rhs_tile = 4;  // right-hand sides one Dslash work-item handles (links loaded once)
     int rhs_group = 4; // right-hand-side tiles interleaved per spatial block (0: grid.y)
 };

@@ -109,3 +109,24 @@ def test_batch_workspace_query_validates():
     with pytest.raises(L.LqcdError) as e:
         L.lqcd_workspace_bytes_batch(g * 9, o * 9, p)
     assert e.value.code == L.EINVAL
+
+
+def test_launch_validation():
+    """Launch shapes outside the documented ranges are refused before any
+    device work; the z-slab orders (2..64) apply to the Dslash only."""
+    from paper_1411_5219_amd import lqcd as L
+    for kernel, prec, cfg in [(L.KERNEL_DSLASH, 64, dict(block=96)), (L.KERNEL_DSLASH, 64, dict(block=256, order=65)),
+                              (L.KERNEL_DSLASH, 64, dict(block=256, order=-1)),
+                              (L.KERNEL_BLAS, 64, dict(block=256, order=2)),
+                              (L.KERNEL_DSLASH, 64, dict(block=256, rhs_tile=3)),
+                              (L.KERNEL_DSLASH, 64, dict(block=256, rhs_group=17))]:
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_set_launch(kernel, prec, **cfg)
+        assert e.value.code == L.EINVAL, cfg
+    saved = L.lqcd_get_launch(L.KERNEL_DSLASH, 32)
+    try:
+        L.lqcd_set_launch(L.KERNEL_DSLASH, 32, 256, 1, 6, 1, 4)
+        assert L.lqcd_get_launch(L.KERNEL_DSLASH, 32)["order"] == 6
+    finally:
+        L.lqcd_set_launch(L.KERNEL_DSLASH, 32, **saved)
+

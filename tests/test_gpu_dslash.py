@@ -31,7 +31,8 @@ LATTICES = [
 # launch configurations every full-M case is checked in: memory order with
 # and without the XCD remap, and row tiles in t-fastest order
 LAUNCHES = [dict(block=128, swizzle=1, order=0), dict(block=64, swizzle=0, order=0),
-            dict(block=192, swizzle=1, order=1), dict(block=64, swizzle=0, order=1)]
+            dict(block=192, swizzle=1, order=1), dict(block=64, swizzle=0, order=1),
+            dict(block=256, swizzle=1, order=4), dict(block=128, swizzle=0, order=3)]
 
 
 @pytest.fixture(scope="module")
@@ -217,7 +218,7 @@ def test_autotune_configs_agree(mods):
     saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64)
     try:
         outs = []
-        for order in (0, 1):
+        for order in (0, 1, 2, 5):
             for sw in (0, 1):
                 for blk in (64, 128, 192, 256):
                     lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, blk, sw, order)
