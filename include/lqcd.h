@@ -66,8 +66,14 @@ enum {
 
 enum { LQCD_PREC_64 = 64, LQCD_PREC_32 = 32, LQCD_PREC_16 = 16 };
 enum { LQCD_RECON_18 = 18, LQCD_RECON_12 = 12 };
-enum { LQCD_OP_HOP = 0, LQCD_OP_SCHUR = 1 };
-enum { LQCD_FIELD_SPINOR_PARITY = 0, LQCD_FIELD_SPINOR_FULL = 1, LQCD_FIELD_GAUGE = 2 };
+enum { LQCD_OP_HOP = 0, LQCD_OP_SCHUR = 1, LQCD_OP_NORMAL = 2 };
+enum {
+    LQCD_FIELD_SPINOR_PARITY = 0,
+    LQCD_FIELD_SPINOR_FULL = 1,
+    LQCD_FIELD_GAUGE = 2,
+    LQCD_FIELD_COLOUR_PARITY = 3,  /* staggered colour vector, one parity */
+    LQCD_FIELD_COLOUR_FULL = 4     /* staggered colour vector, full lattice */
+};
 
 /* Lattice extents (x, y, z, t; all even, >= 2) and boundary phases:
  * psi(x + L_mu mu-hat) = exp(i theta_mu) psi(x). */
@@ -236,6 +242,81 @@ LQCD_API int lqcd_workspace_bytes_batch(int32_t nsys, const lqcd_geom* geoms, co
 LQCD_API int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,
                             const void* const* b, void* const* x, const lqcd_solve_params* params,
                             lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Staggered (Kogut-Susskind) fermions.
+ *
+ * The paper (section 3) adds the standard staggered formulation and
+ * (section 1) counts its derivative part D_KS at 570 flops and 1584 bytes
+ * per site.  Operator (one colour vector, 3 complex, per site; the same
+ * gauge field, layout and boundary phases as the Wilson operator):
+ *
+ *   (D chi)(x) = 1/2 sum_mu eta_mu(x) [ f+ U_mu(x) chi(x + mu) - f- U_mu(x - mu)^+ chi(x - mu) ]
+ *   eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z)
+ *   M = m + D,  M^+ = m - D  (D is anti-Hermitian)
+ *
+ * Colour fields: canonical (V, 3) complex128 per right-hand side, site index
+ * x + Lx (y + Ly (z + Lz t)); internal layout per parity (FP64: 3 planes of
+ * double2; FP32: a plane of float4 and one of float2; FP16: one plane of 16
+ * bytes holding 6 scaled halves and the FP32 scale); a full-lattice field is
+ * the even parity followed by the odd one.  Sizes: lqcd_field_bytes with
+ * LQCD_FIELD_COLOUR_PARITY / LQCD_FIELD_COLOUR_FULL. */
+typedef struct {
+    double mass;      /* bare mass m (lattice units); the solvers need m > 0 */
+    int32_t prec;     /* 64, 32 or 16 (FP16 storage, FP32 arithmetic) */
+    int32_t recon;    /* 18 or 12 (FP16: 12) */
+} lqcd_stag_op;
+
+/* Canonical <-> internal colour fields (nrhs stacked full-lattice fields). */
+LQCD_API int lqcd_pack_colour(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* chi_canonical, void* out,
+                              void* stream);
+LQCD_API int lqcd_unpack_colour(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* in,
+                                void* chi_canonical, void* stream);
+
+/* out = M in (dagger = 0) or M^+ in (dagger = 1) on the full lattice, nrhs
+ * stacked full-lattice colour fields at op->prec; in and out must not
+ * overlap.  Enqueues only. */
+LQCD_API int stag_apply(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out,
+                        int32_t dagger, int32_t nrhs, void* stream);
+
+/* Even-odd pieces on parity colour fields (nrhs stacked):
+ *   op = LQCD_OP_HOP    : out = D_{p,1-p} in onto parity p = out_parity;
+ *   op = LQCD_OP_NORMAL : out = (m^2 - D_eo D_oe) in on even sites, the even
+ *                         block of M^+ M (Hermitian positive definite for
+ *                         m > 0); out_parity must be 0; ws must hold
+ *                         nrhs odd parity fields at op->prec.
+ * in and out must not overlap. */
+LQCD_API int stag_eo_apply(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out,
+                           int32_t out_parity, int32_t op_kind, int32_t nrhs, void* ws, void* stream);
+
+/* Device workspace (bytes) of stag_cg_solve (nshift = 0) or of
+ * stag_multishift_solve with nshift shifts (1..32). */
+LQCD_API int lqcd_workspace_bytes_stag(const lqcd_geom* geom, const lqcd_stag_op* op, int32_t nshift, size_t* bytes);
+
+/* Solve M x = b for one full-lattice FP64 colour field b (U FP64 at
+ * op->recon, op->prec = 64, op->mass > 0): CG on the even-site normal
+ * operator N = m^2 - D_eo D_oe with right-hand side m b_e - D_eo b_o, then
+ * x_o = (b_o - D_oe x_e) / m.  The CG residual r_e of N gives the full one,
+ * ||b - M x|| = ||r_e|| / m, so CG stops at ||r_e|| <= tol m ||b||; the FP64
+ * true residual of the full system is then checked and CG restarts from the
+ * current x if it misses.  params: eo = 1, inner_prec = 64, nrhs = 1 (other
+ * fields as for cg_solve).  x is overwritten.  info: one entry. */
+LQCD_API int stag_cg_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* b, void* x,
+                           const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Multi-shift CG (the inversions a rational approximation needs): solve
+ * (N + shifts[i]) x_i = b for every shift at once, b one even-parity FP64
+ * colour field, x nshift even-parity fields stacked (x_i at byte offset
+ * i * lqcd_field_bytes(COLOUR_PARITY, 64)), shifts >= 0 in any order (1..32
+ * of them).  One Krylov space, the smallest shift as the base system; each
+ * system stops on its own when ||b - (N + shift_i) x_i|| <= tol ||b|| by the
+ * recursion, and info[i].true_resid reports the FP64 true residual
+ * recomputed at the end.  params: tol, maxiter, use_graph, check_every as
+ * for cg_solve; eo = 1, inner_prec = 64, nrhs = 1. */
+LQCD_API int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* b,
+                                   void* x, const double* shifts, int32_t nshift, const lqcd_solve_params* params,
+                                   lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -914,7 +914,8 @@ bool same_kernel(const Step& a, const Step& b)
 {
     if (a.kind != b.kind) return false;
     if (a.kind == STEP_DSLASH)
-        return a.d.prec == b.d.prec && a.d.recon == b.d.recon && a.d.nr == b.d.nr && a.d.lnt == b.d.lnt && a.d.red == b.d.red &&
+        return a.d.kind == b.d.kind && a.d.prec == b.d.prec && a.d.recon == b.d.recon && a.d.nr == b.d.nr &&
+               a.d.lnt == b.d.lnt && a.d.red == b.d.red &&
                a.d.dag == b.d.dag && a.d.a.nrhs == b.d.a.nrhs && a.d.grid.y == b.d.grid.y;
     if (a.kind == STEP_BLAS)
         return a.b.prec == b.b.prec && a.b.op == b.b.op && a.b.nrhs == b.b.nrhs && a.b.block.x == b.b.block.x;
@@ -1081,6 +1082,213 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
     return worst;
 }
 
+
+// ---------------------------------------------------------------------------
+// Staggered fermions: the operator compositions and the (multi-shift) CG.
+
+int check_stag_op(const lqcd_stag_op* op)
+{
+    if (!op) return set_error(LQCD_EINVAL, "op is NULL");
+    int rc = check_prec(op->prec, op->recon);
+    if (rc) return rc;
+    if (!std::isfinite(op->mass)) return set_error(LQCD_EINVAL, "mass must be finite");
+    return LQCD_OK;
+}
+
+int64_t colour_bytes(const Geom& g, int prec) { return colour_parity_bytes(prec, g.S); }
+
+// The staggered operator bound to a gauge field, a precision and a stream.
+// hop() is the even-odd kernel with c = 1/2 giving D; the compositions:
+//   D_{p,1-p} in        : hop(p, in, out, c = 1/2)
+//   (N + s) in, even    : t = D_oe in; out = (m^2 + s) in - D_eo t
+//   M in, full lattice  : out = m in + D in   (M^+ : m in - D in)
+struct StagOp {
+    Geom g;
+    int prec = 64, recon = 18;
+    const void* U = nullptr;
+    double mass = 0;
+    int nrhs = 1;
+    int64_t pb = 0;  // bytes of one parity colour field at prec
+    hipStream_t s = nullptr;
+    RedScratch rs;
+    Launch dcfg, bcfg;
+
+    void tune() { dcfg = launch_for(LQCD_KERNEL_DSLASH, prec); bcfg = launch_for(LQCD_KERNEL_BLAS, prec); }
+
+    DslashArgs base(Ctl* ctl) const
+    {
+        DslashArgs a{};
+        a.g = g;
+        a.U = U;
+        a.st_in = a.st_out = a.st_site = a.st_add = a.st_aux = pb;
+        a.par_bytes = pb;
+        a.r.partials = rs.partials;
+        a.r.capacity = rs.capacity;
+        a.ctl = ctl;
+        return a;
+    }
+
+    // out(parity p) = add + a * site + c * sum_mu eta_mu [U in(x+mu) - U^+ in(x-mu)]
+    hipError_t hop(int p, const void* in, void* out, double c, const void* site, double a, const void* add, int red,
+                   int fin, int pred, Ctl* ctl) const
+    {
+        DslashArgs d = base(ctl);
+        d.parity = p;
+        d.pred = pred;
+        d.in = in;
+        d.out = out;
+        d.site = site;
+        d.add = add;
+        d.a = coef_real(a);
+        d.c = coef_real(c);
+        d.r.fin = fin;
+        return launch_stag(prec, recon, red, d, nrhs, dcfg, s);
+    }
+
+    // out = add + sgn (N + shift) in on even fields; tmp: an odd field.
+    hipError_t normal(const void* in, void* out, void* tmp, double shift, double sgn, const void* add, int red, int fin,
+                      int pred, Ctl* ctl) const
+    {
+        hipError_t e = hop(1, in, tmp, 0.5, nullptr, 0.0, nullptr, RED_NONE, FIN_STORE, pred, ctl);
+        if (e != hipSuccess) return e;
+        return hop(0, tmp, out, -0.5 * sgn, in, sgn * (mass * mass + shift), add, red, fin, pred, ctl);
+    }
+
+    // out = add + sgn M in (M^+ for dag) on full-lattice fields, one launch.
+    hipError_t full_M(const void* in, void* out, bool dag, double sgn, const void* add, int red, int fin, int pred,
+                      Ctl* ctl) const
+    {
+        DslashArgs d = base(ctl);
+        d.full = 1;
+        d.pred = pred;
+        d.in = in;
+        d.site = in;
+        d.out = out;
+        d.add = add;
+        d.st_in = d.st_site = d.st_out = d.st_add = 2 * pb;
+        d.a = coef_real(sgn * mass);
+        d.c = coef_real((dag ? -0.5 : 0.5) * sgn);
+        d.r.fin = fin;
+        return launch_stag(prec, recon, red, d, nrhs, dcfg, s);
+    }
+
+    hipError_t blas(int op, int n, int pred, int fin, Ctl* ctl, void* x, int64_t st_x, void* y = nullptr,
+                    int64_t st_y = 0, void* z = nullptr, int64_t st_z = 0, void* w = nullptr, int64_t st_w = 0,
+                    int nsub = 1) const
+    {
+        BlasArgs a{};
+        a.kind = KIND_COLOUR;
+        a.Vh = g.Vh;
+        a.S = g.S;
+        a.nsub = nsub;
+        a.sub_stride = pb;
+        a.pred = pred;
+        a.x = x;
+        a.y = y;
+        a.z = z;
+        a.w = w;
+        a.st_x = st_x;
+        a.st_y = st_y;
+        a.st_z = st_z;
+        a.st_w = st_w;
+        a.r.partials = rs.partials;
+        a.r.capacity = rs.capacity;
+        a.r.fin = fin;
+        a.ctl = ctl;
+        return launch_blas(prec, op, a, n, bcfg, s);
+    }
+};
+
+// Workspace of a staggered solve: reductions (one right-hand side), control
+// blocks for up to kMaxShifts systems, then the vectors.
+struct StagPlan {
+    RedScratch rs;
+    void* r = nullptr;     // even: residual
+    void* w = nullptr;     // even: (N + s0) p
+    void* t = nullptr;     // odd scratch
+    void* bhat = nullptr;  // even: m b_e - D_eo b_o (CG)
+    void* p = nullptr;     // nshift even fields (multi-shift) or one (CG)
+    size_t bytes = 0;
+};
+
+void plan_stag(const Geom& g, int nshift, void* ws, StagPlan* sp)
+{
+    Arena ar{static_cast<char*>(ws), 0, 0};
+    const int64_t nblk = max_blocks(g);
+    sp->rs.capacity = (int)nblk;
+    sp->rs.partials = static_cast<double*>(ar.take(sizeof(double) * 3 * nblk));
+    sp->rs.ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxShifts));
+    const size_t pb = (size_t)colour_bytes(g, 64);
+    sp->r = ar.take(pb);
+    sp->w = ar.take(pb);
+    sp->t = ar.take(pb);
+    sp->bhat = nshift == 0 ? ar.take(pb) : nullptr;
+    sp->p = ar.take(pb * (size_t)(nshift > 0 ? nshift : 1));
+    sp->bytes = align_up(ar.off, 256);
+}
+
+int check_stag_params(const lqcd_solve_params* p)
+{
+    if (!p) return set_error(LQCD_EINVAL, "params is NULL");
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return set_error(LQCD_EINVAL, "tol must be > 0");
+    if (p->maxiter < 0) return set_error(LQCD_EINVAL, "maxiter < 0");
+    if (p->eo != 1) return set_error(LQCD_EUNSUPPORTED, "staggered solves are even-odd (eo = 1)");
+    if (p->inner_prec != 64) return set_error(LQCD_EUNSUPPORTED, "staggered solves are FP64 (inner_prec = 64)");
+    if (p->nrhs != 1) return set_error(LQCD_EUNSUPPORTED, "staggered solves take one right-hand side (nrhs = 1)");
+    return LQCD_OK;
+}
+
+// The CG iteration on the base system (control block ctl + base) of the
+// shifted family (N + s_i), i < n, with x_i, p_i at stride pb:
+//   w = (N + s_base) p_base, alpha and every zeta_{k+1}, alpha_i  (FIN_MS_ALPHA)
+//   x_i += alpha_i p_i
+//   r -= alpha w, ||r||^2, beta, beta_i, zeta shift, convergence  (FIN_MS_BETA)
+//   p_i = zeta_i r + beta_i p_i
+int stag_ms_iter(const StagOp& o, const StagPlan& sp, char* x, int n, int base, double s_base)
+{
+    Ctl* ctl = sp.rs.ctl;
+    char* p = static_cast<char*>(sp.p);
+    const int64_t pb = o.pb;
+    LQCD_K(o.normal(p + base * pb, sp.w, sp.t, s_base, 1.0, nullptr, RED_NORM_DS, FIN_MS_ALPHA, PRED_ACTIVE,
+                    ctl + base));
+    LQCD_K(o.blas(BLAS_MS_AXPY, n, PRED_ACTIVE, FIN_STORE, ctl, x, pb, p, pb));
+    LQCD_K(o.blas(BLAS_AXMY_NORM, 1, PRED_ACTIVE, FIN_MS_BETA, ctl + base, nullptr, 0, nullptr, 0, sp.r, pb, sp.w,
+                  pb));
+    LQCD_K(o.blas(BLAS_MS_P, n, PRED_ACTIVE, FIN_STORE, ctl, nullptr, 0, p, pb, sp.r, 0));
+    return LQCD_OK;
+}
+
+int stag_validate(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* b, void* x,
+                  const lqcd_solve_params* prm, const void* info, void* ws, void* stream, Geom* g)
+{
+    int rc = make_geom(geom, g);
+    if (rc) return rc;
+    if ((rc = check_stag_op(op))) return rc;
+    if (op->prec != 64) return set_error(LQCD_EINVAL, "solvers take FP64 fields (op->prec = 64)");
+    if (!(op->mass > 0.0)) return set_error(LQCD_EINVAL, "the even-odd solve needs mass > 0");
+    if ((rc = check_stag_params(prm))) return rc;
+    if (!U || !b || !x || !info) return set_error(LQCD_EINVAL, "NULL field or info pointer");
+    if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
+    if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
+    return LQCD_OK;
+}
+
+StagOp stag_bind(const Geom& g, const lqcd_stag_op* op, const void* U, const StagPlan& sp, void* stream)
+{
+    StagOp o;
+    o.g = g;
+    o.prec = 64;
+    o.recon = op->recon;
+    o.U = U;
+    o.mass = op->mass;
+    o.nrhs = 1;
+    o.pb = colour_bytes(g, 64);
+    o.s = static_cast<hipStream_t>(stream);
+    o.rs = sp.rs;
+    o.tune();
+    return o;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1103,6 +1311,8 @@ int lqcd_field_bytes(const lqcd_geom* geom, int32_t kind, int32_t prec, int32_t 
     if ((rc = check_prec(prec, 12))) return rc;
     if (kind == LQCD_FIELD_SPINOR_PARITY) *bytes = (size_t)parity_bytes(g, prec);
     else if (kind == LQCD_FIELD_SPINOR_FULL) *bytes = (size_t)(2 * parity_bytes(g, prec));
+    else if (kind == LQCD_FIELD_COLOUR_PARITY) *bytes = (size_t)colour_bytes(g, prec);
+    else if (kind == LQCD_FIELD_COLOUR_FULL) *bytes = (size_t)(2 * colour_bytes(g, prec));
     else return set_error(LQCD_EINVAL, "unknown field kind %d", kind);
     return LQCD_OK;
 }
@@ -1384,4 +1594,234 @@ int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, con
     return solve_batch(nsys, geoms, ops, U, b, x, params, info, ws, ws_bytes, stream);
 }
 
+
+// ---------------------------------------------------------------------------
+// Staggered fermions
+
+int lqcd_pack_colour(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* chi, void* out, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_prec(prec, 12))) return rc;
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    if (!chi || !out) return set_error(LQCD_EINVAL, "NULL pointer");
+    LQCD_K(launch_pack_colour(prec, g, chi, out, nrhs, static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
+
+int lqcd_unpack_colour(const lqcd_geom* geom, int32_t prec, int32_t nrhs, const void* in, void* chi, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_prec(prec, 12))) return rc;
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    if (!chi || !in) return set_error(LQCD_EINVAL, "NULL pointer");
+    LQCD_K(launch_unpack_colour(prec, g, in, chi, nrhs, static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
+
+int stag_apply(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out, int32_t dagger,
+               int32_t nrhs, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_stag_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    StagOp o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.mass = op->mass;
+    o.nrhs = nrhs;
+    o.pb = colour_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    o.tune();
+    LQCD_K(o.full_M(in, out, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, nullptr));
+    return LQCD_OK;
+}
+
+int stag_eo_apply(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out,
+                  int32_t out_parity, int32_t op_kind, int32_t nrhs, void* ws, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_stag_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (out_parity != 0 && out_parity != 1) return set_error(LQCD_EINVAL, "out_parity must be 0 or 1");
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    StagOp o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.mass = op->mass;
+    o.nrhs = nrhs;
+    o.pb = colour_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    o.tune();
+    if (op_kind == LQCD_OP_HOP) {
+        LQCD_K(o.hop(out_parity, in, out, 0.5, nullptr, 0.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, nullptr));
+        return LQCD_OK;
+    }
+    if (op_kind == LQCD_OP_NORMAL) {
+        if (out_parity != 0) return set_error(LQCD_EINVAL, "the normal operator acts on even sites (out_parity 0)");
+        if (!ws) return set_error(LQCD_EINVAL, "LQCD_OP_NORMAL needs a workspace of nrhs odd fields");
+        LQCD_K(o.normal(in, out, ws, 0.0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, nullptr));
+        return LQCD_OK;
+    }
+    return set_error(LQCD_EINVAL, "unknown op_kind %d for staggered fermions", op_kind);
+}
+
+int lqcd_workspace_bytes_stag(const lqcd_geom* geom, const lqcd_stag_op* op, int32_t nshift, size_t* bytes)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_stag_op(op))) return rc;
+    if (!bytes) return set_error(LQCD_EINVAL, "bytes is NULL");
+    if (nshift < 0 || nshift > kMaxShifts) return set_error(LQCD_EINVAL, "nshift %d not in [0, %d]", nshift, kMaxShifts);
+    StagPlan sp;
+    plan_stag(g, nshift, nullptr, &sp);
+    *bytes = sp.bytes;
+    return LQCD_OK;
+}
+
+int stag_cg_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* b, void* x,
+                  const lqcd_solve_params* prm, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream)
+{
+    const double t0 = now_s();
+    g_err[0] = 0;
+    Geom g;
+    int rc = stag_validate(geom, op, U, b, x, prm, info, ws, stream, &g);
+    if (rc) return rc;
+    StagPlan sp;
+    plan_stag(g, 0, ws, &sp);
+    if (ws_bytes < sp.bytes) return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, sp.bytes);
+    const StagOp o = stag_bind(g, op, U, sp, stream);
+    const int64_t pb = o.pb;
+    const char* bc = static_cast<const char*>(b);
+    char* xc = static_cast<char*>(x);
+    Ctl* ctl = sp.rs.ctl;
+    const double m = op->mass;
+
+    // stop on ||r_e|| <= tol m ||b||: tol2 = (tol m)^2, bb = ||b||^2 (full)
+    LQCD_K(launch_ctl_init(ctl, 1, prm->tol * m, 0.0, prm->maxiter, o.s));
+    ShiftList sl{};
+    LQCD_K(launch_ctl_init_shifts(ctl, 1, 0, sl, o.s));
+    LQCD_K(o.blas(BLAS_NORM, 1, PRED_ALWAYS, FIN_BB_FULL, ctl, const_cast<char*>(bc), 2 * pb, nullptr, 0, nullptr, 0,
+                  nullptr, 0, 2));
+    // bhat = m b_e - D_eo b_o ; x_e = 0
+    LQCD_K(o.hop(0, bc + pb, sp.bhat, -0.5, bc, m, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, ctl));
+    LQCD_K(o.blas(BLAS_ZERO, 1, PRED_ALWAYS, FIN_STORE, ctl, nullptr, 0, xc, 2 * pb));
+
+    int restarts = 0;
+    for (int pass = 0;; ++pass) {
+        // r = bhat - N x_e (bhat itself on the first pass) ; p = r ; rr
+        if (pass == 0) LQCD_K(o.blas(BLAS_COPY, 1, PRED_ACTIVE, FIN_STORE, ctl, sp.bhat, pb, sp.r, pb));
+        else LQCD_K(o.normal(xc, sp.r, sp.t, 0.0, -1.0, sp.bhat, RED_NONE, FIN_STORE, PRED_ACTIVE, ctl));
+        LQCD_K(o.blas(BLAS_COPY, 1, PRED_ACTIVE, FIN_STORE, ctl, sp.r, pb, sp.p, pb));
+        LQCD_K(o.blas(BLAS_NORM, 1, PRED_ACTIVE, FIN_MS_INIT_KEEP, ctl, sp.r, pb));
+        const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+        rc = drive(o.s, ctl, 1, 1, 1, chunk, prm->maxiter, prm->use_graph != 0,
+                   [&]() { return stag_ms_iter(o, sp, xc, 1, 0, 0.0); });
+        if (rc) return rc;
+        // x_o = (b_o - D_oe x_e) / m ; true residual ||b - M x||^2
+        LQCD_K(o.hop(1, xc, xc + pb, -0.5 / m, bc + pb, 1.0 / m, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, ctl));
+        LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS, ctl));
+        std::vector<Ctl> h;
+        if ((rc = read_ctls(o.s, ctl, 1, h))) return rc;
+        const double tr = h[0].bb > 0 ? std::sqrt(h[0].true_rr / h[0].bb) : 0.0;
+        if (h[0].status != 0 || tr <= prm->tol || h[0].iter >= prm->maxiter || restarts >= 8) break;
+        ++restarts;
+        LQCD_K(launch_ctl_reopen(ctl, 1, 1u, o.s));
+    }
+    std::vector<Ctl> h;
+    if ((rc = read_ctls(o.s, ctl, 1, h))) return rc;
+    lqcd_solve_info& in = info[0];
+    in.iters = h[0].iter;
+    in.reliable_updates = 0;
+    in.restarts = restarts;
+    in.true_resid = h[0].bb > 0 ? std::sqrt(h[0].true_rr / h[0].bb) : 0.0;
+    in.seconds = now_s() - t0;
+    // even-odd hops: bhat 1, 2 per iteration and per restart residual, reconstruct 1 and full M 2 per pass
+    in.hops_outer = 1.0 + 2.0 * h[0].iter + 2.0 * restarts + 3.0 * (restarts + 1);
+    in.hops_inner = 0.0;
+    int st = h[0].status;
+    if (st == LQCD_OK && in.true_resid > prm->tol) st = LQCD_ENOCONV;
+    if (st == LQCD_OK && !std::isfinite(in.true_resid)) st = LQCD_ENONFINITE;
+    in.status = st;
+    return st;
+}
+
+int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* b, void* x,
+                          const double* shifts, int32_t nshift, const lqcd_solve_params* prm, lqcd_solve_info* info,
+                          void* ws, size_t ws_bytes, void* stream)
+{
+    const double t0 = now_s();
+    g_err[0] = 0;
+    Geom g;
+    int rc = stag_validate(geom, op, U, b, x, prm, info, ws, stream, &g);
+    if (rc) return rc;
+    if (!shifts) return set_error(LQCD_EINVAL, "shifts is NULL");
+    if (nshift < 1 || nshift > kMaxShifts) return set_error(LQCD_EINVAL, "nshift %d not in [1, %d]", nshift, kMaxShifts);
+    ShiftList sl{};
+    int base = 0;
+    for (int i = 0; i < nshift; ++i) {
+        if (!std::isfinite(shifts[i]) || shifts[i] < 0.0) return set_error(LQCD_EINVAL, "shift %d must be finite and >= 0", i);
+        sl.s[i] = shifts[i];
+        if (shifts[i] < shifts[base]) base = i;
+    }
+    StagPlan sp;
+    plan_stag(g, nshift, ws, &sp);
+    if (ws_bytes < sp.bytes) return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, sp.bytes);
+    const StagOp o = stag_bind(g, op, U, sp, stream);
+    const int64_t pb = o.pb;
+    char* bc = static_cast<char*>(const_cast<void*>(b));
+    char* xc = static_cast<char*>(x);
+    Ctl* ctl = sp.rs.ctl;
+
+    // x_i = 0 ; r = b ; p_i = b ; ||b||^2 sets every shift's threshold
+    LQCD_K(launch_ctl_init(ctl, nshift, prm->tol, 0.0, prm->maxiter, o.s));
+    LQCD_K(launch_ctl_init_shifts(ctl, nshift, base, sl, o.s));
+    LQCD_K(o.blas(BLAS_ZERO, nshift, PRED_ALWAYS, FIN_STORE, ctl, nullptr, 0, xc, pb));
+    LQCD_K(o.blas(BLAS_COPY, 1, PRED_ALWAYS, FIN_STORE, ctl, bc, pb, sp.r, pb));
+    LQCD_K(o.blas(BLAS_COPY, nshift, PRED_ALWAYS, FIN_STORE, ctl, bc, 0, sp.p, pb));
+    LQCD_K(o.blas(BLAS_NORM, 1, PRED_ALWAYS, FIN_MS_INIT, ctl + base, bc, pb));
+    const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+    rc = drive(o.s, ctl, 1, nshift, nshift, chunk, prm->maxiter, prm->use_graph != 0,
+               [&]() { return stag_ms_iter(o, sp, xc, nshift, base, sl.s[base]); });
+    if (rc) return rc;
+    // true residuals ||b - (N + s_i) x_i||^2, one system at a time
+    for (int i = 0; i < nshift; ++i)
+        LQCD_K(o.normal(xc + i * pb, nullptr, sp.t, sl.s[i], -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS, ctl + i));
+    std::vector<Ctl> h;
+    if ((rc = read_ctls(o.s, ctl, nshift, h))) return rc;
+    const double secs = now_s() - t0;
+    int worst = LQCD_OK;
+    for (int i = 0; i < nshift; ++i) {
+        lqcd_solve_info& in = info[i];
+        in.iters = h[i].iter;
+        in.reliable_updates = 0;
+        in.restarts = 0;
+        in.true_resid = h[i].bb > 0 ? std::sqrt(h[i].true_rr / h[i].bb) : 0.0;
+        in.seconds = secs;
+        // the shared iterations are counted on every system: 2 hops each, plus its true residual
+        in.hops_outer = 2.0 * h[base].iter + 2.0;
+        in.hops_inner = 0.0;
+        int st = h[i].status;
+        // the recursion residual decides; the recomputed one may sit above tol by rounding
+        if (st == LQCD_OK && !(in.true_resid <= 10.0 * prm->tol)) st = LQCD_ENOCONV;
+        in.status = st;
+        if (st != LQCD_OK && worst == LQCD_OK) worst = st;
+    }
+    return worst;
+}
 }  // extern "C"

@@ -14,18 +14,23 @@ namespace lqcd {
 
 template <int OP>
 struct BlasRed {
-    static constexpr int N = OP == BLAS_CG_XR ? 1 : OP == BLAS_NORM ? 1 : (OP == BLAS_BI_XR || OP == BLAS_NORM_DOT) ? 3 : 0;
+    static constexpr int N = (OP == BLAS_CG_XR || OP == BLAS_NORM || OP == BLAS_AXMY_NORM) ? 1
+                             : (OP == BLAS_BI_XR || OP == BLAS_NORM_DOT)                  ? 3
+                                                                                          : 0;
 };
 
 template <class R>
 __device__ __forceinline__ cplx<R> cval(const double* d) { return {R(d[0]), R(d[1])}; }
 
-// The work of block bx of nbx (x) and by (right-hand side) of a launch.
-template <int PREC, int OP>
+// The work of block bx of nbx (x) and by (right-hand side) of a launch, on
+// fields of kind KIND (spinors or colour vectors) stored at precision PREC.
+template <int PREC, int KIND, int OP>
 __device__ __forceinline__ void blas_block(const BlasArgs& a, int bx, int nbx, int by)
 {
-    using IO = SpinorIO<PREC>;
-    using R = typename IO::R;
+    using F = FieldIO<PREC, KIND>;
+    using R = typename F::R;
+    using Vec = typename F::Vec;
+    constexpr int NC = F::NC;
     constexpr int N = BlasRed<OP>::N;
     constexpr int NN = N > 0 ? N : 1;
     const int rhs = by;
@@ -48,80 +53,67 @@ __device__ __forceinline__ void blas_block(const BlasArgs& a, int bx, int nbx, i
     if (h < a.Vh) {
         if (OP == BLAS_CG_XR) {
             const R al = R(ctl->alpha);
-            Spinor<R> x, p, r, w;
-            IO::load(P(a.x, a.st_x), S, h, x);
-            IO::load(P(a.y, a.st_y), S, h, p);
-            IO::load(P(a.z, a.st_z), S, h, r);
-            IO::load(P(a.w, a.st_w), S, h, w);
+            Vec x, p, r, w;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.y, a.st_y), S, h, p);
+            F::load(P(a.z, a.st_z), S, h, r);
+            F::load(P(a.w, a.st_w), S, h, w);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    x.s[s][c] = x.s[s][c] + al * p.s[s][c];
-                    r.s[s][c] = r.s[s][c] - al * w.s[s][c];
-                    red[0] += (double)norm2(r.s[s][c]);
-                }
-            IO::store(P(a.x, a.st_x), S, h, x);
-            IO::store(P(a.z, a.st_z), S, h, r);
+            for (int k = 0; k < NC; ++k) {
+                F::at(x, k) = F::at(x, k) + al * F::at(p, k);
+                F::at(r, k) = F::at(r, k) - al * F::at(w, k);
+                red[0] += (double)norm2(F::at(r, k));
+            }
+            F::store(P(a.x, a.st_x), S, h, x);
+            F::store(P(a.z, a.st_z), S, h, r);
         } else if (OP == BLAS_CG_P) {
             const R be = R(ctl->beta);
-            Spinor<R> p, z;
-            IO::load(P(a.y, a.st_y), S, h, p);
-            IO::load(P(a.z, a.st_z), S, h, z);
+            Vec p, z;
+            F::load(P(a.y, a.st_y), S, h, p);
+            F::load(P(a.z, a.st_z), S, h, z);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) p.s[s][c] = z.s[s][c] + be * p.s[s][c];
-            IO::store(P(a.y, a.st_y), S, h, p);
+            for (int k = 0; k < NC; ++k) F::at(p, k) = F::at(z, k) + be * F::at(p, k);
+            F::store(P(a.y, a.st_y), S, h, p);
         } else if (OP == BLAS_COPY) {
-            Spinor<R> x;
-            IO::load(P(a.x, a.st_x), S, h, x);
-            IO::store(P(a.y, a.st_y), S, h, x);
+            Vec x;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::store(P(a.y, a.st_y), S, h, x);
         } else if (OP == BLAS_ZERO) {
-            Spinor<R> x;
+            Vec x;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) x.s[s][c] = {R(0), R(0)};
-            IO::store(P(a.y, a.st_y), S, h, x);
+            for (int k = 0; k < NC; ++k) F::at(x, k) = {R(0), R(0)};
+            F::store(P(a.y, a.st_y), S, h, x);
         } else if (OP == BLAS_SPIN_SCALE) {
+            // spinors: coef.up on spins 0, 1 and coef.lo on spins 2, 3; colour vectors: coef.up
             const cplx<R> cu = cval<R>(a.coef.up), cl = cval<R>(a.coef.lo);
-            Spinor<R> x;
-            IO::load(P(a.x, a.st_x), S, h, x);
+            Vec x;
+            F::load(P(a.x, a.st_x), S, h, x);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) x.s[s][c] = (s < 2 ? cu : cl) * x.s[s][c];
-            IO::store(P(a.y, a.st_y), S, h, x);
+            for (int k = 0; k < NC; ++k) F::at(x, k) = (KIND == KIND_COLOUR || k < 6 ? cu : cl) * F::at(x, k);
+            F::store(P(a.y, a.st_y), S, h, x);
         } else if (OP == BLAS_NORM) {
-            Spinor<R> x;
-            IO::load(P(a.x, a.st_x), S, h, x);
+            Vec x;
+            F::load(P(a.x, a.st_x), S, h, x);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) red[0] += (double)norm2(x.s[s][c]);
+            for (int k = 0; k < NC; ++k) red[0] += (double)norm2(F::at(x, k));
         } else if (OP == BLAS_NORM_DOT) {
-            Spinor<R> x, r0;
-            IO::load(P(a.x, a.st_x), S, h, x);
-            IO::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, r0);
+            Vec x, r0;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, r0);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    red[0] += (double)norm2(x.s[s][c]);
-                    const cplx<R> d = cmulc(r0.s[s][c], x.s[s][c]);
-                    red[1] += (double)d.x;
-                    red[2] += (double)d.y;
-                }
+            for (int k = 0; k < NC; ++k) {
+                red[0] += (double)norm2(F::at(x, k));
+                const cplx<R> d = cmulc(F::at(r0, k), F::at(x, k));
+                red[1] += (double)d.x;
+                red[2] += (double)d.y;
+            }
         } else if (OP == BLAS_XPY) {
-            Spinor<R> x, y;
-            IO::load(P(a.x, a.st_x), S, h, x);
-            IO::load(P(a.y, a.st_y), S, h, y);
+            Vec x, y;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.y, a.st_y), S, h, y);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) y.s[s][c] = y.s[s][c] + x.s[s][c];
-            IO::store(P(a.y, a.st_y), S, h, y);
+            for (int k = 0; k < NC; ++k) F::at(y, k) = F::at(y, k) + F::at(x, k);
+            F::store(P(a.y, a.st_y), S, h, y);
         } else if (OP == BLAS_BI_P) {
             // beta = (rho / rho_old) (alpha / omega), computed in FP64
             double t1[2], t2[2], be[2];
@@ -130,60 +122,83 @@ __device__ __forceinline__ void blas_block(const BlasArgs& a, int bx, int nbx, i
             be[0] = t1[0] * t2[0] - t1[1] * t2[1];
             be[1] = t1[0] * t2[1] + t1[1] * t2[0];
             const cplx<R> b = cval<R>(be), om = cval<R>(ctl->omega);
-            Spinor<R> p, r, v;
-            IO::load(P(a.y, a.st_y), S, h, p);
-            IO::load(P(a.z, a.st_z), S, h, r);
-            IO::load(P(a.v, a.st_v), S, h, v);
+            Vec p, r, v;
+            F::load(P(a.y, a.st_y), S, h, p);
+            F::load(P(a.z, a.st_z), S, h, r);
+            F::load(P(a.v, a.st_v), S, h, v);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) p.s[s][c] = r.s[s][c] + b * (p.s[s][c] - om * v.s[s][c]);
-            IO::store(P(a.y, a.st_y), S, h, p);
+            for (int k = 0; k < NC; ++k) F::at(p, k) = F::at(r, k) + b * (F::at(p, k) - om * F::at(v, k));
+            F::store(P(a.y, a.st_y), S, h, p);
         } else if (OP == BLAS_BI_S) {
             const cplx<R> al = cval<R>(ctl->balpha);
-            Spinor<R> r, v;
-            IO::load(P(a.z, a.st_z), S, h, r);
-            IO::load(P(a.v, a.st_v), S, h, v);
+            Vec r, v;
+            F::load(P(a.z, a.st_z), S, h, r);
+            F::load(P(a.v, a.st_v), S, h, v);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) r.s[s][c] = r.s[s][c] - al * v.s[s][c];
-            IO::store(P(a.w, a.st_w), S, h, r);
+            for (int k = 0; k < NC; ++k) F::at(r, k) = F::at(r, k) - al * F::at(v, k);
+            F::store(P(a.w, a.st_w), S, h, r);
         } else if (OP == BLAS_BI_XR) {
             const cplx<R> al = cval<R>(ctl->balpha), om = cval<R>(ctl->omega);
-            Spinor<R> x, p, sv, t, r0;
-            IO::load(P(a.x, a.st_x), S, h, x);
-            IO::load(P(a.y, a.st_y), S, h, p);
-            IO::load(P(a.w, a.st_w), S, h, sv);
-            IO::load(P(a.v, a.st_v), S, h, t);
-            IO::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, r0);
-            Spinor<R> r;
+            Vec x, p, sv, t, r0, r;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.y, a.st_y), S, h, p);
+            F::load(P(a.w, a.st_w), S, h, sv);
+            F::load(P(a.v, a.st_v), S, h, t);
+            F::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, r0);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int k = 0; k < NC; ++k) {
+                F::at(x, k) = F::at(x, k) + al * F::at(p, k) + om * F::at(sv, k);
+                F::at(r, k) = F::at(sv, k) - om * F::at(t, k);
+                red[0] += (double)norm2(F::at(r, k));
+                const cplx<R> d = cmulc(F::at(r0, k), F::at(r, k));
+                red[1] += (double)d.x;
+                red[2] += (double)d.y;
+            }
+            F::store(P(a.x, a.st_x), S, h, x);
+            F::store(P(a.z, a.st_z), S, h, r);
+        } else if (OP == BLAS_MS_AXPY) {
+            // x_i += alpha_i p_i (alpha of this right-hand side's control block)
+            const R al = R(ctl->alpha);
+            Vec x, p;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.y, a.st_y), S, h, p);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    x.s[s][c] = x.s[s][c] + al * p.s[s][c] + om * sv.s[s][c];
-                    r.s[s][c] = sv.s[s][c] - om * t.s[s][c];
-                    red[0] += (double)norm2(r.s[s][c]);
-                    const cplx<R> d = cmulc(r0.s[s][c], r.s[s][c]);
-                    red[1] += (double)d.x;
-                    red[2] += (double)d.y;
-                }
-            IO::store(P(a.x, a.st_x), S, h, x);
-            IO::store(P(a.z, a.st_z), S, h, r);
+            for (int k = 0; k < NC; ++k) F::at(x, k) = F::at(x, k) + al * F::at(p, k);
+            F::store(P(a.x, a.st_x), S, h, x);
+        } else if (OP == BLAS_MS_P) {
+            // p_i = zeta_i z + beta_i p_i
+            const R ze = R(ctl->zeta), be = R(ctl->beta);
+            Vec p, z;
+            F::load(P(a.y, a.st_y), S, h, p);
+            F::load(P(a.z, a.st_z), S, h, z);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) F::at(p, k) = ze * F::at(z, k) + be * F::at(p, k);
+            F::store(P(a.y, a.st_y), S, h, p);
+        } else if (OP == BLAS_AXMY_NORM) {
+            // z -= alpha w ; red ||z||^2
+            const R al = R(ctl->alpha);
+            Vec z, w;
+            F::load(P(a.z, a.st_z), S, h, z);
+            F::load(P(a.w, a.st_w), S, h, w);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                F::at(z, k) = F::at(z, k) - al * F::at(w, k);
+                red[0] += (double)norm2(F::at(z, k));
+            }
+            F::store(P(a.z, a.st_z), S, h, z);
         }
     }
 
     if (N > 0) block_reduce_store<NN>(red, a.r.partials + (int64_t)rhs * nbx * NN, bx);
 }
 
-template <int PREC, int OP>
+template <int PREC, int KIND, int OP>
 __global__ void __launch_bounds__(256) k_blas(const BlasArgs a)
 {
-    blas_block<PREC, OP>(a, blockIdx.x, gridDim.x, blockIdx.y);
+    blas_block<PREC, KIND, OP>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
-template <int PREC, int OP>
+template <int PREC, int KIND, int OP>
 __global__ void __launch_bounds__(256) k_blas_batch(const BlasArgs* __restrict__ tab, const int* __restrict__ offs,
                                                    int nsys)
 {
@@ -192,7 +207,7 @@ __global__ void __launch_bounds__(256) k_blas_batch(const BlasArgs* __restrict__
     while (s + 1 < nsys && x >= offs[s + 1]) ++s;
     const int bx = x - offs[s];
     if (bx >= tab[s].gx) return;  // padding of the system's range
-    blas_block<PREC, OP>(tab[s], bx, tab[s].gx, blockIdx.y);
+    blas_block<PREC, KIND, OP>(tab[s], bx, tab[s].gx, blockIdx.y);
 }
 
 struct BlasLaunch {
@@ -202,41 +217,65 @@ struct BlasLaunch {
     int nsys;
 };
 
-template <int PREC, int OP>
+template <int PREC, int KIND, int OP>
 static hipError_t blas_one(const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (L.tab) hipLaunchKernelGGL((k_blas_batch<PREC, OP>), grid, block, 0, s, L.tab, L.offs, L.nsys);
-    else hipLaunchKernelGGL((k_blas<PREC, OP>), grid, block, 0, s, *L.a);
+    if (L.tab) hipLaunchKernelGGL((k_blas_batch<PREC, KIND, OP>), grid, block, 0, s, L.tab, L.offs, L.nsys);
+    else hipLaunchKernelGGL((k_blas<PREC, KIND, OP>), grid, block, 0, s, *L.a);
     return hipGetLastError();
 }
 
-template <int PREC>
+#define LQCD_BLAS_CASE(OP) \
+    case OP: return blas_one<PREC, KIND, OP>(L, grid, block, s);
+
+// Spinor fields: every operation.
+template <int PREC, int KIND>
 static hipError_t blas_op(int op, const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    switch (op) {
-#define LQCD_BLAS_CASE(OP) \
-    case OP: return blas_one<PREC, OP>(L, grid, block, s);
-        LQCD_BLAS_CASE(BLAS_CG_XR)
-        LQCD_BLAS_CASE(BLAS_CG_P)
-        LQCD_BLAS_CASE(BLAS_COPY)
-        LQCD_BLAS_CASE(BLAS_ZERO)
-        LQCD_BLAS_CASE(BLAS_SPIN_SCALE)
-        LQCD_BLAS_CASE(BLAS_NORM)
-        LQCD_BLAS_CASE(BLAS_BI_P)
-        LQCD_BLAS_CASE(BLAS_BI_S)
-        LQCD_BLAS_CASE(BLAS_BI_XR)
-        LQCD_BLAS_CASE(BLAS_XPY)
-        LQCD_BLAS_CASE(BLAS_NORM_DOT)
-#undef LQCD_BLAS_CASE
-    default: return hipErrorInvalidValue;
+    if constexpr (KIND == KIND_SPINOR) {
+        switch (op) {
+            LQCD_BLAS_CASE(BLAS_CG_XR)
+            LQCD_BLAS_CASE(BLAS_CG_P)
+            LQCD_BLAS_CASE(BLAS_COPY)
+            LQCD_BLAS_CASE(BLAS_ZERO)
+            LQCD_BLAS_CASE(BLAS_SPIN_SCALE)
+            LQCD_BLAS_CASE(BLAS_NORM)
+            LQCD_BLAS_CASE(BLAS_BI_P)
+            LQCD_BLAS_CASE(BLAS_BI_S)
+            LQCD_BLAS_CASE(BLAS_BI_XR)
+            LQCD_BLAS_CASE(BLAS_XPY)
+            LQCD_BLAS_CASE(BLAS_NORM_DOT)
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        // colour vectors: what the staggered CG and multi-shift CG use
+        switch (op) {
+            LQCD_BLAS_CASE(BLAS_CG_XR)
+            LQCD_BLAS_CASE(BLAS_CG_P)
+            LQCD_BLAS_CASE(BLAS_COPY)
+            LQCD_BLAS_CASE(BLAS_ZERO)
+            LQCD_BLAS_CASE(BLAS_SPIN_SCALE)
+            LQCD_BLAS_CASE(BLAS_NORM)
+            LQCD_BLAS_CASE(BLAS_XPY)
+            LQCD_BLAS_CASE(BLAS_MS_AXPY)
+            LQCD_BLAS_CASE(BLAS_MS_P)
+            LQCD_BLAS_CASE(BLAS_AXMY_NORM)
+        default: return hipErrorInvalidValue;
+        }
     }
 }
+#undef LQCD_BLAS_CASE
 
-static hipError_t blas_prec(int prec, int op, const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+static hipError_t blas_prec(int prec, int kind, int op, const BlasLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (prec == 64) return blas_op<64>(op, L, grid, block, s);
-    if (prec == 32) return blas_op<32>(op, L, grid, block, s);
-    if (prec == 16) return blas_op<16>(op, L, grid, block, s);
+    if (kind == KIND_SPINOR) {
+        if (prec == 64) return blas_op<64, KIND_SPINOR>(op, L, grid, block, s);
+        if (prec == 32) return blas_op<32, KIND_SPINOR>(op, L, grid, block, s);
+        if (prec == 16) return blas_op<16, KIND_SPINOR>(op, L, grid, block, s);
+    } else if (kind == KIND_COLOUR) {
+        if (prec == 64) return blas_op<64, KIND_COLOUR>(op, L, grid, block, s);
+        if (prec == 32) return blas_op<32, KIND_COLOUR>(op, L, grid, block, s);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -253,7 +292,9 @@ hipError_t plan_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch
     p.grid = dim3(nbs * a.nsub, nrhs);
     p.a.gx = (int)p.grid.x;
     p.block = dim3(blk);
-    p.nfin = (op == BLAS_CG_XR || op == BLAS_NORM) ? 1 : (op == BLAS_BI_XR || op == BLAS_NORM_DOT) ? 3 : 0;
+    p.nfin = (op == BLAS_CG_XR || op == BLAS_NORM || op == BLAS_AXMY_NORM) ? 1
+             : (op == BLAS_BI_XR || op == BLAS_NORM_DOT)                  ? 3
+                                                                          : 0;
     p.slots = (int)p.grid.x;
     if (p.nfin && p.slots > a.r.capacity) return hipErrorInvalidValue;  // partials too small
     return hipSuccess;
@@ -262,7 +303,7 @@ hipError_t plan_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch
 hipError_t exec_blas(const BlasPlan& p, hipStream_t s)
 {
     BlasLaunch L{&p.a, nullptr, nullptr, 1};
-    const hipError_t e = blas_prec(p.prec, p.op, L, p.grid, p.block, s);
+    const hipError_t e = blas_prec(p.prec, p.a.kind, p.op, L, p.grid, p.block, s);
     if (e != hipSuccess || p.nfin == 0) return e;
     return launch_finalize(p.nfin, p.a.r.partials, p.slots, p.a.r.fin, p.a.ctl, p.a.pred, p.nrhs, s);
 }
@@ -273,7 +314,7 @@ hipError_t exec_blas_batch(const BlasPlan* plans, int n, const BlasArgs* tab, co
     if (n < 1) return hipErrorInvalidValue;
     const BlasPlan& p0 = plans[0];
     BlasLaunch L{nullptr, tab, offs, n};
-    const hipError_t e = blas_prec(p0.prec, p0.op, L, dim3((unsigned)total_blocks, p0.grid.y), p0.block, s);
+    const hipError_t e = blas_prec(p0.prec, p0.a.kind, p0.op, L, dim3((unsigned)total_blocks, p0.grid.y), p0.block, s);
     if (e != hipSuccess || p0.nfin == 0) return e;
     return launch_finalize_batch(p0.nfin, fin_tab, n, p0.nrhs, s);
 }
@@ -522,10 +563,14 @@ __device__ __forceinline__ int64_t canonical_site(const Geom& g, int p, int64_t 
     return x + (int64_t)g.L[0] * (y + (int64_t)g.L[1] * (z + (int64_t)g.L[2] * t));
 }
 
-template <int PREC, bool PACK>
-__global__ void __launch_bounds__(256) k_pack_spinor(const Geom g, const double2* canon_c, double2* canon_m,
-                                                     const char* in, char* out)
+// Canonical (V, NC) complex128 per right-hand side <-> internal parity
+// fields of kind KIND (NC = 12 for spinors, 3 for colour vectors).
+template <int PREC, int KIND, bool PACK>
+__global__ void __launch_bounds__(256) k_pack_field(const Geom g, const double2* canon_c, double2* canon_m,
+                                                    const char* in, char* out)
 {
+    using F = FieldIO<PREC, KIND>;
+    using R = typename F::R;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
     const int p = (int)(gid / g.Vh);
@@ -533,45 +578,62 @@ __global__ void __launch_bounds__(256) k_pack_spinor(const Geom g, const double2
     if (p >= 2) return;
     const int64_t V = 2 * (int64_t)g.Vh;
     const int64_t i = canonical_site(g, p, h);
-    const int64_t par_bytes = spinor_parity_bytes(PREC, g.S);
+    const int64_t par_bytes = field_parity_bytes(KIND, PREC, g.S);
     const int64_t foff = (int64_t)rhs * 2 * par_bytes + p * par_bytes;
-    using R = typename SpinorIO<PREC>::R;
-    Spinor<R> v;
+    typename F::Vec v;
     if (PACK) {
-        const double2* c = canon_c + ((int64_t)rhs * V + i) * 12;
+        const double2* c = canon_c + ((int64_t)rhs * V + i) * F::NC;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v.s[k / 3][k % 3] = {R(c[k].x), R(c[k].y)};
-        SpinorIO<PREC>::store(out + foff, g.S, h, v);
+        for (int k = 0; k < F::NC; ++k) F::at(v, k) = {R(c[k].x), R(c[k].y)};
+        F::store(out + foff, g.S, h, v);
     } else {
-        SpinorIO<PREC>::load(in + foff, g.S, h, v);
-        double2* c = canon_m + ((int64_t)rhs * V + i) * 12;
+        F::load(in + foff, g.S, h, v);
+        double2* c = canon_m + ((int64_t)rhs * V + i) * F::NC;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) c[k] = make_double2((double)v.s[k / 3][k % 3].x, (double)v.s[k / 3][k % 3].y);
+        for (int k = 0; k < F::NC; ++k) c[k] = make_double2((double)F::at(v, k).x, (double)F::at(v, k).y);
     }
+}
+
+template <int KIND>
+static hipError_t pack_kind(int prec, bool pack, const Geom& g, const void* canon, const void* in, void* out, int nrhs,
+                            hipStream_t s)
+{
+    dim3 b(256), gr((unsigned)((2 * (int64_t)g.Vh + 255) / 256), nrhs);
+    const double2* cc = static_cast<const double2*>(canon);
+    double2* cm = static_cast<double2*>(const_cast<void*>(canon));
+    const char* i = static_cast<const char*>(in);
+    char* o = static_cast<char*>(out);
+#define LQCD_PACK(P)                                                                                         \
+    if (prec == P) {                                                                                         \
+        if (pack) hipLaunchKernelGGL((k_pack_field<P, KIND, true>), gr, b, 0, s, g, cc, nullptr, nullptr, o); \
+        else hipLaunchKernelGGL((k_pack_field<P, KIND, false>), gr, b, 0, s, g, nullptr, cm, i, nullptr);    \
+        return hipGetLastError();                                                                            \
+    }
+    LQCD_PACK(64)
+    LQCD_PACK(32)
+    LQCD_PACK(16)
+#undef LQCD_PACK
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pack_spinor(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s)
 {
-    dim3 b(256), gr((unsigned)((2 * (int64_t)g.Vh + 255) / 256), nrhs);
-    const double2* c = static_cast<const double2*>(canon);
-    char* o = static_cast<char*>(out);
-    if (prec == 64) hipLaunchKernelGGL((k_pack_spinor<64, true>), gr, b, 0, s, g, c, nullptr, nullptr, o);
-    else if (prec == 32) hipLaunchKernelGGL((k_pack_spinor<32, true>), gr, b, 0, s, g, c, nullptr, nullptr, o);
-    else if (prec == 16) hipLaunchKernelGGL((k_pack_spinor<16, true>), gr, b, 0, s, g, c, nullptr, nullptr, o);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    return pack_kind<KIND_SPINOR>(prec, true, g, canon, nullptr, out, nrhs, s);
 }
 
 hipError_t launch_unpack_spinor(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s)
 {
-    dim3 b(256), gr((unsigned)((2 * (int64_t)g.Vh + 255) / 256), nrhs);
-    double2* c = static_cast<double2*>(canon);
-    const char* i = static_cast<const char*>(in);
-    if (prec == 64) hipLaunchKernelGGL((k_pack_spinor<64, false>), gr, b, 0, s, g, nullptr, c, i, nullptr);
-    else if (prec == 32) hipLaunchKernelGGL((k_pack_spinor<32, false>), gr, b, 0, s, g, nullptr, c, i, nullptr);
-    else if (prec == 16) hipLaunchKernelGGL((k_pack_spinor<16, false>), gr, b, 0, s, g, nullptr, c, i, nullptr);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    return pack_kind<KIND_SPINOR>(prec, false, g, canon, in, nullptr, nrhs, s);
+}
+
+hipError_t launch_pack_colour(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s)
+{
+    return pack_kind<KIND_COLOUR>(prec, true, g, canon, nullptr, out, nrhs, s);
+}
+
+hipError_t launch_unpack_colour(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s)
+{
+    return pack_kind<KIND_COLOUR>(prec, false, g, canon, in, nullptr, nrhs, s);
 }
 
 template <int PREC, int RECON, bool FROM_CANON>
@@ -655,6 +717,23 @@ __global__ void k_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int ite
 hipError_t launch_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ctl_init, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, tol, delta, iter_limit);
+    return hipGetLastError();
+}
+
+__global__ void k_ctl_init_shifts(Ctl* ctl, int n, int base, ShiftList shifts)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ctl[i].sigma = shifts.s[i] - shifts.s[base];
+    ctl[i].ms_index = i;
+    ctl[i].ms_n = n;
+    ctl[i].ms_base = base;
+}
+
+hipError_t launch_ctl_init_shifts(Ctl* ctl, int n, int base, const ShiftList& shifts, hipStream_t s)
+{
+    if (n < 1 || n > kMaxShifts || base < 0 || base >= n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ctl_init_shifts, dim3(1), dim3(64), 0, s, ctl, n, base, shifts);
     return hipGetLastError();
 }
 

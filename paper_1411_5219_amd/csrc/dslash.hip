@@ -13,8 +13,18 @@ hipError_t launch_dslash_32(int recon, int nr, bool lnt, bool dag, int red, cons
 hipError_t launch_dslash_16(int recon, int nr, bool lnt, bool dag, int red, const DslashLaunch& L, dim3 grid, dim3 block,
                             hipStream_t s);
 
+hipError_t launch_stag_64(int recon, int red, bool lnt, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_stag_32(int recon, int red, bool lnt, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_stag_16(int recon, int red, bool lnt, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s);
+
 static hipError_t launch_dslash_prec(const DslashPlan& p, const DslashLaunch& L, dim3 grid, hipStream_t s)
 {
+    if (p.kind == PLAN_STAG) {
+        if (p.prec == 64) return launch_stag_64(p.recon, p.red, p.lnt, L, grid, p.block, s);
+        if (p.prec == 32) return launch_stag_32(p.recon, p.red, p.lnt, L, grid, p.block, s);
+        if (p.prec == 16) return launch_stag_16(p.recon, p.red, p.lnt, L, grid, p.block, s);
+        return hipErrorInvalidValue;
+    }
     if (p.prec == 64) return launch_dslash_64(p.recon, p.nr, p.lnt, p.dag, p.red, L, grid, p.block, s);
     if (p.prec == 32) return launch_dslash_32(p.recon, p.nr, p.lnt, p.dag, p.red, L, grid, p.block, s);
     if (p.prec == 16) return launch_dslash_16(p.recon, p.nr, p.lnt, p.dag, p.red, L, grid, p.block, s);
@@ -38,6 +48,7 @@ hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashAr
           (prec == 16 && recon == 12)))
         return hipErrorInvalidValue;
     DslashPlan& p = *out;
+    p.kind = PLAN_WILSON;
     p.prec = prec;
     p.recon = recon;
     p.dag = dagger;
@@ -130,6 +141,27 @@ hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const Dslash
     DslashPlan p;
     hipError_t e = plan_dslash(prec, recon, dagger, red, args, nrhs, cfg, &p);
     if (e != hipSuccess) return e;
+    if (Recorder* r = active_recorder()) {
+        r->steps.push_back(Step{});
+        r->steps.back().kind = STEP_DSLASH;
+        r->steps.back().d = p;
+        return hipSuccess;
+    }
+    return exec_dslash(p, s);
+}
+
+hipError_t launch_stag(int prec, int recon, int red, const DslashArgs& args, int nrhs, const Launch& cfg,
+                       hipStream_t s)
+{
+    if (red != RED_NONE && red != RED_NORM && red != RED_NORM_DS) return hipErrorInvalidValue;
+    Launch c = cfg;
+    c.rhs_tile = 1;   // one right-hand side per work-item, tiles along grid.y
+    c.rhs_group = 0;
+    DslashPlan p;
+    hipError_t e = plan_dslash(prec, recon, false, red, args, nrhs, c, &p);
+    if (e != hipSuccess) return e;
+    p.kind = PLAN_STAG;
+    p.nfin = red == RED_NONE ? 0 : red == RED_NORM ? 1 : 3;
     if (Recorder* r = active_recorder()) {
         r->steps.push_back(Step{});
         r->steps.back().kind = STEP_DSLASH;

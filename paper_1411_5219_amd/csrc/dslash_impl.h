@@ -16,6 +16,7 @@
 // only h is multiplied by the link.
 #pragma once
 
+#include "block_order.h"
 #include "lqcd.h"
 #include "lqcd_device.h"
 #include "lqcd_fin.h"
@@ -82,55 +83,6 @@ __device__ __forceinline__ void phase_mul(cplx<R> (&w)[2][3], cplx<R> ph)
 #pragma unroll
         for (int a = 0; a < 3; ++a) w[s][a] = ph * w[s][a];
 }
-
-// Neighbour of an output site for hop K = 2 mu + (0 forward, 1 backward):
-// the neighbour's parity-local index, the link block (mu, parity) and the
-// parity-local site the link is stored at, and whether the hop crosses the
-// lattice boundary (and so takes the boundary phase).
-// Parity-local indices fit 32 bits (the library limits V/2 to 21 * 2^20),
-// which keeps them in one register each.
-struct Nbr {
-    int nb, lsite;
-    int lblk;
-    bool cross;
-};
-
-struct SiteGeo {
-    int x, y, z, t, p, Lx, Ly, Lz, Lt;
-    int h, base, hy, hz, ht;
-
-    template <int K>
-    __device__ __forceinline__ Nbr get() const
-    {
-        constexpr int MU = K >> 1;
-        constexpr bool FWD = (K & 1) == 0;
-        Nbr n;
-        if constexpr (MU == 0) {
-            if constexpr (FWD) {
-                n.cross = x == Lx - 1;
-                n.nb = base + ((n.cross ? 0 : x + 1) >> 1);
-            } else {
-                n.cross = x == 0;
-                n.nb = base + ((n.cross ? Lx - 1 : x - 1) >> 1);
-            }
-        } else {
-            const int c = MU == 1 ? y : MU == 2 ? z : t;
-            const int Lc = MU == 1 ? Ly : MU == 2 ? Lz : Lt;
-            const int hc = MU == 1 ? hy : MU == 2 ? hz : ht;
-            if constexpr (FWD) {
-                n.cross = c == Lc - 1;
-                n.nb = n.cross ? h - (Lc - 1) * hc : h + hc;
-            } else {
-                n.cross = c == 0;
-                n.nb = n.cross ? h + (Lc - 1) * hc : h - hc;
-            }
-        }
-        // U_mu(x) for forward hops, U_mu(x - mu) (stored at the neighbour) for backward ones
-        n.lblk = 2 * MU + (FWD ? p : 1 - p);
-        n.lsite = FWD ? h : n.nb;
-        return n;
-    }
-};
 
 // Operands of one hop for a tile of NR right-hand sides: the link (loaded
 // once for the tile) and the neighbour spinor of each right-hand side.
@@ -360,32 +312,9 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
 {
     using R = typename SpinorIO<PREC>::R;
     constexpr int N = RedN<RED>::N;
-    const int nb = nbx;
-    int bid = a.swizzle ? xcd_swizzle(bx, nb) : bx;
-    int p = a.parity;
-    int64_t poff = 0, ioff = 0;  // parity offsets of output-side / neighbour fields
-    if (a.full) {  // both parities in one launch: the first nb/2 blocks even, the rest odd
-        const int nbh = nb >> 1;
-        p = bid >= nbh;
-        bid -= p * nbh;
-        poff = p * a.par_bytes;
-        ioff = (1 - p) * a.par_bytes;
-    }
-    // right-hand-side tile of this block and its spatial block
-    int tile = by;
-    int nsp = a.full ? nb >> 1 : nb;  // spatial blocks per parity (per tile)
-    if (a.rhs_group > 0) {
-        const int G = a.rhs_group;
-        const int ti = bid % G;
-        const int rest = bid / G;
-        nsp = a.nsp;
-        const int sp = rest % nsp;
-        tile = (rest / nsp) * G + ti;
-        bid = sp;
-    }
+    const BlockPos bp = block_pos(a, bx, nbx, by);
+    const int p = bp.p, tile = bp.tile;
     const int rhs0 = tile * NR;
-    const int pslot = bid + p * nsp;        // partials slot of this block within its right-hand side
-    const int nslots = nsp * (a.full ? 2 : 1);
     bool act[NR];
     bool any = false;
 #pragma unroll
@@ -395,41 +324,9 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
         any = any || act[r];
     }
     if (!any) return;
-    const int Lx = a.g.L[0], Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
-    const int Lxh = a.g.Lxh;
-    int h, xh, y, z, t;
-    bool valid;
-    if (a.rows == 0) {
-        h = bid * a.bdim + threadIdx.x;
-        valid = (int)threadIdx.x < a.bdim && h < a.g.Vh;
-        xh = h % Lxh;
-        int r = h / Lxh;
-        y = r % Ly;
-        r /= Ly;
-        z = r % Lz;
-        t = r / Lz;
-    } else {
-        int yc;
-        if (a.ztile <= 1) {
-            t = bid % Lt;
-            const int r = bid / Lt;
-            z = r % Lz;
-            yc = r / Lz;
-        } else {
-            const int T = a.ztile, nzs = Lz / T;
-            const int zl = bid % T;
-            int r = bid / T;
-            t = r % Lt;
-            r /= Lt;
-            z = (r % nzs) * T + zl;
-            yc = r / nzs;
-        }
-        const int yr = threadIdx.x / Lxh;
-        xh = threadIdx.x - yr * Lxh;
-        y = yc * a.rows + yr;
-        valid = yr < a.rows && y < Ly;
-        h = xh + Lxh * (y + Ly * (z + Lz * t));
-    }
+    const SitePos sp = site_pos(a, bp.bid, p);
+    const int h = sp.h;
+    const int64_t poff = bp.poff, ioff = bp.ioff;
     const int64_t S = a.g.S;
 
     double tot[NR][N];
@@ -438,11 +335,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
 #pragma unroll
         for (int j = 0; j < N; ++j) tot[r][j] = 0.0;
 
-    if (valid) {
-        const int x = 2 * xh + ((y + z + t + p) & 1);
-        const int64_t hy = Lxh, hz = (int64_t)Lxh * Ly, ht = hz * Lz;
-        const int64_t base = h - xh;
-
+    if (sp.valid) {
         const char* in[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) in[r] = static_cast<const char*>(a.in) + (int64_t)(rhs0 + r) * a.st_in + ioff;
@@ -459,7 +352,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
                                {R(a.g.ph[1][0]), R(a.g.ph[1][1])},
                                {R(a.g.ph[2][0]), R(a.g.ph[2][1])},
                                {R(a.g.ph[3][0]), R(a.g.ph[3][1])}};
-        const SiteGeo geo{x, y, z, t, p, Lx, Ly, Lz, Lt, h, (int)base, (int)hy, (int)hz, (int)ht};
+        const SiteGeo geo = site_geo(a.g, sp, p);
         HopPipe<PREC, RECON, NR, LNT, SF, HopTune<PREC, NR>::depth> pipe{in, act, a.U, S, geo, ph, acc};
         pipe.run();
 
@@ -533,7 +426,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
         }
     }
 
-    if (RED != RED_NONE) block_reduce_tile<NR, N>(tot, a.r.partials, nslots, rhs0, a.nrhs, pslot);
+    if (RED != RED_NONE) block_reduce_tile<NR, N>(tot, a.r.partials, bp.nslots, rhs0, a.nrhs, bp.pslot);
 }
 
 template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>

@@ -15,6 +15,10 @@
 //       FP32/12 : 3 planes float4 (complex pairs of rows 0 and 1)
 //       FP16/12 : one plane of 8 halves (row 0, element (1,0)) and one
 //                 plane of 4 halves (elements (1,1), (1,2))
+//   colour vector (staggered fermions, 3 complex per site):
+//       FP64    : 3 planes of double2
+//       FP32    : one plane of float4 (colours 0, 1) and one of float2 (2)
+//       FP16    : one plane of 16 bytes: 6 halves (scaled) and the FP32 scale
 // A full-lattice field is the even-parity field followed by the odd one.
 #pragma once
 
@@ -251,6 +255,141 @@ struct SpinorIO<16> {
 __host__ __device__ inline int64_t spinor_parity_bytes(int prec, int64_t S)
 {
     return prec == 64 ? 192 * S : prec == 32 ? 96 * S : 52 * S;
+}
+
+// ---------------------------------------------------------------------------
+// Colour-vector storage (staggered fermions)
+
+template <class R>
+struct Colour {
+    cplx<R> c[3];
+};
+
+template <int PREC>
+struct ColourIO;
+
+template <>
+struct ColourIO<64> {
+    using R = double;
+    static constexpr int kBytesPerSite = 48;
+    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Colour<R>& v)
+    {
+        const rsrc_t r = make_rsrc(base, 48 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double2 d = bload<double2>(r, o, (uint32_t)(k * S * 16));
+            v.c[k] = {d.x, d.y};
+        }
+    }
+    template <int AUX = 0>
+    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Colour<R>& v)
+    {
+        const rsrc_t r = make_rsrc(base, 48 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bstore<AUX>(r, o, (uint32_t)(k * S * 16), make_double2(v.c[k].x, v.c[k].y));
+    }
+};
+
+template <>
+struct ColourIO<32> {
+    using R = float;
+    static constexpr int kBytesPerSite = 24;
+    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Colour<R>& v)
+    {
+        const rsrc_t r = make_rsrc(base, 24 * S);
+        const float4 a = bload<float4>(r, static_cast<uint32_t>(site) * 16u, 0u);
+        const float2 b = bload<float2>(r, static_cast<uint32_t>(site) * 8u, (uint32_t)(16 * S));
+        v.c[0] = {a.x, a.y};
+        v.c[1] = {a.z, a.w};
+        v.c[2] = {b.x, b.y};
+    }
+    template <int AUX = 0>
+    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Colour<R>& v)
+    {
+        const rsrc_t r = make_rsrc(base, 24 * S);
+        bstore<AUX>(r, static_cast<uint32_t>(site) * 16u, 0u, make_float4(v.c[0].x, v.c[0].y, v.c[1].x, v.c[1].y));
+        bstore<AUX>(r, static_cast<uint32_t>(site) * 8u, (uint32_t)(16 * S), make_float2(v.c[2].x, v.c[2].y));
+    }
+};
+
+// FP16 storage, FP32 arithmetic: the 6 reals as halves relative to the
+// site's largest magnitude, which is stored as an FP32 in the same 16 bytes.
+template <>
+struct ColourIO<16> {
+    using R = float;
+    static constexpr int kBytesPerSite = 16;
+    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Colour<R>& v)
+    {
+        const rsrc_t r = make_rsrc(base, 16 * S);
+        const uint4 d = bload<uint4>(r, static_cast<uint32_t>(site) * 16u, 0u);
+        const float scale = __uint_as_float(d.w);
+        const uint32_t w[3] = {d.x, d.y, d.z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v.c[k] = {scale * SpinorIO<16>::h2f(w[k], 0), scale * SpinorIO<16>::h2f(w[k], 1)};
+    }
+    template <int AUX = 0>
+    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Colour<R>& v)
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) m = fmaxf(m, fmaxf(fabsf(v.c[k].x), fabsf(v.c[k].y)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        uint32_t w[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] = SpinorIO<16>::f2h2(v.c[k].x * inv, v.c[k].y * inv);
+        const rsrc_t r = make_rsrc(base, 16 * S);
+        bstore<AUX>(r, static_cast<uint32_t>(site) * 16u, 0u, make_uint4(w[0], w[1], w[2], __float_as_uint(m)));
+    }
+};
+
+// Bytes of one parity of a colour-vector field with stride S.
+__host__ __device__ inline int64_t colour_parity_bytes(int prec, int64_t S)
+{
+    return prec == 64 ? 48 * S : prec == 32 ? 24 * S : 16 * S;
+}
+
+// Site-local kernels (BLAS, conversion, packing) see a field as NC complex
+// numbers per site: KIND 0 is a spinor (12), KIND 1 a colour vector (3).
+enum FieldKind { KIND_SPINOR = 0, KIND_COLOUR = 1 };
+
+template <int PREC, int KIND>
+struct FieldIO;
+
+template <int PREC>
+struct FieldIO<PREC, KIND_SPINOR> {
+    using IO = SpinorIO<PREC>;
+    using R = typename IO::R;
+    using Vec = Spinor<R>;
+    static constexpr int NC = 12;
+    __device__ static __forceinline__ cplx<R>& at(Vec& v, int k) { return v.s[k / 3][k % 3]; }
+    __device__ static __forceinline__ void load(const void* b, int64_t S, int64_t h, Vec& v) { IO::load(b, S, h, v); }
+    template <int AUX = 0>
+    __device__ static __forceinline__ void store(void* b, int64_t S, int64_t h, const Vec& v)
+    {
+        IO::template store<AUX>(b, S, h, v);
+    }
+};
+
+template <int PREC>
+struct FieldIO<PREC, KIND_COLOUR> {
+    using IO = ColourIO<PREC>;
+    using R = typename IO::R;
+    using Vec = Colour<R>;
+    static constexpr int NC = 3;
+    __device__ static __forceinline__ cplx<R>& at(Vec& v, int k) { return v.c[k]; }
+    __device__ static __forceinline__ void load(const void* b, int64_t S, int64_t h, Vec& v) { IO::load(b, S, h, v); }
+    template <int AUX = 0>
+    __device__ static __forceinline__ void store(void* b, int64_t S, int64_t h, const Vec& v)
+    {
+        IO::template store<AUX>(b, S, h, v);
+    }
+};
+
+__host__ __device__ inline int64_t field_parity_bytes(int kind, int prec, int64_t S)
+{
+    return kind == KIND_COLOUR ? colour_parity_bytes(prec, S) : spinor_parity_bytes(prec, S);
 }
 
 // ---------------------------------------------------------------------------

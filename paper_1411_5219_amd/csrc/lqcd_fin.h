@@ -136,6 +136,70 @@ __device__ inline void finalize_totals(int fin, Ctl* c, const double* v)
         }
         if (c->iter >= c->iter_limit) fail(c, LQCD_ENOCONV);
         break;
+    case FIN_MS_INIT:
+    case FIN_MS_INIT_KEEP: {
+        Ctl* c0 = c - c->ms_index;
+        c->rr = v[0];
+        c->alpha_prev = 1.0;
+        c->beta_prev = 0.0;
+        for (int i = 0; i < c->ms_n; ++i) {
+            Ctl* ci = c0 + i;
+            if (fin == FIN_MS_INIT) {
+                ci->bb = v[0];
+                ci->thresh = ci->tol2 * v[0];
+            }
+            ci->zeta_prev = 1.0;
+            ci->zeta = 1.0;
+            if (!finite(v[0])) fail(ci, LQCD_ENONFINITE);
+            else if (v[0] <= ci->thresh) ci->done = 1;
+        }
+        break;
+    }
+    case FIN_MS_ALPHA: {
+        // v[1] = Re <w, p> = <p, A p> of the base system
+        Ctl* c0 = c - c->ms_index;
+        const double pap = v[1];
+        const bool bad = !finite(pap) || !(pap > 0.0);
+        const double al = bad ? 0.0 : c->rr / pap;
+        for (int i = 0; i < c->ms_n; ++i) {
+            Ctl* ci = c0 + i;
+            if (ci->done) continue;
+            if (bad) { fail(ci, finite(pap) ? LQCD_EBREAKDOWN : LQCD_ENONFINITE); continue; }
+            // zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1}
+            //   / (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 + sigma alpha_k))
+            const double den = al * c->beta_prev * (ci->zeta_prev - ci->zeta) +
+                               ci->zeta_prev * c->alpha_prev * (1.0 + ci->sigma * al);
+            const double zn = ci->zeta * ci->zeta_prev * c->alpha_prev / den;
+            if (!finite(zn) || ci->zeta == 0.0) { fail(ci, LQCD_ENONFINITE); continue; }
+            ci->zeta_next = zn;
+            ci->alpha = al * zn / ci->zeta;
+        }
+        c->alpha = al;  // the base system's alpha (its zeta is 1)
+        break;
+    }
+    case FIN_MS_BETA: {
+        Ctl* c0 = c - c->ms_index;
+        const double rr = v[0];
+        const double be = c->rr > 0.0 ? rr / c->rr : 0.0;
+        const int it = c->iter + 1;
+        for (int i = 0; i < c->ms_n; ++i) {
+            Ctl* ci = c0 + i;
+            if (ci->done) continue;
+            if (!finite(rr)) { fail(ci, LQCD_ENONFINITE); continue; }
+            const double q = ci->zeta_next / ci->zeta;
+            ci->beta = be * q * q;
+            ci->zeta_prev = ci->zeta;
+            ci->zeta = ci->zeta_next;
+            ci->iter = it;
+            if (ci->zeta * ci->zeta * rr <= ci->thresh) ci->done = 1;
+            else if (it >= ci->iter_limit) fail(ci, LQCD_ENOCONV);
+        }
+        c->iter = it;
+        c->alpha_prev = c->alpha;
+        c->beta_prev = be;
+        c->rr = rr;
+        break;
+    }
     default:
         break;
     }

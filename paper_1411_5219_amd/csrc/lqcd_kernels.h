@@ -48,6 +48,11 @@ enum Fin {
     FIN_BB = 12,          // bb = red[0] + ||b_o||^2, thresh = tol^2 * bb
     FIN_BB_FULL = 13,     // bb = ||b||^2 of a full-lattice field, thresh = tol^2 * bb
     FIN_RR_INIT = 14,     // rr = rr_max = ||r||^2 (start of a reliable-update solve)
+    // multi-shift CG, run by the base system's finalize for every shift
+    FIN_MS_INIT = 15,     // rr = ||b||^2 = bb of every shift, thresh = tol^2 bb, zeta = 1
+    FIN_MS_INIT_KEEP = 16,// rr = ||r||^2, zeta = 1; bb and thresh already set
+    FIN_MS_ALPHA = 17,    // alpha = rr / <p, A p>; zeta_{k+1}, alpha_i of every shift
+    FIN_MS_BETA = 18,     // rr' = ||r||^2, beta, beta_i, zeta shift, per-shift convergence
 };
 
 // Predicates on the control block evaluated at the top of a kernel.
@@ -71,13 +76,20 @@ struct Ctl {
     double true_rr;
     double rho[2], rho_old[2], balpha[2], omega[2], r0v[2], ts[2], tt;
     double red[6];    // FIN_STORE totals
+    // Multi-shift CG (one Ctl per shifted system, ms_n of them in a row; the
+    // base system, the smallest shift, at index ms_base): this system's shift
+    // minus the base shift and its residual ratios to the base residual,
+    // zeta_{k-1}, zeta_k and, inside an iteration, zeta_{k+1}; the base also
+    // keeps the base CG's alpha_{k-1} and beta_{k-1}.
+    double sigma, zeta_prev, zeta, zeta_next, alpha_prev, beta_prev;
+    int ms_index, ms_n, ms_base;
     int iter;         // completed iterations
     int done;         // 1 when converged (or failed): every kernel becomes a no-op
     int status;       // 0, or a negative LQCD error code
     int update;       // reliable update pending
     int nupdates;     // reliable updates performed
     int iter_limit;   // stop (done, status ENOCONV) at this many iterations
-    int pad[2];
+    int pad[1];
 };
 
 struct RedArgs {
@@ -152,6 +164,12 @@ hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, 
 // ---- launchers (return hipError_t) ----
 hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& a, int nrhs,
                          const Launch& cfg, hipStream_t s);
+// The staggered even-odd hop with the same arguments: out = add + a * site +
+// c * sum_mu eta_mu [U chi(x + mu) - U^+ chi(x - mu)] (a, c: the up entries of
+// the coefficients), one right-hand side per work-item, reductions NONE, NORM
+// or NORM_DS.
+hipError_t launch_stag(int prec, int recon, int red, const DslashArgs& args, int nrhs, const Launch& cfg,
+                       hipStream_t s);
 
 // One Dslash launch, or a batch of nsys argument sets in device memory.
 struct DslashLaunch {
@@ -171,9 +189,13 @@ struct FinArgs {
 };
 
 // A planned Dslash launch (final arguments, grid, kernel selectors).
+// Stencil of a planned hop launch.
+enum PlanKind { PLAN_WILSON = 0, PLAN_STAG = 1 };
+
 struct DslashPlan {
     DslashArgs a;
     dim3 grid, block;
+    int kind;   // PlanKind
     int prec, recon, nr, red;
     bool dag;
     bool lnt;   // streaming link loads (one right-hand-side tile of one)
@@ -202,9 +224,13 @@ enum Blas {
     BLAS_BI_XR = 8,       // x += alpha p + omega s; r = s - omega t; red ||r||^2, <r0, r>
     BLAS_XPY = 9,         // y += x
     BLAS_NORM_DOT = 10,   // red ||x||^2, <r0, x>
+    BLAS_MS_AXPY = 11,    // x += alpha p                          (alpha of each right-hand side's Ctl)
+    BLAS_MS_P = 12,       // p = zeta z + beta p                   (zeta, beta of each Ctl)
+    BLAS_AXMY_NORM = 13,  // z -= alpha w;                         red ||z||^2
 };
 
 struct BlasArgs {
+    int kind;               // FieldKind of every operand (0: spinor, 1: colour vector)
     int Vh;
     int64_t S;
     int nsub;               // sub-fields of Vh sites each (1: parity field, 2: full lattice)
@@ -285,6 +311,8 @@ void set_recorder(Recorder* r);
 // Canonical complex128 <-> internal layouts.
 hipError_t launch_pack_spinor(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s);
 hipError_t launch_unpack_spinor(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s);
+hipError_t launch_pack_colour(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s);
+hipError_t launch_unpack_colour(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s);
 hipError_t launch_pack_gauge(int prec, int recon, const Geom& g, const void* canon, void* out, hipStream_t s);
 // Re-encode an internal FP64/18 gauge field at another precision / recon.
 hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, void* out, hipStream_t s);
@@ -294,6 +322,13 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // Initialise control blocks on the device.
 hipError_t launch_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit, hipStream_t s);
+// Multi-shift control blocks: ctl[i].sigma = shifts[i] - shifts[base],
+// ms_index = i, ms_n = n, ms_base = base (after launch_ctl_init).
+constexpr int kMaxShifts = 32;
+struct ShiftList {
+    double s[kMaxShifts];
+};
+hipError_t launch_ctl_init_shifts(Ctl* ctl, int n, int base, const ShiftList& shifts, hipStream_t s);
 // Re-open the solves whose bit is set in mask (done = 0, status = 0) after a
 // failed true-residual check.
 hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s);

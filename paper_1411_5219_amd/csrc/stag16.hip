@@ -1,0 +1,12 @@
+// FP16-storage instantiations of the even-odd staggered hop kernels.
+#include "staggered_impl.h"
+
+namespace lqcd {
+
+hipError_t launch_stag_16(int recon, int red, bool lnt, const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (recon == 12) return launch_stag_red<16, 12>(red, lnt, L, grid, block, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lqcd

@@ -68,3 +68,30 @@ class Lattice:
     def workspace(self, op, params=None):
         n = L.lqcd_workspace_bytes(self.g, op, params)
         return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def colour(self, chi, prec=64, stream=None):
+        """Canonical complex128 (V,3) or (nrhs,V,3) -> internal full-lattice colour fields."""
+        pt = torch.as_tensor(np.ascontiguousarray(chi)) if isinstance(chi, np.ndarray) else chi
+        pd = pt.to(self.device, dtype=torch.complex128).contiguous()
+        nrhs = 1 if pd.dim() == 2 else pd.shape[0]
+        out = self.empty(L.FIELD_COLOUR_FULL, prec, nrhs=nrhs)
+        L.lqcd_pack_colour(self.g, prec, nrhs, pd, out, stream)
+        return out
+
+    def unpack_colour(self, field, prec=64, nrhs=1, stream=None, numpy=True):
+        shape = (self.V, 3) if nrhs == 1 else (nrhs, self.V, 3)
+        out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        L.lqcd_unpack_colour(self.g, prec, nrhs, field, out, stream)
+        if numpy:
+            torch.cuda.synchronize(self.device)
+            return out.cpu().numpy()
+        return out
+
+    def colour_parity(self, full, parity, prec=64, nrhs=1):
+        """The parity half of full-lattice colour fields, stacked per rhs (a copy)."""
+        pb = self.nbytes(L.FIELD_COLOUR_PARITY, prec)
+        return full.view(nrhs, 2, pb)[:, parity, :].contiguous().view(-1)
+
+    def stag_workspace(self, op, nshift=0):
+        n = L.lqcd_workspace_bytes_stag(self.g, op, nshift)
+        return torch.empty(n, dtype=torch.uint8, device=self.device)

@@ -19,8 +19,8 @@ LIB_PATH = os.environ.get("LQCD_LIBRARY") or os.path.join(os.path.dirname(os.pat
 OK, EINVAL, EUNSUPPORTED, ENOCONV, EBREAKDOWN, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
 PREC_64, PREC_32, PREC_16 = 64, 32, 16
 RECON_18, RECON_12 = 18, 12
-OP_HOP, OP_SCHUR = 0, 1
-FIELD_SPINOR_PARITY, FIELD_SPINOR_FULL, FIELD_GAUGE = 0, 1, 2
+OP_HOP, OP_SCHUR, OP_NORMAL = 0, 1, 2
+FIELD_SPINOR_PARITY, FIELD_SPINOR_FULL, FIELD_GAUGE, FIELD_COLOUR_PARITY, FIELD_COLOUR_FULL = 0, 1, 2, 3, 4
 
 ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV: "ENOCONV",
                EBREAKDOWN: "EBREAKDOWN", ENONFINITE: "ENONFINITE", EHIP: "EHIP"}
@@ -29,7 +29,9 @@ ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV
 SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_set_launch",
            "lqcd_get_launch", "lqcd_autotune_dslash", "lqcd_pack_gauge",
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
-           "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch"]
+           "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
+           "lqcd_unpack_colour", "stag_apply", "stag_eo_apply", "lqcd_workspace_bytes_stag", "stag_cg_solve",
+           "stag_multishift_solve"]
 
 
 class Geom(ctypes.Structure):
@@ -39,6 +41,10 @@ class Geom(ctypes.Structure):
 class Op(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("mu", ctypes.c_double), ("prec", ctypes.c_int32),
                 ("recon", ctypes.c_int32)]
+
+
+class StagOp(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("prec", ctypes.c_int32), ("recon", ctypes.c_int32)]
 
 
 class SolveParams(ctypes.Structure):
@@ -78,6 +84,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, szp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)
     G, O, P, I = ctypes.POINTER(Geom), ctypes.POINTER(Op), ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)
+    SO = ctypes.POINTER(StagOp)
     sig = {
         "lqcd_last_error": ([], ctypes.c_char_p),
         "lqcd_version": ([], ctypes.c_char_p),
@@ -97,6 +104,14 @@ def _load():
         "lqcd_workspace_bytes_batch": ([i32, G, O, P, szp], ctypes.c_int),
         "cg_solve_batch": ([i32, G, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), P, I, vp,
                             ctypes.c_size_t, vp], ctypes.c_int),
+        "lqcd_pack_colour": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
+        "lqcd_unpack_colour": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
+        "stag_apply": ([G, SO, vp, vp, vp, i32, i32, vp], ctypes.c_int),
+        "stag_eo_apply": ([G, SO, vp, vp, vp, i32, i32, i32, vp, vp], ctypes.c_int),
+        "lqcd_workspace_bytes_stag": ([G, SO, i32, szp], ctypes.c_int),
+        "stag_cg_solve": ([G, SO, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "stag_multishift_solve": ([G, SO, vp, vp, vp, ctypes.POINTER(ctypes.c_double), i32, P, I, vp,
+                                   ctypes.c_size_t, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -262,3 +277,61 @@ def cg_solve_batch(geoms, ops, Us, bs, xs, params, ws, stream=None):
         raise LqcdError(rc, lqcd_last_error())
     flat = [i.as_dict() for i in infos]
     return rc, [flat[s * params.nrhs:(s + 1) * params.nrhs] for s in range(n)]
+
+
+# ---------------------------------------------------------------------------
+# Staggered fermions
+
+
+def stag_op(mass, prec=64, recon=18) -> StagOp:
+    return StagOp(float(mass), int(prec), int(recon))
+
+
+def lqcd_pack_colour(g, prec, nrhs, chi_canonical, out, stream=None):
+    return _check(_lib.lqcd_pack_colour(ctypes.byref(g), int(prec), int(nrhs), _ptr(chi_canonical), _ptr(out),
+                                        _stream(stream)))
+
+
+def lqcd_unpack_colour(g, prec, nrhs, inp, chi_canonical, stream=None):
+    return _check(_lib.lqcd_unpack_colour(ctypes.byref(g), int(prec), int(nrhs), _ptr(inp), _ptr(chi_canonical),
+                                          _stream(stream)))
+
+
+def stag_apply(g, o, U, inp, out, dagger=0, nrhs=1, stream=None):
+    return _check(_lib.stag_apply(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(dagger),
+                                  int(nrhs), _stream(stream)))
+
+
+def stag_eo_apply(g, o, U, inp, out, out_parity, op_kind=OP_HOP, nrhs=1, ws=None, stream=None):
+    return _check(_lib.stag_eo_apply(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out),
+                                     int(out_parity), int(op_kind), int(nrhs), _ptr(ws), _stream(stream)))
+
+
+def lqcd_workspace_bytes_stag(g, o, nshift=0) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.lqcd_workspace_bytes_stag(ctypes.byref(g), ctypes.byref(o), int(nshift), ctypes.byref(n)))
+    return n.value
+
+
+def stag_cg_solve(g, o, U, b, x, params, ws, stream=None):
+    """Returns (status, info); raises on EINVAL / EUNSUPPORTED / EHIP."""
+    info = SolveInfo()
+    nbytes = ws.numel() * ws.element_size() if hasattr(ws, "numel") else 0
+    rc = _lib.stag_cg_solve(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(b), _ptr(x), ctypes.byref(params),
+                            ctypes.byref(info), _ptr(ws), nbytes, _stream(stream))
+    if rc in (EINVAL, EUNSUPPORTED, EHIP):
+        raise LqcdError(rc, lqcd_last_error())
+    return rc, info.as_dict()
+
+
+def stag_multishift_solve(g, o, U, b, x, shifts, params, ws, stream=None):
+    """Returns (status, [info per shift]); raises on EINVAL / EUNSUPPORTED / EHIP."""
+    n = len(shifts)
+    sh = (ctypes.c_double * n)(*[float(v) for v in shifts])
+    infos = (SolveInfo * n)()
+    nbytes = ws.numel() * ws.element_size() if hasattr(ws, "numel") else 0
+    rc = _lib.stag_multishift_solve(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(b), _ptr(x), sh, n,
+                                    ctypes.byref(params), infos, _ptr(ws), nbytes, _stream(stream))
+    if rc in (EINVAL, EUNSUPPORTED, EHIP):
+        raise LqcdError(rc, lqcd_last_error())
+    return rc, [i.as_dict() for i in infos]

@@ -130,3 +130,41 @@ def test_launch_validation():
     finally:
         L.lqcd_set_launch(L.KERNEL_DSLASH, 32, **saved)
 
+
+
+def test_staggered_sizes_and_validation():
+    """Colour-field sizes follow the layout (FP64 48 B, FP32 24 B, FP16 16 B
+    per site and parity at stride S); the staggered entry points refuse bad
+    arguments before any device work."""
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((4, 4, 4, 4))
+    S = 144
+    assert L.lqcd_field_bytes(g, L.FIELD_COLOUR_PARITY, 64) == 48 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_COLOUR_FULL, 32) == 2 * 24 * S
+    assert L.lqcd_field_bytes(g, L.FIELD_COLOUR_PARITY, 16) == 16 * S
+    o = L.stag_op(0.1)
+    w0 = L.lqcd_workspace_bytes_stag(g, o, 0)
+    w8 = L.lqcd_workspace_bytes_stag(g, o, 8)
+    assert w8 > w0 > 0
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_workspace_bytes_stag(g, o, 33)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.stag_apply(g, L.stag_op(0.1, prec=16, recon=18), 16, 32, 48, stream=0)
+    assert e.value.code == L.EUNSUPPORTED
+    with pytest.raises(L.LqcdError) as e:
+        L.stag_eo_apply(g, o, 16, 32, 48, out_parity=1, op_kind=L.OP_NORMAL, ws=64, stream=0)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.stag_eo_apply(g, o, 16, 32, 48, out_parity=0, op_kind=L.OP_SCHUR, stream=0)
+    assert e.value.code == L.EINVAL
+    p = L.solve_params(tol=1e-10, eo=1, inner_prec=64)
+    for bad_op, bad_p in [(L.stag_op(0.0), p), (L.stag_op(0.1, prec=32), p),
+                          (o, L.solve_params(tol=1e-10, eo=0)), (o, L.solve_params(tol=1e-10, nrhs=2))]:
+        with pytest.raises(L.LqcdError) as e:
+            L.stag_cg_solve(g, bad_op, 16, 32, 48, bad_p, None, stream=0)
+        assert e.value.code in (L.EINVAL, L.EUNSUPPORTED)
+    for shifts in ([], [0.1] * 33, [-0.1], [float("nan")]):
+        with pytest.raises(L.LqcdError) as e:
+            L.stag_multishift_solve(g, o, 16, 32, 48, shifts, p, 64, stream=0)
+        assert e.value.code == L.EINVAL
