@@ -17,6 +17,12 @@ One step is one pass of the whole hot path on synthetic inputs:
      own eps and kappa, 4 Gaussian sources each, one batched CGNR replayed
      from a HIP graph.
 
+After the timed steps, the staggered operator (the paper's D_KS) is measured
+on the same 48^3 x 12 links: even-odd hop bursts in FP64/18, FP32/12 and
+FP16/12, the FP64 even-odd CG at m = 0.1, and the multi-shift CG with 8
+shifts against the same 8 systems solved one at a time; it is reported in
+its own block and is not part of `value`.
+
 `value` is whole-step throughput in the metric's unit: compulsory Dslash
 bytes of every hop in the step (input spinor, links, output spinor per
 output site; links counted once per batched application) divided by the
@@ -51,6 +57,11 @@ THETA = (0.0, 0.0, 0.0, math.pi)
 MULTI_L = (32, 32, 32, 8)
 UNEVEN = [((16, 16, 16, 8), 0.3, 0.15), ((20, 20, 20, 8), 0.4, 0.16), ((24, 24, 24, 8), 0.5, 0.155),
           ((32, 32, 32, 8), 0.4, 0.16)]
+# staggered: colour vector bytes per site; compulsory bytes of one even-odd hop per output site
+COLOUR_B = {64: 48, 32: 24, 16: 16}
+STAG_HOP_BYTES = {k: 2 * COLOUR_B[k[0]] + 8 * v for k, v in LINK_B.items()}
+STAG_MASS = 0.1
+STAG_SHIFTS = [0.0] + [float(v) for v in (1e-4, 4.6e-4, 2.2e-3, 1e-2, 4.6e-2, 0.22, 1.0)]
 
 
 def log(msg):
@@ -130,6 +141,81 @@ def recorded_traffic(workload):
     return t, f"{os.path.relpath(path, ROOT)}: read {float(vals['read_bytes']):.4g} B + write {float(vals['write_bytes']):.4g} B"
 
 
+def staggered(lat, U, b_colour, stream, hops, log):
+    """The staggered hop bursts, CG and multi-shift CG on one lattice."""
+    import numpy as np
+    import torch
+
+    from paper_1411_5219_amd import lqcd
+
+    Vh = lat.V // 2
+    out = {"mass": STAG_MASS}
+    with torch.cuda.stream(stream):
+        bd = lat.colour(b_colour)
+        hop_stats = {}
+        for k in [(64, 18), (32, 12), (16, 12)]:
+            Uk = lat.gauge(U, k[0], k[1])
+            src = lat.colour_parity(lat.colour(b_colour, k[0]), 1, k[0])
+            dst = lat.empty(lqcd.FIELD_COLOUR_PARITY, k[0])
+            o = lqcd.stag_op(STAG_MASS, k[0], k[1])
+            for _ in range(3):
+                lqcd.stag_eo_apply(lat.g, o, Uk, src, dst, 0, stream=stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(hops):
+                lqcd.stag_eo_apply(lat.g, o, Uk, src, dst, 0, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) / hops * 1e3
+            gbs = Vh * STAG_HOP_BYTES[k] / (us * 1e-6) / 1e9
+            hop_stats[f"fp{k[0]}_{k[1]}"] = {"avg_launch_us": us, "bytes_per_launch": Vh * STAG_HOP_BYTES[k],
+                                             "GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+            del Uk
+        out["hop"] = hop_stats
+        o = lqcd.stag_op(STAG_MASS)
+        U64 = lat.gauge(U)
+        x = lat.zeros(lqcd.FIELD_COLOUR_FULL, 64)
+        ws = lat.stag_workspace(o)
+        p = lqcd.solve_params(tol=1e-10, maxiter=100000, eo=1, inner_prec=64, use_graph=1)
+        cg = []
+        for _ in range(3):
+            rc, info = lqcd.stag_cg_solve(lat.g, o, U64, bd, x, p, ws, stream=stream)
+            if rc != 0:
+                raise RuntimeError(f"staggered CG failed: {info}")
+            cg.append(info)
+        log(f"staggered CG: {cg[-1]['iters']} iterations, {cg[-1]['seconds'] * 1e3:.1f} ms")
+        out["cg"] = {"seconds_median": float(np.median([i["seconds"] for i in cg])), "iters": cg[-1]["iters"],
+                     "true_resid": cg[-1]["true_resid"], "tol": 1e-10}
+        n = len(STAG_SHIFTS)
+        be = lat.colour_parity(bd, 0)
+        xs = lat.zeros(lqcd.FIELD_COLOUR_PARITY, 64, nrhs=n)
+        wsm = lat.stag_workspace(o, n)
+        ms = []
+        for _ in range(2):
+            rc, infos = lqcd.stag_multishift_solve(lat.g, o, U64, be, xs, STAG_SHIFTS, p, wsm, stream=stream)
+            if rc != 0:
+                raise RuntimeError(f"multi-shift CG failed: {infos}")
+            ms.append(infos)
+        x1 = lat.zeros(lqcd.FIELD_COLOUR_PARITY, 64)
+        ws1 = lat.stag_workspace(o, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sh in STAG_SHIFTS:
+            rc, info1 = lqcd.stag_multishift_solve(lat.g, o, U64, be, x1, [sh], p, ws1, stream=stream)
+            if rc != 0:
+                raise RuntimeError(f"single-shift CG failed: {info1}")
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - t0
+        med = float(np.median([i[0]["seconds"] for i in ms]))
+        out["multishift"] = {"shifts": STAG_SHIFTS, "rhs": "N = m^2 - D_eo D_oe on even sites, Gaussian source",
+                             "seconds_median": med, "iters": [i["iters"] for i in ms[-1]],
+                             "true_resid_max": max(i["true_resid"] for i in ms[-1]),
+                             "separate_solves_seconds": t_sep, "speedup_vs_separate": t_sep / med}
+        log(f"multi-shift CG: {med * 1e3:.1f} ms vs {t_sep * 1e3:.1f} ms separately")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +284,12 @@ def main():
             for k, Uk in Ug.items():
                 for _ in range(5):
                     lqcd.dslash_eo_apply(lat.g, ops[k], Uk, hop_in[k], hop_out[k], 0, lqcd.OP_HOP, 0, stream=stream)
+            # the staggered FP64/18 hop on the same links
+            chi = np.asarray(b)[:, 0, :].copy()
+            sin = lat.colour_parity(lat.colour(chi), 1)
+            sout = lat.empty(lqcd.FIELD_COLOUR_PARITY, 64)
+            for _ in range(5):
+                lqcd.stag_eo_apply(lat.g, lqcd.stag_op(STAG_MASS), Ug[(64, 18)], sin, sout, 0, stream=stream)
             a = torch.empty((1 << 30) // 4, dtype=torch.float32, device=dev)
             c = torch.empty_like(a)
             a.fill_(1.0)
@@ -311,6 +403,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
+    log("staggered operator")
+    stag = staggered(lat, U, np.asarray(b)[:, 0, :].copy(), stream, args.hops, log)
+
     hop_stats = {}
     for k, evs in rec["hops"].items():
         ms = sum(a.elapsed_time(b_) for a, b_ in evs) / (len(evs) * args.hops)
@@ -372,6 +467,7 @@ def main():
         "solves": solve_stats,
         "multi_rhs": multi,
         "uneven_batch": uneven,
+        "staggered": stag,
         "device": torch.cuda.get_device_properties(0).name,
     }
     if not args.no_cpu_baseline:

@@ -130,12 +130,15 @@ typedef struct {
     double hops_inner;         /* same, at the inner precision (mixed precision only) */
 } lqcd_solve_info;
 
-/* Launch configuration of a kernel family at one storage precision:
+/* Launch configuration of a kernel family (LQCD_KERNEL_DSLASH: the Wilson
+ * hop; LQCD_KERNEL_STAG: the staggered hop, which ignores rhs_tile and
+ * rhs_group; LQCD_KERNEL_BLAS: the site-local kernels) at one storage
+ * precision:
  *   block   work-items per block (64, 128, 192 or 256; with order = 1 the
  *           requested size, the block then holds whole x-rows)
  *   swizzle 1: block indices are remapped so that each of the 8 XCDs works
  *           on a contiguous range of blocks
- *   order   Dslash only.  0: blocks walk the sites in memory order;
+ *   order   hop kernels only.  0: blocks walk the sites in memory order;
  *           1: a block covers whole x-rows at one (z, t) and blocks run
  *           t fastest, then z, so neighbour spinors are reused from the
  *           XCD's L2 cache; k in 2..64: the same row blocks in z-slabs of
@@ -156,7 +159,7 @@ typedef struct {
     int32_t rhs_group;
 } lqcd_launch;
 
-enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1 };
+enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1, LQCD_KERNEL_STAG = 2 };
 
 /* Message of the last error on this thread ("" if none). */
 LQCD_API const char* lqcd_last_error(void);

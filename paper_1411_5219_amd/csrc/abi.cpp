@@ -130,8 +130,11 @@ std::mutex g_launch_mu;
 // blocks for the site-local kernels.
 // Several right-hand sides: FP64 tiles of 2 in groups of 2, FP32 single
 // right-hand sides in groups of 4, FP16 tiles of 2 in groups of 4.
-Launch g_launch[2][3] = {{{256, 1, 1, 2, 2}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
-                         {{256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}}};
+// The staggered hop (colour vectors of 48 / 24 / 16 bytes) gains less from
+// neighbour reuse: memory order in FP64, row tiles of 192 in FP32 and FP16.
+Launch g_launch[3][3] = {{{256, 1, 1, 2, 2}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
+                         {{256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}},
+                         {{256, 1, 0, 1, 0}, {192, 1, 1, 1, 0}, {192, 1, 1, 1, 0}}};
 
 int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
 
@@ -1113,7 +1116,7 @@ struct StagOp {
     RedScratch rs;
     Launch dcfg, bcfg;
 
-    void tune() { dcfg = launch_for(LQCD_KERNEL_DSLASH, prec); bcfg = launch_for(LQCD_KERNEL_BLAS, prec); }
+    void tune() { dcfg = launch_for(LQCD_KERNEL_STAG, prec); bcfg = launch_for(LQCD_KERNEL_BLAS, prec); }
 
     DslashArgs base(Ctl* ctl) const
     {
@@ -1347,7 +1350,8 @@ int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, const lqcd_so
 
 int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
 {
-    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS) return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS && kernel != LQCD_KERNEL_STAG)
+        return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
     const int k = prec_slot(prec);
     if (k < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
     if (!cfg) return set_error(LQCD_EINVAL, "cfg is NULL");
@@ -1355,7 +1359,8 @@ int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
         return set_error(LQCD_EINVAL, "block %d not in {64, 128, 192, 256}", cfg->block);
     if (cfg->swizzle != 0 && cfg->swizzle != 1) return set_error(LQCD_EINVAL, "swizzle must be 0 or 1");
     if (cfg->order < 0 || cfg->order > 64) return set_error(LQCD_EINVAL, "order must be in 0..64");
-    if (cfg->order >= 1 && kernel != LQCD_KERNEL_DSLASH) return set_error(LQCD_EINVAL, "order >= 1 applies to the Dslash only");
+    if (cfg->order >= 1 && kernel == LQCD_KERNEL_BLAS)
+        return set_error(LQCD_EINVAL, "order >= 1 applies to the hop kernels only");
     if (cfg->rhs_tile != 1 && cfg->rhs_tile != 2 && cfg->rhs_tile != 4)
         return set_error(LQCD_EINVAL, "rhs_tile %d not in {1, 2, 4}", cfg->rhs_tile);
     if (cfg->rhs_group != 0 && (cfg->rhs_group < 2 || cfg->rhs_group > 16))
@@ -1367,7 +1372,8 @@ int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
 
 int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
 {
-    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS) return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS && kernel != LQCD_KERNEL_STAG)
+        return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
     const int k = prec_slot(prec);
     if (k < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
     if (!cfg) return set_error(LQCD_EINVAL, "cfg is NULL");

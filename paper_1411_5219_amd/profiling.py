@@ -33,7 +33,7 @@ import sys
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/dslash_impl.h", "csrc/dslash.hip", "csrc/lqcd_device.h", "csrc/lqcd_kernels.h"]
+KERNEL_SOURCES = ["csrc/dslash_impl.h", "csrc/block_order.h", "csrc/dslash.hip", "csrc/lqcd_device.h", "csrc/lqcd_kernels.h"]
 
 
 def kernel_source_digest() -> str:

@@ -57,16 +57,16 @@ def test_full_M(mods, L4, theta, prec, recon, dagger):
     Ud = lat.gauge(U, prec, recon)
     inp = lat.colour(chi, prec)
     ref = S.apply_M(U, chi, L4, theta, mass, dagger=bool(dagger))
-    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_STAG, prec)
     try:
         for cfg in LAUNCHES:
-            lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **cfg)
+            lqcd.lqcd_set_launch(lqcd.KERNEL_STAG, prec, **cfg)
             out = lat.empty(lqcd.FIELD_COLOUR_FULL, prec)
             lqcd.stag_apply(lat.g, lqcd.stag_op(mass, prec, recon), Ud, inp, out, dagger=dagger)
             err = site_rel_err(lat.unpack_colour(out, prec), ref, 3)
             assert err <= TOL[prec], (cfg, err)
     finally:
-        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
+        lqcd.lqcd_set_launch(lqcd.KERNEL_STAG, prec, **saved)
 
 
 @pytest.mark.parametrize("L4,theta", LATTICES[1:3])
