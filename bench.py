@@ -216,6 +216,74 @@ def staggered(lat, U, b_colour, stream, hops, log):
     return out
 
 
+SWEEP = [(16, 16, 16, 8), (24, 24, 24, 8), (32, 32, 32, 8), (48, 48, 48, 12), (64, 64, 64, 16)]
+
+
+def sweep(stream, hops):
+    """Even-odd hop rate per lattice size and storage (compulsory bytes per
+    launch over the event-timed mean launch), Wilson and staggered, unit
+    links (the traffic does not depend on the link values), and the CPU
+    oracle's full-lattice hop on the same host (one application, all cores)
+    in the same accounting: a full-lattice hop is two even-odd hops."""
+    import numpy as np
+    import torch
+
+    from lattice_inputs import gaussian_spinor, unit_gauge
+    from oracle import staggered as OS
+    from oracle import wilson as OW
+    from paper_1411_5219_amd import fields, lqcd
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(hops):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / hops * 1e3
+
+    rows = []
+    for L in SWEEP:
+        log(f"sweep {L}")
+        lat = fields.Lattice(L, THETA, device=torch.device("cuda:0"))
+        Vh = lat.V // 2
+        U = unit_gauge(L)
+        psi = gaussian_spinor(L, seed=2009)
+        chi = np.ascontiguousarray(psi[:, 0, :])
+        row = {"lattice": list(L)}
+        with torch.cuda.stream(stream):
+            for k in [(64, 18), (32, 12), (16, 12)]:
+                Uk = lat.gauge(U, k[0], k[1])
+                src = lat.parity_view(lat.spinor(psi, k[0]), 1, k[0])
+                dst = lat.empty(lqcd.FIELD_SPINOR_PARITY, k[0])
+                o = lqcd.op(0.16, 0.005, k[0], k[1])
+                us = timed(lambda: lqcd.dslash_eo_apply(lat.g, o, Uk, src, dst, 0, stream=stream))
+                row[f"wilson_fp{k[0]}_{k[1]}"] = {"us": us, "GBps": Vh * HOP_BYTES[k] / us / 1e3}
+                ssrc = lat.colour_parity(lat.colour(chi, k[0]), 1, k[0])
+                sdst = lat.empty(lqcd.FIELD_COLOUR_PARITY, k[0])
+                so = lqcd.stag_op(STAG_MASS, k[0], k[1])
+                us = timed(lambda: lqcd.stag_eo_apply(lat.g, so, Uk, ssrc, sdst, 0, stream=stream))
+                row[f"stag_fp{k[0]}_{k[1]}"] = {"us": us, "GBps": Vh * STAG_HOP_BYTES[k] / us / 1e3}
+                del Uk, src, dst, ssrc, sdst
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        OW.hop(U, psi, L, THETA)
+        t = time.perf_counter() - t0
+        row["oracle_wilson_fp64"] = {"s": t, "GBps": 2 * Vh * HOP_BYTES[(64, 18)] / t / 1e9}
+        t0 = time.perf_counter()
+        OS.hop(U, chi, L, THETA)
+        t = time.perf_counter() - t0
+        row["oracle_stag_fp64"] = {"s": t, "GBps": 2 * Vh * STAG_HOP_BYTES[(64, 18)] / t / 1e9}
+        row["oracle_cores"] = OW.num_threads()
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del lat
+    print(json.dumps({"sweep": rows, "device": torch.cuda.get_device_properties(0).name}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +295,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--profile-hops", action="store_true",
                     help="only run the Dslash hops of each precision and a 1 GiB copy (for counter passes)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the hop rate per lattice size (16^3x8 .. 64^3x16), Wilson and staggered, "
+                         "with the CPU oracle's hop beside it")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -246,6 +317,9 @@ def main():
     # one non-default stream for everything: the HIP events sit on the stream
     # the kernels run on, and the graph-replayed batch may capture on it
     stream = torch.cuda.Stream(device=dev)
+    if args.sweep:
+        sweep(stream, args.hops)
+        return
     L = WORKLOADS[args.workload]
     kappa, mu, eps, tol = 0.16, 0.005, 0.4, 1e-10
     Vh = int(np.prod(L)) // 2

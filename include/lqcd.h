@@ -292,6 +292,13 @@ LQCD_API int stag_apply(const lqcd_geom* geom, const lqcd_stag_op* op, const voi
 LQCD_API int stag_eo_apply(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out,
                            int32_t out_parity, int32_t op_kind, int32_t nrhs, void* ws, void* stream);
 
+/* Times the staggered even-odd hop (LQCD_OP_HOP, out_parity 0, nrhs 1) in
+ * the same 16 launch shapes as lqcd_autotune_dslash and keeps the fastest
+ * for LQCD_KERNEL_STAG at op->prec; in and out are parity colour fields
+ * (scratch; out is overwritten).  Synchronises stream. */
+LQCD_API int lqcd_autotune_stag(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in,
+                                void* out, int32_t reps, void* stream, lqcd_launch* best, double* best_us);
+
 /* Device workspace (bytes) of stag_cg_solve (nshift = 0) or of
  * stag_multishift_solve with nshift shifts (1..32). */
 LQCD_API int lqcd_workspace_bytes_stag(const lqcd_geom* geom, const lqcd_stag_op* op, int32_t nshift, size_t* bytes);

@@ -1086,6 +1086,65 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
 }
 
 
+// Times the even-odd hop of one kernel family (launch(cfg) enqueues one hop
+// with launch shape cfg) in the 16 shapes {memory order, row tiles} x {XCD
+// remap off, on} x block {64, 128, 192, 256} with HIP events, keeps the
+// fastest in the process-wide table (the right-hand-side tile and group of
+// the family are kept: they only matter for several right-hand sides) and
+// reports it.  Synchronises the stream.
+template <class F>
+int autotune_hop(int kernel, int prec, int reps, hipStream_t s, lqcd_launch* best, double* best_us, F&& launch)
+{
+    hipEvent_t e0, e1;
+    LQCD_HIP(hipEventCreate(&e0));
+    LQCD_HIP(hipEventCreate(&e1));
+    Launch win{};
+    float win_ms = 0.f;
+    bool have = false;
+    int result = LQCD_OK;
+    for (int order = 0; order < 2 && !result; ++order)
+        for (int sw = 0; sw < 2 && !result; ++sw)
+            for (int blk = 64; blk <= 256 && !result; blk += 64) {
+                const Launch cfg{blk, sw, order, 1, 0};
+                hipError_t e = hipSuccess;
+                for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch(cfg);
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch(cfg);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    result = set_error(LQCD_EHIP, "autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                if (!have || ms < win_ms) {
+                    have = true;
+                    win_ms = ms;
+                    win = cfg;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result) return result;
+    {
+        std::lock_guard<std::mutex> lk(g_launch_mu);
+        Launch& slot = g_launch[kernel][prec_slot(prec)];
+        win.rhs_tile = slot.rhs_tile;
+        win.rhs_group = slot.rhs_group;
+        slot = win;
+    }
+    if (best) {
+        best->block = win.block;
+        best->swizzle = win.swizzle;
+        best->order = win.order;
+        best->rhs_tile = win.rhs_tile;
+        best->rhs_group = win.rhs_group;
+    }
+    if (best_us) *best_us = 1e3 * win_ms / reps;
+    return LQCD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Staggered fermions: the operator compositions and the (multi-shift) CG.
 
@@ -1406,58 +1465,36 @@ int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U
     o.nrhs = 1;
     o.pb = parity_bytes(g, op->prec);
     o.s = static_cast<hipStream_t>(stream);
-    hipEvent_t e0, e1;
-    LQCD_HIP(hipEventCreate(&e0));
-    LQCD_HIP(hipEventCreate(&e1));
-    Launch win{};
-    float win_ms = 0.f;
-    bool have = false;
-    int result = LQCD_OK;
-    for (int order = 0; order < 2 && !result; ++order)
-        for (int sw = 0; sw < 2 && !result; ++sw)
-            for (int blk = 64; blk <= 256 && !result; blk += 64) {
-                o.dcfg = Launch{blk, sw, order, 1, 0};
-                hipError_t e = hipSuccess;
-                for (int i = 0; i < 2 && e == hipSuccess; ++i)
-                    e = o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
-                              PRED_ALWAYS);
-                if (e == hipSuccess) e = hipEventRecord(e0, o.s);
-                for (int i = 0; i < reps && e == hipSuccess; ++i)
-                    e = o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
-                              PRED_ALWAYS);
-                if (e == hipSuccess) e = hipEventRecord(e1, o.s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) {
-                    result = set_error(LQCD_EHIP, "autotune: %s", hipGetErrorString(e));
-                    break;
-                }
-                if (!have || ms < win_ms) {
-                    have = true;
-                    win_ms = ms;
-                    win = o.dcfg;
-                }
-            }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (result) return result;
-    {
-        // the right-hand-side tile is kept: it only matters for nrhs > 1
-        std::lock_guard<std::mutex> lk(g_launch_mu);
-        win.rhs_tile = g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)].rhs_tile;
-        win.rhs_group = g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)].rhs_group;
-        g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)] = win;
-    }
-    if (best) {
-        best->block = win.block;
-        best->swizzle = win.swizzle;
-        best->order = win.order;
-        best->rhs_tile = win.rhs_tile;
-        best->rhs_group = win.rhs_group;
-    }
-    if (best_us) *best_us = 1e3 * win_ms / reps;
-    return LQCD_OK;
+    return autotune_hop(LQCD_KERNEL_DSLASH, op->prec, reps, o.s, best, best_us, [&](const Launch& cfg) {
+        o.dcfg = cfg;
+        return o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
+                     PRED_ALWAYS);
+    });
+}
+
+int lqcd_autotune_stag(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out,
+                       int32_t reps, void* stream, lqcd_launch* best, double* best_us)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_stag_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (reps < 1 || reps > 10000) return set_error(LQCD_EINVAL, "reps %d out of range", reps);
+    StagOp o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.mass = op->mass;
+    o.nrhs = 1;
+    o.pb = colour_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    return autotune_hop(LQCD_KERNEL_STAG, op->prec, reps, o.s, best, best_us, [&](const Launch& cfg) {
+        o.dcfg = cfg;
+        return o.hop(0, in, out, 0.5, nullptr, 0.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, nullptr);
+    });
 }
 
 int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,

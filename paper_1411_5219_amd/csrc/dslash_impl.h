@@ -454,17 +454,12 @@ k_dslash_eo_batch(const DslashArgs* __restrict__ tab,
     dslash_block<PREC, RECON, DAG, RED, NR, LNT>(tab[s], bx, tab[s].gx, blockIdx.y);
 }
 
-#ifndef LQCD_DSLASH_LDS_PAD
-#define LQCD_DSLASH_LDS_PAD 0
-#endif
-
 template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
 static hipError_t launch_one(const DslashLaunch& L, dim3 grid, dim3 block, hipStream_t s)
 {
-    constexpr unsigned pad = LQCD_DSLASH_LDS_PAD;
     if (L.tab)
-        hipLaunchKernelGGL((k_dslash_eo_batch<PREC, RECON, DAG, RED, NR, LNT>), grid, block, pad, s, L.tab, L.offs, L.nsys);
-    else hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED, NR, LNT>), grid, block, pad, s, *L.a);
+        hipLaunchKernelGGL((k_dslash_eo_batch<PREC, RECON, DAG, RED, NR, LNT>), grid, block, 0, s, L.tab, L.offs, L.nsys);
+    else hipLaunchKernelGGL((k_dslash_eo<PREC, RECON, DAG, RED, NR, LNT>), grid, block, 0, s, *L.a);
     return hipGetLastError();
 }
 

@@ -202,3 +202,34 @@ def test_multishift(mods, shifts, use_graph):
         rel = np.linalg.norm((x - xs_ref[i]).ravel()) / np.linalg.norm(xs_ref[i].ravel())
         assert rel < 1e-6, (i, rel)
         assert abs(infos[i]["iters"] - out_ref[i][0]) <= 2, (infos[i], out_ref[i])
+
+
+def test_launch_shapes_bitwise_and_autotune(mods):
+    """Every launch shape of the staggered hop gives the same bits (the
+    per-site arithmetic does not depend on the shape); the autotuner keeps
+    one of them."""
+    torch, fields, lqcd = mods
+    L4, theta = (8, 6, 10, 4), (0.0, 0.0, 0.0, math.pi)
+    U, chi = _setup(L4, seed=9, kind="exp")
+    lat = fields.Lattice(L4, theta)
+    o = lqcd.stag_op(0.1)
+    Ud = lat.gauge(U)
+    src = lat.colour_parity(lat.colour(chi), 1)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_STAG, 64)
+    try:
+        outs = []
+        for order in (0, 1, 3):
+            for sw in (0, 1):
+                for blk in (64, 128, 192, 256):
+                    lqcd.lqcd_set_launch(lqcd.KERNEL_STAG, 64, blk, sw, order)
+                    out = lat.zeros(lqcd.FIELD_COLOUR_PARITY, 64)
+                    lqcd.stag_eo_apply(lat.g, o, Ud, src, out, 0)
+                    outs.append(out)
+        torch.cuda.synchronize()
+        for out in outs[1:]:
+            assert torch.equal(out, outs[0])
+        scratch = lat.zeros(lqcd.FIELD_COLOUR_PARITY, 64)
+        best, us = lqcd.lqcd_autotune_stag(lat.g, o, Ud, src, scratch, reps=3)
+        assert lqcd.lqcd_get_launch(lqcd.KERNEL_STAG, 64) == best and us > 0
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_STAG, 64, **saved)
