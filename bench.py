@@ -424,6 +424,9 @@ def main():
 
     def step(rec):
         byts = hops(rec.get("hops") if rec is not None else None)
+        # a solve's reported time runs from its call to its return: let the
+        # queued hop bursts finish first so that they are not counted in it
+        stream.synchronize()
         for n, p in solves.items():
             rc, info = lqcd.cg_solve(lat.g, o64, Ug[(64, 18)], bd, xs[n], p, ws[n], stream=stream)
             check(rc, info, n)

@@ -193,6 +193,15 @@ LQCD_API int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg);
 LQCD_API int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                                   int32_t reps, void* stream, lqcd_launch* best, double* best_us);
 
+/* For several right-hand sides: with the block shape of LQCD_KERNEL_DSLASH at
+ * op->prec kept, times the even-odd hop on nrhs (2..16) stacked parity
+ * fields for every right-hand-side tile compiled (1, 2, 4; FP64 1, 2) and
+ * group (0, 2, 4, 8, 16) and keeps the fastest tile and group in the table.
+ * best_us: mean time of one launch over all nrhs.  Synchronises stream. */
+LQCD_API int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in,
+                                      void* out, int32_t nrhs, int32_t reps, void* stream, lqcd_launch* best,
+                                      double* best_us);
+
 /* Canonical complex128 gauge field (device) -> internal layout at prec/recon. */
 LQCD_API int lqcd_pack_gauge(const lqcd_geom* geom, int32_t prec, int32_t recon, const void* U_canonical, void* U_out,
                     void* stream);

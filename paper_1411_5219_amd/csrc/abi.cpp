@@ -1472,6 +1472,87 @@ int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U
     });
 }
 
+int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                             int32_t nrhs, int32_t reps, void* stream, lqcd_launch* best, double* best_us)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (nrhs < 2 || nrhs > kMaxRhs) return set_error(LQCD_EINVAL, "nrhs %d not in [2, %d]", nrhs, kMaxRhs);
+    if (reps < 1 || reps > 10000) return set_error(LQCD_EINVAL, "reps %d out of range", reps);
+    Op o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.kappa = op->kappa;
+    o.mu = op->mu;
+    o.nrhs = nrhs;
+    o.pb = parity_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    const Launch shape = launch_for(LQCD_KERNEL_DSLASH, op->prec);
+    hipEvent_t e0, e1;
+    LQCD_HIP(hipEventCreate(&e0));
+    LQCD_HIP(hipEventCreate(&e1));
+    Launch win = shape;
+    float win_ms = 0.f;
+    bool have = false;
+    int result = LQCD_OK;
+    const int tiles[3] = {1, 2, 4};
+    const int groups[5] = {0, 2, 4, 8, 16};
+    for (int ti = 0; ti < 3 && !result; ++ti) {
+        if (dslash_rhs_tile(op->prec, tiles[ti], nrhs) != tiles[ti]) continue;  // not compiled / larger than nrhs
+        for (int gi = 0; gi < 5 && !result; ++gi) {
+            Launch cfg = shape;
+            cfg.rhs_tile = tiles[ti];
+            cfg.rhs_group = groups[gi];
+            o.dcfg = cfg;
+            auto hop = [&]() {
+                return o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
+                             PRED_ALWAYS);
+            };
+            hipError_t e = hipSuccess;
+            for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hop();
+            if (e == hipSuccess) e = hipEventRecord(e0, o.s);
+            for (int i = 0; i < reps && e == hipSuccess; ++i) e = hop();
+            if (e == hipSuccess) e = hipEventRecord(e1, o.s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                result = set_error(LQCD_EHIP, "autotune: %s", hipGetErrorString(e));
+                break;
+            }
+            if (!have || ms < win_ms) {
+                have = true;
+                win_ms = ms;
+                win = cfg;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result) return result;
+    {
+        std::lock_guard<std::mutex> lk(g_launch_mu);
+        Launch& slot = g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)];
+        slot.rhs_tile = win.rhs_tile;
+        slot.rhs_group = win.rhs_group;
+    }
+    if (best) {
+        best->block = win.block;
+        best->swizzle = win.swizzle;
+        best->order = win.order;
+        best->rhs_tile = win.rhs_tile;
+        best->rhs_group = win.rhs_group;
+    }
+    if (best_us) *best_us = 1e3 * win_ms / reps;
+    return LQCD_OK;
+}
+
 int lqcd_autotune_stag(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* in, void* out,
                        int32_t reps, void* stream, lqcd_launch* best, double* best_us)
 {

@@ -31,7 +31,7 @@ SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspac
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
            "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
            "lqcd_unpack_colour", "stag_apply", "stag_eo_apply", "lqcd_workspace_bytes_stag", "stag_cg_solve",
-           "stag_multishift_solve", "lqcd_autotune_stag"]
+           "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs"]
 
 
 class Geom(ctypes.Structure):
@@ -111,6 +111,8 @@ def _load():
         "lqcd_workspace_bytes_stag": ([G, SO, i32, szp], ctypes.c_int),
         "lqcd_autotune_stag": ([G, SO, vp, vp, vp, i32, vp, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int),
+        "lqcd_autotune_dslash_rhs": ([G, O, vp, vp, vp, i32, i32, vp, ctypes.POINTER(Launch),
+                                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "stag_cg_solve": ([G, SO, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "stag_multishift_solve": ([G, SO, vp, vp, vp, ctypes.POINTER(ctypes.c_double), i32, P, I, vp,
                                    ctypes.c_size_t, vp], ctypes.c_int),
@@ -344,5 +346,15 @@ def lqcd_autotune_stag(g, o, U, inp, out, reps=10, stream=None):
     us = ctypes.c_double()
     _check(_lib.lqcd_autotune_stag(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(reps),
                                    _stream(stream), ctypes.byref(best), ctypes.byref(us)))
+    return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
+             "rhs_group": best.rhs_group}, us.value)
+
+
+def lqcd_autotune_dslash_rhs(g, o, U, inp, out, nrhs, reps=10, stream=None):
+    """Tunes the right-hand-side tile and group for nrhs stacked fields; returns (launch, us per launch)."""
+    best = Launch()
+    us = ctypes.c_double()
+    _check(_lib.lqcd_autotune_dslash_rhs(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(nrhs),
+                                         int(reps), _stream(stream), ctypes.byref(best), ctypes.byref(us)))
     return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
              "rhs_group": best.rhs_group}, us.value)

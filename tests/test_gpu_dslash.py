@@ -152,6 +152,40 @@ def test_multi_rhs_equals_single(mods, prec, recon, tile, group):
         lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
 
 
+@pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
+def test_rhs_autotune(mods, prec, recon):
+    """The right-hand-side autotuner keeps the block shape, installs one of the
+    compiled tiles and groups, and the tuned even-odd hop of 6 right-hand
+    sides still equals the oracle's hop of each."""
+    torch, fields, lqcd = mods
+    L4, theta = (8, 6, 10, 4), (0.0, 0.0, 0.0, math.pi)
+    U, psi = _setup(L4, theta, seed=4, kind="exp", nrhs=6)
+    print(f"\n[case] rhs autotune prec={prec}", flush=True)
+    lat = fields.Lattice(L4, theta)
+    o = lqcd.op(0.16, 0.005, prec, recon)
+    Ud = lat.gauge(U, prec, recon)
+    src = lat.parity_view(lat.spinor(psi, prec), 1, prec, nrhs=6)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+    try:
+        scratch = lat.empty(lqcd.FIELD_SPINOR_PARITY, prec, nrhs=6)
+        best, us = lqcd.lqcd_autotune_dslash_rhs(lat.g, o, Ud, src, scratch, 6, reps=3)
+        now = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+        assert now == best and us > 0
+        assert {k: now[k] for k in ("block", "swizzle", "order")} == {k: saved[k] for k in ("block", "swizzle", "order")}
+        assert now["rhs_tile"] in ((1, 2) if prec == 64 else (1, 2, 4)) and now["rhs_group"] in (0, 2, 4, 8, 16)
+        out = lat.zeros(lqcd.FIELD_SPINOR_FULL, prec, nrhs=6)
+        pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, prec)
+        even = lat.zeros(lqcd.FIELD_SPINOR_PARITY, prec, nrhs=6)
+        lqcd.dslash_eo_apply(lat.g, o, Ud, src, even, 0, nrhs=6)
+        out.view(6, 2, pb)[:, 0, :] = even.view(6, pb)
+        got = lat.unpack(out, prec, nrhs=6)
+        for k in range(6):
+            ref = W.hop_eo(U, psi[k], L4, theta, 0)
+            assert site_rel_err(got[k], ref) <= TOL[prec], k
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
+
+
 def test_pack_roundtrip(mods):
     torch, fields, lqcd = mods
     L4 = (6, 4, 6, 10)
