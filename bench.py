@@ -21,7 +21,10 @@ After the timed steps, the staggered operator (the paper's D_KS) is measured
 on the same 48^3 x 12 links: even-odd hop bursts in FP64/18, FP32/12 and
 FP16/12, the FP64 even-odd CG at m = 0.1, and the multi-shift CG with 8
 shifts against the same 8 systems solved one at a time; it is reported in
-its own block and is not part of `value`.
+its own block and is not part of `value`.  So is the N_f = 2 twisted-mass
+pseudo-fermion force on the same lattice: the force kernel alone (HIP
+events) and one whole force evaluation as an HMC step makes it (two mixed
+FP32/12 solves to 1e-10 and the kernel).
 
 `value` is whole-step throughput in the metric's unit: compulsory Dslash
 bytes of every hop in the step (input spinor, links, output spinor per
@@ -216,6 +219,69 @@ def staggered(lat, U, b_colour, stream, hops, log):
     return out
 
 
+FORCE_BYTES = 2 * 192 + 4 * 144 + 4 * 9 * 16  # X, Wf in; four links; four 3x3 complex128 out
+
+
+def tm_force(lat, U, b, kappa, mu, stream, log, launches=20):
+    """The N_f = 2 pseudo-fermion force: the force kernel alone, then one whole
+    evaluation (X = M^-1 phi, Wf = M(-mu)^-1 gamma_5 X, kernel) as an HMC
+    step makes it, with mixed FP32/12 solves to 1e-10."""
+    import numpy as np
+    import torch
+
+    from paper_1411_5219_amd import lqcd
+
+    V = lat.V
+    o = lqcd.op(kappa, mu)
+    om = lqcd.op(kappa, -mu)
+    p = lqcd.solve_params(tol=1e-10, maxiter=100000, eo=1, inner_prec=32, inner_recon=12)
+    with torch.cuda.stream(stream):
+        Ud = lat.gauge(U)
+        phi = lat.spinor(b)
+        X = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+        Wf = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+        tmp = lat.empty(lqcd.FIELD_SPINOR_FULL, 64)
+        ws = lat.workspace(o, p)
+        F = torch.zeros((4, V, 3, 3), dtype=torch.complex128, device=lat.device)
+
+    def evaluate():
+        rc, i1 = lqcd.cg_solve(lat.g, o, Ud, phi, X, p, ws, stream=stream)
+        if rc != 0:
+            raise RuntimeError(f"force solve X failed: {i1}")
+        lqcd.lqcd_gamma5(lat.g, X, tmp, stream=stream)
+        rc, i2 = lqcd.cg_solve(lat.g, om, Ud, tmp, Wf, p, ws, stream=stream)
+        if rc != 0:
+            raise RuntimeError(f"force solve Wf failed: {i2}")
+        lqcd.tm_force(lat.g, o, Ud, X, Wf, F, stream=stream)
+        return i1[0], i2[0]
+
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        i1, i2 = evaluate()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    for _ in range(3):
+        lqcd.tm_force(lat.g, o, Ud, X, Wf, F, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        lqcd.tm_force(lat.g, o, Ud, X, Wf, F, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) / launches * 1e3
+    gbs = V * FORCE_BYTES / (us * 1e-6) / 1e9
+    out = {"kernel": {"name": "k_tm_force<18>", "avg_launch_us": us, "bytes_per_launch": V * FORCE_BYTES,
+                      "GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS},
+           "evaluation": {"seconds_median": float(np.median(times)), "solves": "mixed FP32/12, tol 1e-10",
+                          "iters": [i1["iters"], i2["iters"]], "true_resid": [i1["true_resid"], i2["true_resid"]],
+                          "solve_seconds": [i1["seconds"], i2["seconds"]]}}
+    log(f"tm force kernel {us:.1f} us ({gbs:.0f} GB/s); evaluation {out['evaluation']['seconds_median'] * 1e3:.1f} ms")
+    return out
+
+
 SWEEP = [(16, 16, 16, 8), (24, 24, 24, 8), (32, 32, 32, 8), (48, 48, 48, 12), (64, 64, 64, 16)]
 
 
@@ -364,6 +430,12 @@ def main():
             sout = lat.empty(lqcd.FIELD_COLOUR_PARITY, 64)
             for _ in range(5):
                 lqcd.stag_eo_apply(lat.g, lqcd.stag_op(STAG_MASS), Ug[(64, 18)], sin, sout, 0, stream=stream)
+            # the pseudo-fermion force kernel on the same links
+            Xf = lat.spinor(b)
+            Ff = torch.zeros((4, lat.V, 3, 3), dtype=torch.complex128, device=dev)
+            for _ in range(5):
+                lqcd.tm_force(lat.g, o64, Ug[(64, 18)], Xf, bd, Ff, stream=stream)
+            del Ff
             a = torch.empty((1 << 30) // 4, dtype=torch.float32, device=dev)
             c = torch.empty_like(a)
             a.fill_(1.0)
@@ -482,6 +554,8 @@ def main():
 
     log("staggered operator")
     stag = staggered(lat, U, np.asarray(b)[:, 0, :].copy(), stream, args.hops, log)
+    log("twisted-mass pseudo-fermion force")
+    force = tm_force(lat, U, b, kappa, mu, stream, log)
 
     hop_stats = {}
     for k, evs in rec["hops"].items():
@@ -545,6 +619,7 @@ def main():
         "multi_rhs": multi,
         "uneven_batch": uneven,
         "staggered": stag,
+        "tm_force": force,
         "device": torch.cuda.get_device_properties(0).name,
     }
     if not args.no_cpu_baseline:

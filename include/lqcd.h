@@ -337,6 +337,33 @@ LQCD_API int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op
                                    void* x, const double* shifts, int32_t nshift, const lqcd_solve_params* params,
                                    lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * N_f = 2 twisted-mass HMC, fermion part (the paper generates gauge fields
+ * with HMC, §3, the determinant entering through pseudo-fermions that need
+ * the inverse of M, §1).  Pseudo-fermion action S_f = ||M^-1 phi||^2; its
+ * force along U_mu(y) -> exp(i w T^a) U_mu(y), T^a = lambda_a / 2, is
+ * F_mu(y) = sum_a (dS_f / dw^a) T^a (3x3 Hermitian, traceless):
+ *
+ *   X = M^-1 phi,  Wf = M(-mu)^-1 gamma_5 X  (so Z = gamma_5 Wf = (M^+)^-1 X)
+ *   W = f+ U_mu(y) A - f- B U_mu(y)^+
+ *   A = sum_s [(1 - gamma_mu) X(y + mu)]_s Z_s(y)^+,  B = sum_s X_s(y) [(1 + gamma_mu) Z(y + mu)]_s^+
+ *   F_mu(y) = (i kappa / 2) [(W - W^+) - tr(W - W^+) / 3]
+ *
+ * (f+- the boundary phases of the forward hop from y and of the backward hop
+ * from y + mu). */
+
+/* out = gamma_5 in (chiral basis: diag(1, 1, -1, -1) on spin), nrhs stacked
+ * full-lattice FP64 spinor fields; in and out may be the same field. */
+LQCD_API int lqcd_gamma5(const lqcd_geom* geom, int32_t nrhs, const void* in, void* out, void* stream);
+
+/* F = scale * force (accumulate = 0) or F += scale * force (accumulate = 1);
+ * X and Wf full-lattice FP64 spinor fields (internal layout), U FP64 at
+ * op->recon (op->prec = 64), F device memory in the canonical layout
+ * F[mu][site][3][3] complex128, site = x + Lx (y + Ly (z + Lz t)).
+ * Enqueues only. */
+LQCD_API int tm_force(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* X, const void* Wf,
+                      void* F, double scale, int32_t accumulate, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1948,4 +1948,45 @@ int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const v
     }
     return worst;
 }
+
+// ---------------------------------------------------------------------------
+// Twisted-mass pseudo-fermion force (the HMC's fermion part)
+
+int lqcd_gamma5(const lqcd_geom* geom, int32_t nrhs, const void* in, void* out, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if (!in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (nrhs < 1 || nrhs > 65535) return set_error(LQCD_EINVAL, "nrhs %d out of range", nrhs);
+    BlasArgs a{};
+    a.kind = KIND_SPINOR;
+    a.Vh = g.Vh;
+    a.S = g.S;
+    a.nsub = 2;
+    a.sub_stride = parity_bytes(g, 64);
+    a.pred = PRED_ALWAYS;
+    a.x = const_cast<void*>(in);
+    a.y = out;
+    a.st_x = a.st_y = 2 * parity_bytes(g, 64);
+    a.coef = SpinCoef{{1.0, 0.0}, {-1.0, 0.0}};
+    a.r.fin = FIN_STORE;
+    LQCD_K(launch_blas(64, BLAS_SPIN_SCALE, a, nrhs, launch_for(LQCD_KERNEL_BLAS, 64), static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
+
+int tm_force(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* X, const void* Wf, void* F,
+             double scale, int32_t accumulate, void* stream)
+{
+    Geom g;
+    int rc = make_geom(geom, &g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (op->prec != 64) return set_error(LQCD_EINVAL, "the force takes FP64 fields (op->prec = 64)");
+    if (!U || !X || !Wf || !F) return set_error(LQCD_EINVAL, "NULL pointer");
+    if (accumulate != 0 && accumulate != 1) return set_error(LQCD_EINVAL, "accumulate must be 0 or 1");
+    if (!std::isfinite(scale)) return set_error(LQCD_EINVAL, "scale must be finite");
+    LQCD_K(launch_tm_force(op->recon, g, U, X, Wf, F, op->kappa, scale, accumulate, static_cast<hipStream_t>(stream)));
+    return LQCD_OK;
+}
 }  // extern "C"

@@ -311,6 +311,11 @@ void set_recorder(Recorder* r);
 // Canonical complex128 <-> internal layouts.
 hipError_t launch_pack_spinor(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s);
 hipError_t launch_unpack_spinor(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s);
+// The twisted-mass pseudo-fermion force of full-lattice FP64 fields X and Wf
+// (Z = gamma_5 Wf) into canonical F[mu][site][3][3]: F = scale * force
+// (accumulate = 0) or F += scale * force.
+hipError_t launch_tm_force(int recon, const Geom& g, const void* U, const void* X, const void* Wf, void* F,
+                           double kappa, double scale, int accumulate, hipStream_t s);
 hipError_t launch_pack_colour(int prec, const Geom& g, const void* canon, void* out, int nrhs, hipStream_t s);
 hipError_t launch_unpack_colour(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s);
 hipError_t launch_pack_gauge(int prec, int recon, const Geom& g, const void* canon, void* out, hipStream_t s);

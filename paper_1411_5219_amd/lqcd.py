@@ -31,7 +31,7 @@ SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspac
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
            "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
            "lqcd_unpack_colour", "stag_apply", "stag_eo_apply", "lqcd_workspace_bytes_stag", "stag_cg_solve",
-           "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs"]
+           "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs", "lqcd_gamma5", "tm_force"]
 
 
 class Geom(ctypes.Structure):
@@ -113,6 +113,8 @@ def _load():
                                ctypes.c_int),
         "lqcd_autotune_dslash_rhs": ([G, O, vp, vp, vp, i32, i32, vp, ctypes.POINTER(Launch),
                                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "lqcd_gamma5": ([G, i32, vp, vp, vp], ctypes.c_int),
+        "tm_force": ([G, O, vp, vp, vp, vp, ctypes.c_double, i32, vp], ctypes.c_int),
         "stag_cg_solve": ([G, SO, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "stag_multishift_solve": ([G, SO, vp, vp, vp, ctypes.POINTER(ctypes.c_double), i32, P, I, vp,
                                    ctypes.c_size_t, vp], ctypes.c_int),
@@ -358,3 +360,16 @@ def lqcd_autotune_dslash_rhs(g, o, U, inp, out, nrhs, reps=10, stream=None):
                                          int(reps), _stream(stream), ctypes.byref(best), ctypes.byref(us)))
     return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
              "rhs_group": best.rhs_group}, us.value)
+
+
+# ---------------------------------------------------------------------------
+# Twisted-mass pseudo-fermion force
+
+
+def lqcd_gamma5(g, inp, out, nrhs=1, stream=None):
+    return _check(_lib.lqcd_gamma5(ctypes.byref(g), int(nrhs), _ptr(inp), _ptr(out), _stream(stream)))
+
+
+def tm_force(g, o, U, X, Wf, F, scale=1.0, accumulate=0, stream=None):
+    return _check(_lib.tm_force(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(X), _ptr(Wf), _ptr(F), float(scale),
+                                int(accumulate), _stream(stream)))

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "lqcd.h")).read()
-    return sorted(set(re.findall(r"LQCD_API\s+(?:const\s+char\s*\*|int)\s+([a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"LQCD_API\s+(?:const\s+char\s*\*|int)\s+([a-z_0-9]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():

@@ -1,0 +1,173 @@
+"""GPU parity of the twisted-mass pseudo-fermion force against the FP64 oracle.
+
+The force kernel is a bilinear function of X and Z, so its parity is checked
+on independent Gaussian X and Z (any pair, not only solutions) on lattices
+with several blocks, ragged tails and twisted boundaries, in both link
+encodings; then end to end, with X and Z from the library's own solves, on a
+lattice small enough for the oracle's dense solves.  The molecular-dynamics
+checks (energy conservation at second order in the step, reversibility) run
+the whole N_f = 2 step: solves, force kernel and the host gauge part.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import site_rel_err
+from lattice_inputs import gauge_field, gaussian_spinor
+from oracle import force as F
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [
+    ((4, 2, 2, 2), (0.3, 0.0, 0.7, math.pi)),
+    ((4, 6, 8, 2), (0.0, 0.0, 0.0, math.pi)),
+    ((6, 4, 6, 10), (0.3, -0.7, 1.1, math.pi + 0.2)),
+]
+KAPPA, MU = 0.13, 0.2
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    from paper_1411_5219_amd import fields, lqcd
+    assert torch.cuda.is_available()
+    return torch, fields, lqcd
+
+
+def _g5(psi):
+    _, g5 = W.gammas()
+    return np.einsum("st,...tc->...sc", g5, psi)
+
+
+def _force_gpu(torch, fields, lqcd, L4, theta, U, X, Z, recon=18, scale=1.0, F0=None):
+    lat = fields.Lattice(L4, theta)
+    Ud = lat.gauge(U, 64, recon)
+    Xd = lat.spinor(X, 64)
+    Wd = lat.spinor(_g5(Z), 64)  # the kernel takes Wf with Z = gamma_5 Wf
+    if F0 is None:
+        Fd = torch.full((4, lat.V, 3, 3), float("nan"), dtype=torch.complex128, device=lat.device)
+        acc = 0
+    else:
+        Fd = torch.as_tensor(F0).to(lat.device).contiguous()
+        acc = 1
+    lqcd.tm_force(lat.g, lqcd.op(KAPPA, MU, 64, recon), Ud, Xd, Wd, Fd, scale=scale, accumulate=acc)
+    torch.cuda.synchronize()
+    return Fd.cpu().numpy()
+
+
+@pytest.mark.parametrize("L4,theta", LATTICES)
+def test_gamma5(mods, L4, theta):
+    torch, fields, lqcd = mods
+    lat = fields.Lattice(L4, theta)
+    psi = gaussian_spinor(L4, seed=11, nrhs=2)
+    out = lat.empty(lqcd.FIELD_SPINOR_FULL, 64, nrhs=2)
+    lqcd.lqcd_gamma5(lat.g, lat.spinor(psi, 64), out, nrhs=2)
+    got = lat.unpack(out, 64, nrhs=2)
+    assert np.array_equal(got, _g5(psi))
+
+
+@pytest.mark.parametrize("L4,theta", LATTICES)
+@pytest.mark.parametrize("recon", [18, 12])
+def test_force_kernel(mods, L4, theta, recon):
+    torch, fields, lqcd = mods
+    print(f"\n[case] tm_force L={L4} recon={recon}", flush=True)
+    U = gauge_field(L4, "haar", seed=21)
+    X = gaussian_spinor(L4, seed=22)
+    Z = gaussian_spinor(L4, seed=23)
+    ref = F.force(U, X, Z, L4, theta, KAPPA)
+    got = _force_gpu(torch, fields, lqcd, L4, theta, U, X, Z, recon)
+    assert np.all(np.isfinite(got))
+    tol = 1e-13 if recon == 18 else 1e-12
+    assert site_rel_err(got, ref, ncomp=9) <= tol
+
+
+def test_force_scale_accumulate(mods):
+    torch, fields, lqcd = mods
+    L4, theta = LATTICES[1]
+    U = gauge_field(L4, "haar", seed=31)
+    X = gaussian_spinor(L4, seed=32)
+    Z = gaussian_spinor(L4, seed=33)
+    rng = np.random.default_rng(34)
+    F0 = rng.standard_normal((4, int(np.prod(L4)), 3, 3)) + 1j * rng.standard_normal((4, int(np.prod(L4)), 3, 3))
+    ref = F0 - 0.75 * F.force(U, X, Z, L4, theta, KAPPA)
+    got = _force_gpu(torch, fields, lqcd, L4, theta, U, X, Z, 18, scale=-0.75, F0=F0)
+    assert site_rel_err(got, ref, ncomp=9) <= 1e-13
+
+
+def test_force_end_to_end(mods):
+    """X = M^-1 phi and Wf = M(-mu)^-1 gamma_5 X by the library's solves, then
+    the kernel, against the oracle's dense solves and closed form."""
+    torch, fields, lqcd = mods
+    L4, theta = LATTICES[0]
+    U = gauge_field(L4, "haar", seed=5)
+    phi = gaussian_spinor(L4, seed=6)
+    Xo, Zo = F.solve_pair(U, phi, L4, theta, KAPPA, MU)
+    ref = F.force(U, Xo, Zo, L4, theta, KAPPA)
+
+    lat = fields.Lattice(L4, theta)
+    Ud = lat.gauge(U, 64, 18)
+    params = lqcd.solve_params(tol=1e-13, maxiter=10000)
+    op_p, op_m = lqcd.op(KAPPA, MU), lqcd.op(KAPPA, -MU)
+    ws = lat.workspace(op_p, params)
+    Xd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    Wd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    tmp = lat.empty(lqcd.FIELD_SPINOR_FULL, 64)
+    rc, _ = lqcd.cg_solve(lat.g, op_p, Ud, lat.spinor(phi, 64), Xd, params, ws)
+    assert rc == lqcd.OK
+    lqcd.lqcd_gamma5(lat.g, Xd, tmp)
+    rc, _ = lqcd.cg_solve(lat.g, op_m, Ud, tmp, Wd, params, ws)
+    assert rc == lqcd.OK
+    Fd = torch.zeros((4, lat.V, 3, 3), dtype=torch.complex128, device=lat.device)
+    lqcd.tm_force(lat.g, op_p, Ud, Xd, Wd, Fd)
+    torch.cuda.synchronize()
+    got = Fd.cpu().numpy()
+    assert site_rel_err(lat.unpack(Xd, 64), Xo) <= 1e-11
+    assert site_rel_err(got, ref, ncomp=9) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def md(mods):
+    from paper_1411_5219_amd import hmc
+    L4, theta = (4, 4, 4, 4), (0.0, 0.0, 0.0, math.pi)
+    U = gauge_field(L4, "exp", eps=0.3, seed=41)
+    rng = np.random.default_rng(42)
+    P = hmc.gaussian_momenta(L4, rng)
+    V = int(np.prod(L4))
+    eta = (rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3))) / math.sqrt(2.0)
+    run = hmc.TwistedMassHMC(L4, theta, kappa=0.12, mu=0.1, beta=5.6, tol=1e-13)
+    phi = run.heatbath(U, eta)
+    return hmc, run, U, P, phi, eta
+
+
+def test_heatbath_action(md):
+    """S_f(phi = M eta) = ||eta||^2."""
+    hmc, run, U, P, phi, eta = md
+    s = run.fermion_action(U, phi)
+    assert abs(s - np.vdot(eta, eta).real) <= 1e-10 * s
+
+
+def test_md_energy_second_order(md):
+    """Leapfrog violates H at O(dt^2): halving the step quarters dH."""
+    hmc, run, U, P, phi, _ = md
+    H0 = run.hamiltonian(U, P, phi)
+    dH = []
+    for n in (4, 8):
+        U1, P1 = run.leapfrog(U, P, phi, 0.25 / n, n)
+        dH.append(run.hamiltonian(U1, P1, phi) - H0)
+    print(f"\n[md] dH = {dH}", flush=True)
+    ratio = dH[0] / dH[1]
+    assert abs(dH[0]) > 1e-6
+    assert 3.0 < ratio < 5.3, dH
+
+
+def test_md_reversible(md):
+    """Integrating forward, flipping the momenta and integrating again returns
+    to the start (to the solver tolerance)."""
+    hmc, run, U, P, phi, _ = md
+    U1, P1 = run.leapfrog(U, P, phi, 0.05, 4)
+    U2, P2 = run.leapfrog(U1, -P1, phi, 0.05, 4)
+    assert np.max(np.abs(U2 - U)) <= 1e-9
+    assert np.max(np.abs(P2 + P)) <= 1e-9
