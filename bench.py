@@ -124,13 +124,14 @@ def cpu_baseline(U, b, L, theta, kappa, mu, budget_s):
             "cpu_model": cpu_model()}
 
 
-def recorded_traffic(workload):
-    """HBM bytes per launch of the FP64 hop from the committed counter passes
-    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for
-    a 1 GiB copy), or None when they were taken on other kernel sources."""
+def recorded_traffic(workload, name="dslash_fp64", sources=None):
+    """HBM bytes per launch of a roofline kernel (the FP64 hop by default)
+    from the committed counter passes (FETCH_SIZE and WRITE_SIZE, each scaled
+    by the same counter's reading for a 1 GiB copy), or None when they were
+    taken on other kernel sources."""
     from paper_1411_5219_amd.profiling import kernel_source_digest
 
-    path = os.path.join(ROOT, "profiles", f"dslash_fp64_{workload}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None, "no counter passes recorded for this workload"
     vals = {}
@@ -138,7 +139,7 @@ def recorded_traffic(workload):
         if " = " in line:
             k, v = line.split(" = ", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_digest") != kernel_source_digest():
+    if vals.get("kernel_source_digest") != kernel_source_digest(sources):
         return None, "counters were taken on an older kernel"
     t = float(vals["read_bytes"]) + float(vals["write_bytes"])
     return t, f"{os.path.relpath(path, ROOT)}: read {float(vals['read_bytes']):.4g} B + write {float(vals['write_bytes']):.4g} B"
@@ -273,8 +274,12 @@ def tm_force(lat, U, b, kappa, mu, stream, log, launches=20):
     e1.synchronize()
     us = e0.elapsed_time(e1) / launches * 1e3
     gbs = V * FORCE_BYTES / (us * 1e-6) / 1e9
-    out = {"kernel": {"name": "k_tm_force<18>", "avg_launch_us": us, "bytes_per_launch": V * FORCE_BYTES,
-                      "GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS},
+    from paper_1411_5219_amd.profiling import FORCE_SOURCES
+
+    traffic, note = recorded_traffic(f"{lat.L[0]}x{lat.L[3]}", "tm_force", FORCE_SOURCES)
+    out = {"kernel": {"name": "k_tm_force<18>", "bound": "hbm", "avg_launch_us": us,
+                      "bytes_per_launch": V * FORCE_BYTES, "GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                      "traffic": traffic, "traffic_note": note},
            "evaluation": {"seconds_median": float(np.median(times)), "solves": "mixed FP32/12, tol 1e-10",
                           "iters": [i1["iters"], i2["iters"]], "true_resid": [i1["true_resid"], i2["true_resid"]],
                           "solve_seconds": [i1["seconds"], i2["seconds"]]}}

@@ -359,8 +359,11 @@ LQCD_API int lqcd_gamma5(const lqcd_geom* geom, int32_t nrhs, const void* in, vo
 /* F = scale * force (accumulate = 0) or F += scale * force (accumulate = 1);
  * X and Wf full-lattice FP64 spinor fields (internal layout), U FP64 at
  * op->recon (op->prec = 64), F device memory in the canonical layout
- * F[mu][site][3][3] complex128, site = x + Lx (y + Ly (z + Lz t)).
- * Enqueues only. */
+ * F[mu][site][3][3] complex128, site = x + Lx (y + Ly (z + Lz t)), caller
+ * owned (4 * V * 144 bytes), not overlapping X, Wf or U.  EINVAL for a NULL
+ * pointer, op->prec != 64, accumulate not 0 or 1, a non-finite scale, or a
+ * lattice whose full-lattice FP64 spinor field or one direction of F would
+ * reach 2 GiB (about 11 million sites; 64^3 x 32 fits).  Enqueues only. */
 LQCD_API int tm_force(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* X, const void* Wf,
                       void* F, double scale, int32_t accumulate, void* stream);
 

@@ -1986,6 +1986,9 @@ int tm_force(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void
     if (!U || !X || !Wf || !F) return set_error(LQCD_EINVAL, "NULL pointer");
     if (accumulate != 0 && accumulate != 1) return set_error(LQCD_EINVAL, "accumulate must be 0 or 1");
     if (!std::isfinite(scale)) return set_error(LQCD_EINVAL, "scale must be finite");
+    if (384 * g.S > INT32_MAX || 2 * (int64_t)g.Vh * 144 > INT32_MAX)
+        return set_error(LQCD_EINVAL, "lattice too large for the force kernel: a full-lattice FP64 spinor field "
+                                      "and one direction of F must each stay under 2 GiB (about 11 million sites)");
     LQCD_K(launch_tm_force(op->recon, g, U, X, Wf, F, op->kappa, scale, accumulate, static_cast<hipStream_t>(stream)));
     return LQCD_OK;
 }

@@ -36,9 +36,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/dslash_impl.h", "csrc/block_order.h", "csrc/dslash.hip", "csrc/lqcd_device.h", "csrc/lqcd_kernels.h"]
 
 
-def kernel_source_digest() -> str:
+# sources of the pseudo-fermion force kernel
+FORCE_SOURCES = ["csrc/force.hip", "csrc/dslash_impl.h", "csrc/block_order.h", "csrc/lqcd_device.h",
+                 "csrc/lqcd_kernels.h"]
+
+
+def kernel_source_digest(sources=None) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         with open(os.path.join(PKG, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -21,10 +21,14 @@ from oracle import wilson as W
 
 pytestmark = pytest.mark.gpu
 
+# xy planes smaller than one 64-site segment, exactly one, and several with a
+# ragged last segment
 LATTICES = [
     ((4, 2, 2, 2), (0.3, 0.0, 0.7, math.pi)),
     ((4, 6, 8, 2), (0.0, 0.0, 0.0, math.pi)),
     ((6, 4, 6, 10), (0.3, -0.7, 1.1, math.pi + 0.2)),
+    ((8, 8, 6, 6), (0.0, 0.0, 0.0, math.pi)),
+    ((10, 10, 6, 4), (0.2, 0.4, -0.3, math.pi)),
 ]
 KAPPA, MU = 0.13, 0.2
 
