@@ -64,6 +64,11 @@ UNEVEN = [((16, 16, 16, 8), 0.3, 0.15), ((20, 20, 20, 8), 0.4, 0.16), ((24, 24, 
 COLOUR_B = {64: 48, 32: 24, 16: 16}
 STAG_HOP_BYTES = {k: 2 * COLOUR_B[k[0]] + 8 * v for k, v in LINK_B.items()}
 STAG_MASS = 0.1
+# reliable-update threshold per inner precision: the largest drop of the
+# low-precision residual before the FP64 true residual is recomputed
+# (measured on 48^3x12: FP32 inner 10 -> 5 updates at the same 53
+# iterations; FP16 inner 10 -> 7 updates, fewer lets its iterations grow)
+DELTA = {32: 0.01, 16: 0.05}
 STAG_SHIFTS = [0.0] + [float(v) for v in (1e-4, 4.6e-4, 2.2e-3, 1e-2, 4.6e-2, 0.22, 1.0)]
 
 
@@ -235,7 +240,8 @@ def tm_force(lat, U, b, kappa, mu, stream, log, launches=20):
     V = lat.V
     o = lqcd.op(kappa, mu)
     om = lqcd.op(kappa, -mu)
-    p = lqcd.solve_params(tol=1e-10, maxiter=100000, eo=1, inner_prec=32, inner_recon=12)
+    p = lqcd.solve_params(tol=1e-10, maxiter=100000, eo=1, inner_prec=32, inner_recon=12,
+                          delta_reliable=DELTA[32])
     with torch.cuda.stream(stream):
         Ud = lat.gauge(U)
         phi = lat.spinor(b)
@@ -284,6 +290,41 @@ def tm_force(lat, U, b, kappa, mu, stream, log, launches=20):
                           "iters": [i1["iters"], i2["iters"]], "true_resid": [i1["true_resid"], i2["true_resid"]],
                           "solve_seconds": [i1["seconds"], i2["seconds"]]}}
     log(f"tm force kernel {us:.1f} us ({gbs:.0f} GB/s); evaluation {out['evaluation']['seconds_median'] * 1e3:.1f} ms")
+    return out
+
+
+def stream_probe(stream, reps=10):
+    """The device's memory facts and what plain streaming kernels reach: a
+    1 GiB copy (1 GiB read + 1 GiB written) and an elementwise add (2 GiB
+    read + 1 GiB written), HIP events on the stream, median of reps."""
+    import numpy as np
+    import torch
+
+    from paper_1411_5219_amd import lqcd
+
+    n = (1 << 30) // 4
+    out = {}
+    with torch.cuda.stream(stream):
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for name, fn, byts in (("copy", lambda: c.copy_(a), 2 << 30), ("add", lambda: torch.add(a, b, out=c), 3 << 30)):
+            fn()
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            out[f"{name}_GBps"] = byts / float(np.median(ts)) / 1e9
+        del a, b, c
+    clock_khz, bus_bits = lqcd.lqcd_device_memory(torch.cuda.current_device())
+    out.update({"memory_clock_khz": clock_khz, "memory_bus_bits": bus_bits, "nominal_peak_GBps": HBM_PEAK_GBS,
+                "note": "peak is the published 8 TB/s (8192-bit HBM3E at 8 Gb/s per pin); the runtime reports the "
+                        "memory clock and bus width, not the data rate per clock"})
     return out
 
 
@@ -453,8 +494,10 @@ def main():
     # ---- solves on the headline lattice
     solves = {
         "fp64": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64),
-        "mixed_fp32": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12),
-        "mixed_fp16": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=16, inner_recon=12),
+        "mixed_fp32": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12,
+                                        delta_reliable=DELTA[32]),
+        "mixed_fp16": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=16, inner_recon=12,
+                                        delta_reliable=DELTA[16]),
     }
     with torch.cuda.stream(stream):
         ws = {n: lat.workspace(o64, p) for n, p in solves.items()}
@@ -466,8 +509,10 @@ def main():
     bm = np.concatenate([np.stack([point_source(MULTI_L, s_, c_) for s_ in range(4) for c_ in range(3)]),
                          gaussian_spinor(MULTI_L, seed=2003, nrhs=4)])
     nm = bm.shape[0]
-    pm = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=nm)
-    p1 = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=1)
+    pm = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=nm,
+                           delta_reliable=DELTA[32])
+    p1 = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=1,
+                           delta_reliable=DELTA[32])
     with torch.cuda.stream(stream):
         latm = fields.Lattice(MULTI_L, THETA, device=dev)
         Umd = latm.gauge(Um)
@@ -480,7 +525,8 @@ def main():
 
     # ---- uneven-volume batch, 4 Gaussian sources each, graph replay
     log("uneven-batch inputs")
-    pb = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=4, use_graph=1)
+    pb = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=4, use_graph=1,
+                           delta_reliable=DELTA[32])
     gb, ob, Ub, bb, xb, lb = [], [], [], [], [], []
     with torch.cuda.stream(stream):
         for i, (Li, epsi, kappai) in enumerate(UNEVEN):
@@ -561,13 +607,17 @@ def main():
     stag = staggered(lat, U, np.asarray(b)[:, 0, :].copy(), stream, args.hops, log)
     log("twisted-mass pseudo-fermion force")
     force = tm_force(lat, U, b, kappa, mu, stream, log)
+    log("stream probe")
+    probe = stream_probe(stream)
 
     hop_stats = {}
     for k, evs in rec["hops"].items():
-        ms = sum(a.elapsed_time(b_) for a, b_ in evs) / (len(evs) * args.hops)
+        per_burst = [a.elapsed_time(b_) / args.hops for a, b_ in evs]
+        ms = sum(per_burst) / len(per_burst)
         bpl = Vh * HOP_BYTES[k]
         gbs = bpl / (ms * 1e-3) / 1e9
-        hop_stats[f"fp{k[0]}_{k[1]}"] = {"avg_launch_us": ms * 1e3, "bytes_per_launch": bpl, "GBps": gbs,
+        hop_stats[f"fp{k[0]}_{k[1]}"] = {"avg_launch_us": ms * 1e3, "median_burst_us": float(np.median(per_burst)) * 1e3,
+                                         "bursts": len(per_burst), "bytes_per_launch": bpl, "GBps": gbs,
                                          "frac_hbm_peak": gbs / HBM_PEAK_GBS}
     main_k = hop_stats["fp64_18"]
     traffic, traffic_note = recorded_traffic(args.workload)
@@ -614,7 +664,8 @@ def main():
                                "uneven 16^3..32^3x8 batched solve",
                    "lattice": list(L), "kappa": kappa, "mu": mu, "links": f"exp(i eps H), eps={eps}",
                    "bc": "periodic space, antiperiodic time", "tol": tol,
-                   "hops_per_precision_per_step": args.hops},
+                   "hops_per_precision_per_step": args.hops,
+                   "delta_reliable": {"fp32_inner": DELTA[32], "fp16_inner": DELTA[16]}},
         "roofline": {"bound": "hbm", "kernel": "k_dslash_eo<64,18> (FP64 even-odd hop)",
                      "achieved": main_k["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": main_k["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
@@ -625,6 +676,7 @@ def main():
         "uneven_batch": uneven,
         "staggered": stag,
         "tm_force": force,
+        "stream_probe": probe,
         "device": torch.cuda.get_device_properties(0).name,
     }
     if not args.no_cpu_baseline:

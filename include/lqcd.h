@@ -167,6 +167,12 @@ LQCD_API const char* lqcd_last_error(void);
 /* Library version string. */
 LQCD_API const char* lqcd_version(void);
 
+/* The memory clock (kHz) and bus width (bits) the HIP runtime reports for
+ * device (the inputs of a nominal HBM peak; the data rate per clock depends
+ * on the memory type and is not reported).  EINVAL for NULL outputs, EHIP
+ * for a runtime error (e.g. no such device). */
+LQCD_API int lqcd_device_memory(int32_t device, int32_t* clock_khz, int32_t* bus_bits);
+
 /* Bytes of one field in the internal layout.  kind: LQCD_FIELD_*; prec and
  * recon as in lqcd_op (recon ignored for spinors).  nrhs fields stacked are
  * nrhs times this size. */

@@ -1359,6 +1359,17 @@ const char* lqcd_last_error(void) { return g_err; }
 
 const char* lqcd_version(void) { return "lqcd-gfx950 1.0"; }
 
+int lqcd_device_memory(int32_t device, int32_t* clock_khz, int32_t* bus_bits)
+{
+    if (!clock_khz || !bus_bits) return set_error(LQCD_EINVAL, "NULL output pointer");
+    int c = 0, w = 0;
+    LQCD_K(hipDeviceGetAttribute(&c, hipDeviceAttributeMemoryClockRate, device));
+    LQCD_K(hipDeviceGetAttribute(&w, hipDeviceAttributeMemoryBusWidth, device));
+    *clock_khz = c;
+    *bus_bits = w;
+    return LQCD_OK;
+}
+
 int lqcd_field_bytes(const lqcd_geom* geom, int32_t kind, int32_t prec, int32_t recon, size_t* bytes)
 {
     Geom g;

@@ -26,7 +26,7 @@ ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOCONV
                EBREAKDOWN: "EBREAKDOWN", ENONFINITE: "ENONFINITE", EHIP: "EHIP"}
 
 # Every symbol the header declares.
-SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_set_launch",
+SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_device_memory", "lqcd_field_bytes", "lqcd_workspace_bytes", "lqcd_set_launch",
            "lqcd_get_launch", "lqcd_autotune_dslash", "lqcd_pack_gauge",
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
            "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
@@ -88,6 +88,7 @@ def _load():
     sig = {
         "lqcd_last_error": ([], ctypes.c_char_p),
         "lqcd_version": ([], ctypes.c_char_p),
+        "lqcd_device_memory": ([i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
         "lqcd_field_bytes": ([G, i32, i32, i32, szp], ctypes.c_int),
         "lqcd_workspace_bytes": ([G, O, P, szp], ctypes.c_int),
         "lqcd_set_launch": ([i32, i32, ctypes.POINTER(Launch)], ctypes.c_int),
@@ -364,6 +365,13 @@ def lqcd_autotune_dslash_rhs(g, o, U, inp, out, nrhs, reps=10, stream=None):
 
 # ---------------------------------------------------------------------------
 # Twisted-mass pseudo-fermion force
+
+
+def lqcd_device_memory(device=0):
+    """(memory clock in kHz, bus width in bits) as the HIP runtime reports them."""
+    c, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.lqcd_device_memory(int(device), ctypes.byref(c), ctypes.byref(w)))
+    return c.value, w.value
 
 
 def lqcd_gamma5(g, inp, out, nrhs=1, stream=None):

@@ -267,3 +267,11 @@ def test_autotune_configs_agree(mods):
         assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64) == best and us > 0
     finally:
         lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, **saved)
+
+
+def test_device_memory(mods):
+    torch, fields, lqcd = mods
+    clock_khz, bus_bits = lqcd.lqcd_device_memory(0)
+    assert clock_khz > 0 and bus_bits > 0
+    with pytest.raises(lqcd.LqcdError):
+        lqcd.lqcd_device_memory(torch.cuda.device_count())
