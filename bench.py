@@ -396,6 +396,61 @@ def sweep(stream, hops):
     print(json.dumps({"sweep": rows, "device": torch.cuda.get_device_properties(0).name}), flush=True)
 
 
+# (name, lattice, links, eps, kappa, mu, theta, tol, even-odd, seed index)
+ORACLE_SOLVES = [
+    ("4^4 full lattice, Wilson", (4, 4, 4, 4), "haar", 0.0, 0.12, 0.0, 1e-12, False, 0),
+    ("24^3x8 even-odd", (24, 24, 24, 8), "exp", 0.4, 0.16, 0.005, 1e-10, True, 1),
+    ("32^3x8 even-odd", (32, 32, 32, 8), "exp", 0.4, 0.16, 0.005, 1e-10, True, 2),
+]
+
+
+def oracle_solves(stream):
+    """FP64 CGNR to tolerance on the small workloads: the library (median of
+    3 solves) and the CPU oracle (one solve, all host cores) on the same
+    inputs, with both true residuals and the distance between the solutions."""
+    import numpy as np
+    import torch
+
+    from lattice_inputs import gauge_field, gaussian_spinor
+    from oracle import solvers as OS
+    from oracle import wilson as OW
+    from paper_1411_5219_amd import fields, lqcd
+
+    rows = []
+    for name, L, kind, eps, kappa, mu, tol, eo, n in ORACLE_SOLVES:
+        log(f"oracle solve {name}")
+        U = gauge_field(L, kind, eps=eps, seed=1000 + n)
+        b = gaussian_spinor(L, seed=2000 + n)
+        lat = fields.Lattice(L, THETA, device=torch.device("cuda:0"))
+        o = lqcd.op(kappa, mu)
+        p = lqcd.solve_params(tol=tol, maxiter=100000, eo=int(eo), inner_prec=64)
+        with torch.cuda.stream(stream):
+            Ud = lat.gauge(U)
+            bd = lat.spinor(b)
+            xd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+            ws = lat.workspace(o, p)
+        ts = []
+        for _ in range(3):
+            rc, info = lqcd.cg_solve(lat.g, o, Ud, bd, xd, p, ws, stream=stream)
+            if rc != 0:
+                raise RuntimeError(f"{name}: GPU solve failed: {info}")
+            ts.append(info[0]["seconds"])
+        xg = lat.unpack(xd, stream=stream)
+        t0 = time.perf_counter()
+        xo, oinfo = OS.solve(U, b, L, THETA, kappa, mu, tol, eo=eo)
+        t_or = time.perf_counter() - t0
+        row = {"workload": name, "lattice": list(L), "tol": tol, "gpu_seconds_median": float(np.median(ts)),
+               "gpu_iters": info[0]["iters"], "gpu_true_resid": OW.true_residual(U, xg, b, L, THETA, kappa, mu),
+               "oracle_seconds": t_or, "oracle_iters": oinfo.iters, "oracle_true_resid": oinfo.true_resid,
+               "oracle_cores": OW.num_threads(),
+               "solution_rel_diff": float(np.linalg.norm((xg - xo).ravel()) / np.linalg.norm(xo.ravel()))}
+        row["speedup"] = t_or / row["gpu_seconds_median"]
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print(json.dumps({"oracle_solves": rows, "cpu_model": cpu_model(),
+                      "device": torch.cuda.get_device_properties(0).name}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +462,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--profile-hops", action="store_true",
                     help="only run the Dslash hops of each precision and a 1 GiB copy (for counter passes)")
+    ap.add_argument("--oracle-solves", action="store_true",
+                    help="only the FP64 CGNR to tolerance on 4^4, 24^3x8 and 32^3x8, library and CPU oracle side "
+                         "by side (about a minute of host time)")
     ap.add_argument("--sweep", action="store_true",
                     help="only the hop rate per lattice size (16^3x8 .. 64^3x16), Wilson and staggered, "
                          "with the CPU oracle's hop beside it")
@@ -431,6 +489,9 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     if args.sweep:
         sweep(stream, args.hops)
+        return
+    if args.oracle_solves:
+        oracle_solves(stream)
         return
     L = WORKLOADS[args.workload]
     kappa, mu, eps, tol = 0.16, 0.005, 0.4, 1e-10
