@@ -60,29 +60,34 @@ def _neighbour(L, mu, step):
     return X[0] + L[0] * (X[1] + L[1] * (X[2] + L[2] * X[3]))
 
 
-def force(U, X, Z, L, theta, kappa):
-    """F[mu, site] (3x3 Hermitian traceless) from X = M^-1 phi, Z = (M^+)^-1 X."""
+def force_link(U, X, Z, L, theta, kappa, mu, y):
+    """F_mu(y) (3x3 Hermitian traceless) of the link U_mu(y), from X = M^-1 phi
+    and Z = (M^+)^-1 X."""
     g, _ = W.gammas()
-    Xc = site_coords(L)
+    one = np.eye(4)
+    c = [y % L[0], (y // L[0]) % L[1], (y // (L[0] * L[1])) % L[2], y // (L[0] * L[1] * L[2])]
+    edge = c[mu] == L[mu] - 1                         # the link crosses the boundary
+    c[mu] = (c[mu] + 1) % L[mu]
+    fwd = c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))
+    fp = np.exp(1j * theta[mu]) if edge else 1.0      # forward hop phase
+    fm = np.conj(fp)                                  # backward hop phase (from y + mu)
+    u = U[mu, y]
+    v = (u @ ((one - g[mu]) @ X[fwd]).T).T * fp       # [s, colour] = f+ U (1 - gamma) X(y+mu)
+    w1 = sum(np.outer(v[s], np.conj(Z[y, s])) for s in range(4))
+    r = (u @ ((one + g[mu]) @ Z[fwd]).T).T            # U (1 + gamma) Z(y+mu)
+    w2 = fm * sum(np.outer(X[y, s], np.conj(r[s])) for s in range(4))
+    Wm = w1 - w2
+    A = Wm - Wm.conj().T
+    return 0.5j * kappa * (A - np.trace(A) / 3 * np.eye(3))
+
+
+def force(U, X, Z, L, theta, kappa):
+    """F[mu, site] for every link (force_link on each)."""
     V = int(np.prod(L))
     F = np.zeros((4, V, 3, 3), dtype=np.complex128)
-    one = np.eye(4)
     for mu in range(4):
-        fwd = _neighbour(L, mu, +1)
-        edge = Xc[mu] == L[mu] - 1                        # the link crosses the boundary
-        fp = np.where(edge, np.exp(1j * theta[mu]), 1.0)  # forward hop phase
-        fm = np.conj(fp)                                  # backward hop phase (from y + mu)
-        Pm = one - g[mu]
-        Pp = one + g[mu]
         for y in range(V):
-            u = U[mu, y]
-            v = (u @ (Pm @ X[fwd[y]]).T).T * fp[y]         # [s, colour] = f+ U (1 - gamma) X(y+mu)
-            w1 = sum(np.outer(v[s], np.conj(Z[y, s])) for s in range(4))
-            r = (u @ (Pp @ Z[fwd[y]]).T).T                 # U (1 + gamma) Z(y+mu)
-            w2 = fm[y] * sum(np.outer(X[y, s], np.conj(r[s])) for s in range(4))
-            Wm = w1 - w2
-            A = Wm - Wm.conj().T
-            F[mu, y] = 0.5j * kappa * (A - np.trace(A) / 3 * np.eye(3))
+            F[mu, y] = force_link(U, X, Z, L, theta, kappa, mu, y)
     return F
 
 
