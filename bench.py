@@ -129,6 +129,32 @@ def cpu_baseline(U, b, L, theta, kappa, mu, budget_s):
             "cpu_model": cpu_model()}
 
 
+def oracle_staggered_sample(U, chi, L, theta, mass, shifts, cg_iters, ms_iters, budget_s):
+    """The oracle's staggered CG and multi-shift CG on the same inputs for as
+    many iterations as fit about budget_s each; time per iteration and the
+    time it would take for the library's iteration counts (extrapolated)."""
+    from oracle import solvers as SV
+    from oracle import staggered as OS
+    from oracle import wilson as OW
+
+    A = lambda v: OS.normal_e(U, v, L, theta, mass)  # noqa: E731
+    bh = OS.eo_source(U, chi, L, theta, mass)
+    out = {"cores": OW.num_threads(), "kind": "oracle"}
+    for name, run, gpu_iters in (("cg", lambda n: SV.cg(A, bh, 1e-300, n), cg_iters),
+                                 ("multishift", lambda n: SV.multishift_cg(A, bh, shifts, 1e-300, n), ms_iters)):
+        t0 = time.perf_counter()
+        run(1)
+        t1 = time.perf_counter() - t0  # start + 1 iteration
+        n = max(1, int(budget_s / max(t1 / 2, 1e-3)) - 1)
+        t0 = time.perf_counter()
+        run(n)
+        t = time.perf_counter() - t0
+        per = t / (n + 1)
+        out[name] = {"iterations_run": n, "seconds": t, "seconds_per_iteration": per,
+                     "seconds_extrapolated": per * (gpu_iters + 1), "library_iterations": gpu_iters}
+    return out
+
+
 def recorded_traffic(workload, name="dslash_fp64", sources=None):
     """HBM bytes per launch of a roofline kernel (the FP64 hop by default)
     from the committed counter passes (FETCH_SIZE and WRITE_SIZE, each scaled
@@ -150,7 +176,7 @@ def recorded_traffic(workload, name="dslash_fp64", sources=None):
     return t, f"{os.path.relpath(path, ROOT)}: read {float(vals['read_bytes']):.4g} B + write {float(vals['write_bytes']):.4g} B"
 
 
-def staggered(lat, U, b_colour, stream, hops, log):
+def staggered(lat, U, b_colour, stream, hops, log, oracle_budget=0.0):
     """The staggered hop bursts, CG and multi-shift CG on one lattice."""
     import numpy as np
     import torch
@@ -222,13 +248,17 @@ def staggered(lat, U, b_colour, stream, hops, log):
                              "true_resid_max": max(i["true_resid"] for i in ms[-1]),
                              "separate_solves_seconds": t_sep, "speedup_vs_separate": t_sep / med}
         log(f"multi-shift CG: {med * 1e3:.1f} ms vs {t_sep * 1e3:.1f} ms separately")
+    if oracle_budget > 0:
+        log("staggered oracle sample")
+        out["oracle"] = oracle_staggered_sample(U, b_colour, lat.L, lat.theta, STAG_MASS, STAG_SHIFTS,
+                                                cg[-1]["iters"], max(i["iters"] for i in ms[-1]), oracle_budget)
     return out
 
 
 FORCE_BYTES = 2 * 192 + 4 * 144 + 4 * 9 * 16  # X, Wf in; four links; four 3x3 complex128 out
 
 
-def tm_force(lat, U, b, kappa, mu, stream, log, launches=20):
+def tm_force(lat, U, b, kappa, mu, stream, log, launches=20, oracle_links=0):
     """The N_f = 2 pseudo-fermion force: the force kernel alone, then one whole
     evaluation (X = M^-1 phi, Wf = M(-mu)^-1 gamma_5 X, kernel) as an HMC
     step makes it, with mixed FP32/12 solves to 1e-10."""
@@ -290,6 +320,19 @@ def tm_force(lat, U, b, kappa, mu, stream, log, launches=20):
                           "iters": [i1["iters"], i2["iters"]], "true_resid": [i1["true_resid"], i2["true_resid"]],
                           "solve_seconds": [i1["seconds"], i2["seconds"]]}}
     log(f"tm force kernel {us:.1f} us ({gbs:.0f} GB/s); evaluation {out['evaluation']['seconds_median'] * 1e3:.1f} ms")
+    if oracle_links > 0:
+        from oracle import force as OF
+
+        rng = np.random.default_rng(11)
+        ys = rng.integers(0, V, oracle_links)
+        t0 = time.perf_counter()
+        for i, y in enumerate(ys):
+            OF.force_link(U, b, b, lat.L, lat.theta, kappa, i % 4, int(y))
+        t = time.perf_counter() - t0
+        full = t / oracle_links * 4 * V
+        out["oracle"] = {"kind": "oracle", "cores": 1, "links_sampled": oracle_links, "seconds": t,
+                         "seconds_full_lattice_extrapolated": full, "GBps_same_accounting": V * FORCE_BYTES / full / 1e9,
+                         "note": "the oracle's per-link force (numpy, one thread) on random links of the same lattice"}
     return out
 
 
@@ -665,9 +708,10 @@ def main():
     elapsed = time.perf_counter() - t0
 
     log("staggered operator")
-    stag = staggered(lat, U, np.asarray(b)[:, 0, :].copy(), stream, args.hops, log)
+    oracle_side = 0.0 if args.no_cpu_baseline else 5.0
+    stag = staggered(lat, U, np.asarray(b)[:, 0, :].copy(), stream, args.hops, log, oracle_budget=oracle_side)
     log("twisted-mass pseudo-fermion force")
-    force = tm_force(lat, U, b, kappa, mu, stream, log)
+    force = tm_force(lat, U, b, kappa, mu, stream, log, oracle_links=0 if args.no_cpu_baseline else 2000)
     log("stream probe")
     probe = stream_probe(stream)
 

@@ -1363,8 +1363,12 @@ int lqcd_device_memory(int32_t device, int32_t* clock_khz, int32_t* bus_bits)
 {
     if (!clock_khz || !bus_bits) return set_error(LQCD_EINVAL, "NULL output pointer");
     int c = 0, w = 0;
-    LQCD_K(hipDeviceGetAttribute(&c, hipDeviceAttributeMemoryClockRate, device));
-    LQCD_K(hipDeviceGetAttribute(&w, hipDeviceAttributeMemoryBusWidth, device));
+    hipError_t e = hipDeviceGetAttribute(&c, hipDeviceAttributeMemoryClockRate, device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&w, hipDeviceAttributeMemoryBusWidth, device);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // a failed query must not linger as the runtime's last error for later launches
+        return set_error(LQCD_EHIP, "device attribute query failed: %s", hipGetErrorString(e));
+    }
     *clock_khz = c;
     *bus_bits = w;
     return LQCD_OK;

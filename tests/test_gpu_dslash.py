@@ -275,3 +275,8 @@ def test_device_memory(mods):
     assert clock_khz > 0 and bus_bits > 0
     with pytest.raises(lqcd.LqcdError):
         lqcd.lqcd_device_memory(torch.cuda.device_count())
+    # the failed query leaves nothing behind for the next launch
+    lat = fields.Lattice((4, 4, 4, 4))
+    out = lat.empty(lqcd.FIELD_SPINOR_FULL, 64)
+    lqcd.lqcd_pack_spinor(lat.g, 64, 1, torch.zeros((lat.V, 4, 3), dtype=torch.complex128, device="cuda"), out)
+    torch.cuda.synchronize()
