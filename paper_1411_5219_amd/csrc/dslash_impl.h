@@ -67,12 +67,7 @@ __device__ __forceinline__ void link_mul(const Link<R>& U, const cplx<R> (&h)[2]
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cplx<R> t;
-            if (!ADJ) t = U.u[a][0] * h[s][0] + U.u[a][1] * h[s][1] + U.u[a][2] * h[s][2];
-            else t = cmulc(U.u[0][a], h[s][0]) + cmulc(U.u[1][a], h[s][1]) + cmulc(U.u[2][a], h[s][2]);
-            w[s][a] = t;
-        }
+        for (int a = 0; a < 3; ++a) w[s][a] = su3_row<R, ADJ>(U.u, a, h[s]);
 }
 
 template <class R>

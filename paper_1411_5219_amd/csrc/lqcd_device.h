@@ -56,6 +56,53 @@ __device__ __forceinline__ cplx<R> cmulc(cplx<R> a, cplx<R> b)
 }
 template <class R>
 __device__ __forceinline__ cplx<R> conj(cplx<R> a) { return {a.x, -a.y}; }
+
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// sum_k U[a][k] v[k] (ADJ = false) or sum_k conj(U[k][a]) v[k] (ADJ = true):
+// one row of an SU(3) matrix-vector product.  In FP32 each real part is a
+// single chain of fused multiply-adds (1 multiply + 5 FMAs): summing three
+// complex products as written compiles to 3 multiplies, 3 FMAs and 2 adds
+// per real part (the sum of two FMA results is not contracted), and the FP32
+// and FP16-storage hops are bound by their VALU issue.  FP64 keeps the
+// written form: its hop is bound by memory, and the chains' longer live
+// ranges push it past the register budget of two waves per SIMD.
+template <class R, bool ADJ>
+__device__ __forceinline__ cplx<R> su3_row(const cplx<R> (&U)[3][3], int a, const cplx<R> (&v)[3])
+{
+    if constexpr (sizeof(R) == 8) {
+        if (!ADJ) return U[a][0] * v[0] + U[a][1] * v[1] + U[a][2] * v[2];
+        return cmulc(U[0][a], v[0]) + cmulc(U[1][a], v[1]) + cmulc(U[2][a], v[2]);
+    }
+    R re, im;
+    if (!ADJ) {
+        re = U[a][0].x * v[0].x;
+        im = U[a][0].x * v[0].y;
+        re = fmar(-U[a][0].y, v[0].y, re);
+        im = fmar(U[a][0].y, v[0].x, im);
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+            re = fmar(U[a][k].x, v[k].x, re);
+            im = fmar(U[a][k].x, v[k].y, im);
+            re = fmar(-U[a][k].y, v[k].y, re);
+            im = fmar(U[a][k].y, v[k].x, im);
+        }
+    } else {
+        re = U[0][a].x * v[0].x;
+        im = U[0][a].x * v[0].y;
+        re = fmar(U[0][a].y, v[0].y, re);
+        im = fmar(-U[0][a].y, v[0].x, im);
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+            re = fmar(U[k][a].x, v[k].x, re);
+            im = fmar(U[k][a].x, v[k].y, im);
+            re = fmar(U[k][a].y, v[k].y, re);
+            im = fmar(-U[k][a].y, v[k].x, im);
+        }
+    }
+    return {re, im};
+}
 // i * a and -i * a
 template <class R>
 __device__ __forceinline__ cplx<R> ti(cplx<R> a) { return {-a.y, a.x}; }

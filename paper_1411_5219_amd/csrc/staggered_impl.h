@@ -26,8 +26,7 @@ __device__ __forceinline__ void su3_vec(const Link<R>& U, const Colour<R>& v, Co
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (!ADJ) w.c[a] = U.u[a][0] * v.c[0] + U.u[a][1] * v.c[1] + U.u[a][2] * v.c[2];
-        else w.c[a] = cmulc(U.u[0][a], v.c[0]) + cmulc(U.u[1][a], v.c[1]) + cmulc(U.u[2][a], v.c[2]);
+        w.c[a] = su3_row<R, ADJ>(U.u, a, v.c);
     }
 }
 
