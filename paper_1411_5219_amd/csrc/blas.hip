@@ -337,19 +337,42 @@ thread_local Recorder* g_recorder = nullptr;
 Recorder* active_recorder() { return g_recorder; }
 void set_recorder(Recorder* r) { g_recorder = r; }
 
+// Sum of one right-hand side's partials by one block of kFinThreads: each
+// thread adds its strided share four blocks' partials at a time (the four
+// loads issued together: the partials were just written on other XCDs and
+// each round trip is long), then the block folds the threads' sums in a
+// fixed order.
+constexpr int kFinThreads = 1024;
+
 template <int N>
-__global__ void __launch_bounds__(256) k_finalize(const double* partials, int nblocks, int fin, Ctl* ctl, int pred)
+__device__ __forceinline__ void sum_partials(const double* p, int nblocks, double (&v)[N])
+{
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = 0.0;
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kFinThreads) {
+        double t[4][N];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * kFinThreads;
+#pragma unroll
+            for (int j = 0; j < N; ++j) t[u][j] = b < nblocks ? p[(int64_t)b * N + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < N; ++j) v[j] += t[u][j];
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kFinThreads) k_finalize(const double* partials, int nblocks, int fin, Ctl* ctl,
+                                                          int pred)
 {
     const int rhs = blockIdx.x;
     Ctl* c = ctl + rhs;
     if (pred_skip(pred, c)) return;
-    const double* p = partials + (int64_t)rhs * nblocks * N;
     double v[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-#pragma unroll
-        for (int j = 0; j < N; ++j) v[j] += p[(int64_t)b * N + j];
+    sum_partials<N>(partials + (int64_t)rhs * nblocks * N, nblocks, v);
     __shared__ double tot[N];
     block_reduce_store<N>(v, tot, 0);
     __syncthreads();
@@ -363,19 +386,14 @@ __global__ void __launch_bounds__(256) k_finalize(const double* partials, int nb
 
 // One block per (system, right-hand side): the finalize of every system of a batched launch.
 template <int N>
-__global__ void __launch_bounds__(256) k_finalize_batch(const FinArgs* __restrict__ tab, int nrhs)
+__global__ void __launch_bounds__(kFinThreads) k_finalize_batch(const FinArgs* __restrict__ tab, int nrhs)
 {
     const FinArgs& f = tab[blockIdx.x / nrhs];
     const int rhs = blockIdx.x % nrhs;
     Ctl* c = f.ctl + rhs;
     if (pred_skip(f.pred, c)) return;
-    const double* p = f.partials + (int64_t)rhs * f.nblocks * N;
     double v[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = 0.0;
-    for (int b = threadIdx.x; b < f.nblocks; b += blockDim.x)
-#pragma unroll
-        for (int j = 0; j < N; ++j) v[j] += p[(int64_t)b * N + j];
+    sum_partials<N>(f.partials + (int64_t)rhs * f.nblocks * N, f.nblocks, v);
     __shared__ double tot[N];
     block_reduce_store<N>(v, tot, 0);
     __syncthreads();
@@ -389,7 +407,7 @@ __global__ void __launch_bounds__(256) k_finalize_batch(const FinArgs* __restric
 
 hipError_t launch_finalize_batch(int N, const FinArgs* tab, int nsys, int nrhs, hipStream_t s)
 {
-    dim3 g((unsigned)(nsys * nrhs)), b(256);
+    dim3 g((unsigned)(nsys * nrhs)), b(kFinThreads);
     if (N == 1) hipLaunchKernelGGL(k_finalize_batch<1>, g, b, 0, s, tab, nrhs);
     else if (N == 2) hipLaunchKernelGGL(k_finalize_batch<2>, g, b, 0, s, tab, nrhs);
     else if (N == 3) hipLaunchKernelGGL(k_finalize_batch<3>, g, b, 0, s, tab, nrhs);
@@ -401,7 +419,7 @@ hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, 
                            hipStream_t s)
 {
     if (!ctl) return hipErrorInvalidValue;
-    dim3 g(nrhs), b(256);
+    dim3 g(nrhs), b(kFinThreads);
     if (N == 1) hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
     else if (N == 2) hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
     else if (N == 3) hipLaunchKernelGGL(k_finalize<3>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
