@@ -8,8 +8,9 @@ One step is one pass of the whole hot path on synthetic inputs:
      FP64/18, FP32/12 and FP16/12 storage, timed with HIP events on the
      stream they run on (FP64/18 is the roofline kernel);
   2. on the same lattice, one Gaussian source: plain FP64 even-odd CGNR to a
-     true residual of 1e-10, then mixed precision (FP32/12 and FP16/12 inner
-     Dslash, FP64 reliable updates) to the same true residual;
+     true residual of 1e-10 (with 18-real and with 12-real FP64 links), then
+     mixed precision (FP32/12 and FP16/12 inner Dslash, FP64 reliable
+     updates) to the same true residual;
   3. multi right-hand side: 12 unit point sources at the origin plus 4
      Gaussian sources on 32^3 x 8, solved together (FP32/12 inner, FP64
      reliable updates), the batched Dslash loading each link once per tile;
@@ -87,12 +88,13 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def solve_bytes(infos, Vh, inner):
+def solve_bytes(infos, Vh, inner, outer=(64, 18)):
     """Compulsory Dslash bytes of one solve over its right-hand sides: spinor
     traffic per right-hand side, link traffic once per batched application
-    (as many as the right-hand side that applied the most hops)."""
+    (as many as the right-hand side that applied the most hops); outer: the
+    storage of the FP64 links."""
     b = Vh * (sum(i["hops_outer"] for i in infos) * 2 * SPINOR_B[64]
-              + max(i["hops_outer"] for i in infos) * 8 * LINK_B[(64, 18)])
+              + max(i["hops_outer"] for i in infos) * 8 * LINK_B[outer])
     if inner[0] != 64:
         b += Vh * (sum(i["hops_inner"] for i in infos) * 2 * SPINOR_B[inner[0]]
                    + max(i["hops_inner"] for i in infos) * 8 * LINK_B[inner])
@@ -598,14 +600,20 @@ def main():
     # ---- solves on the headline lattice
     solves = {
         "fp64": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64),
+        "fp64_links12": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64),
         "mixed_fp32": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12,
                                         delta_reliable=DELTA[32]),
         "mixed_fp16": lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=16, inner_recon=12,
                                         delta_reliable=DELTA[16]),
     }
+    # the FP64 solve with 12-real FP64 links (third row rebuilt in FP64 from
+    # the first two: FP64 arithmetic, 1152 instead of 1536 bytes per hop site)
+    o64_12 = lqcd.op(kappa, mu, 64, 12)
     with torch.cuda.stream(stream):
+        U64_12 = lat.gauge(U, 64, 12)
         ws = {n: lat.workspace(o64, p) for n, p in solves.items()}
         xs = {n: lat.zeros(lqcd.FIELD_SPINOR_FULL, 64) for n in solves}
+    solve_op = {n: (o64_12, U64_12, (64, 12)) if n == "fp64_links12" else (o64, Ug[(64, 18)], (64, 18)) for n in solves}
 
     # ---- multi right-hand side: 12 point sources + 4 Gaussian
     log(f"multi-RHS inputs on {MULTI_L}")
@@ -655,9 +663,10 @@ def main():
         # queued hop bursts finish first so that they are not counted in it
         stream.synchronize()
         for n, p in solves.items():
-            rc, info = lqcd.cg_solve(lat.g, o64, Ug[(64, 18)], bd, xs[n], p, ws[n], stream=stream)
+            o_n, U_n, outer = solve_op[n]
+            rc, info = lqcd.cg_solve(lat.g, o_n, U_n, bd, xs[n], p, ws[n], stream=stream)
             check(rc, info, n)
-            byts += solve_bytes(info, Vh, (p.inner_prec, p.inner_recon))
+            byts += solve_bytes(info, Vh, (p.inner_prec, p.inner_recon), outer)
             if rec is not None:
                 rec.setdefault(n, []).append(info)
         rc, info = lqcd.cg_solve(latm.g, o64, Umd, bmd, xmd, pm, wsm, stream=stream)
@@ -733,7 +742,7 @@ def main():
         last = rec[n][-1][0]
         solve_stats[n] = {"seconds_median": med([i[0]["seconds"] for i in rec[n]]), "iters": last["iters"],
                           "reliable_updates": last["reliable_updates"], "true_resid": last["true_resid"]}
-    for n in ("mixed_fp32", "mixed_fp16"):
+    for n in ("fp64_links12", "mixed_fp32", "mixed_fp16"):
         solve_stats[n]["speedup_vs_fp64"] = solve_stats["fp64"]["seconds_median"] / solve_stats[n]["seconds_median"]
     mr = rec["multi_rhs"]
     multi = {"lattice": list(MULTI_L), "sources": "12 unit point sources at the origin + 4 Gaussian",
@@ -764,7 +773,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"twisted-mass Wilson even-odd Dslash + CGNR solves on {L[0]}^3x{L[3]} (FP64; "
+        "config": {"workload": f"twisted-mass Wilson even-odd Dslash + CGNR solves on {L[0]}^3x{L[3]} (FP64 with 18- "
+                               "and 12-real links; "
                                "mixed FP32/12 and FP16/12 with FP64 reliable updates), 16-RHS solve on 32^3x8, "
                                "uneven 16^3..32^3x8 batched solve",
                    "lattice": list(L), "kappa": kappa, "mu": mu, "links": f"exp(i eps H), eps={eps}",

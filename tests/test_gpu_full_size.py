@@ -65,6 +65,20 @@ def test_single_source_48x12_certified(mods, big, inner):
     assert abs(tr - info[0]["true_resid"]) <= 1e-3 * TOL
 
 
+def test_fp64_links12_48x12_certified(mods, big):
+    """The FP64 solve on 12-real FP64 links (third row rebuilt in FP64)."""
+    torch, fields, lqcd = mods
+    U, b, lat, Ud, bd = big
+    print("\n[case] 48^3x12 fp64 solve, 12-real links", flush=True)
+    o = lqcd.op(KAPPA, MU, 64, 12)
+    p = lqcd.solve_params(tol=TOL, maxiter=100000, eo=1, inner_prec=64)
+    xd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    rc, info = lqcd.cg_solve(lat.g, o, lat.gauge(U, 64, 12), bd, xd, p, lat.workspace(o, p))
+    assert rc == lqcd.OK, info
+    tr = W.true_residual(U, lat.unpack(xd), b, L48, THETA, KAPPA, MU)
+    assert tr <= TOL and abs(tr - info[0]["true_resid"]) <= 1e-3 * TOL
+
+
 def test_force_48x12_sampled(mods, big):
     """The force kernel on the full lattice (Gaussian X and Z) against the
     oracle's per-link force on sampled links: random bulk links and links on
