@@ -132,7 +132,7 @@ std::mutex g_launch_mu;
 // right-hand sides in groups of 4, FP16 tiles of 2 in groups of 4.
 // The staggered hop (colour vectors of 48 / 24 / 16 bytes) gains less from
 // neighbour reuse: memory order in FP64, row tiles of 192 in FP32 and FP16.
-Launch g_launch[3][3] = {{{256, 1, 1, 2, 2}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
+Launch g_launch[3][3] = {{{256, 1, 1, 1, 4}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
                          {{256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}},
                          {{256, 1, 0, 1, 0}, {192, 1, 1, 1, 0}, {192, 1, 1, 1, 0}}};
 
