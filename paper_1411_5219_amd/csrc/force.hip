@@ -31,9 +31,10 @@
 #include "dslash_impl.h"
 
 // Waves per SIMD the register allocation must allow: one direction's state
-// needs about 165 VGPRs, which fits three waves without spilling.
+// needs about 170 VGPRs; at three waves the compiler spills a few of them,
+// and two waves without spills measured slightly faster.
 #ifndef LQCD_FORCE_WAVES
-#define LQCD_FORCE_WAVES 3
+#define LQCD_FORCE_WAVES 2
 #endif
 #ifndef LQCD_FORCE_SWIZZLE
 #define LQCD_FORCE_SWIZZLE 1

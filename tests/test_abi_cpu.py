@@ -168,3 +168,30 @@ def test_staggered_sizes_and_validation():
         with pytest.raises(L.LqcdError) as e:
             L.stag_multishift_solve(g, o, 16, 32, 48, shifts, p, 64, stream=0)
         assert e.value.code == L.EINVAL
+
+
+def test_force_and_gamma5_validation():
+    """The force and gamma_5 entry points refuse bad arguments before any
+    device work: FP32 operators, a bad accumulate flag, a non-finite scale,
+    NULL fields, lattices whose fields would pass 2 GiB, bad nrhs; the device
+    query refuses NULL outputs."""
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((4, 4, 4, 4))
+    o = L.op(0.13, 0.1)
+    cases = [dict(o=L.op(0.13, 0.1, prec=32, recon=12)), dict(accumulate=2), dict(scale=float("nan")),
+             dict(U=None), dict(F=None)]
+    for c in cases:
+        args = dict(g=g, o=o, U=16, X=32, Wf=48, F=64, scale=1.0, accumulate=0)
+        args.update(c)
+        with pytest.raises(L.LqcdError) as e:
+            L.tm_force(args["g"], args["o"], args["U"], args["X"], args["Wf"], args["F"], scale=args["scale"],
+                       accumulate=args["accumulate"], stream=0)
+        assert e.value.code == L.EINVAL, c
+    with pytest.raises(L.LqcdError) as e:  # 64^3 x 48: a full-lattice FP64 spinor field is 2.4 GB
+        L.tm_force(L.geom((64, 64, 64, 48)), o, 16, 32, 48, 64, stream=0)
+    assert e.value.code == L.EINVAL
+    for nrhs, inp in ((0, 16), (1, None)):
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_gamma5(g, inp, 32, nrhs=nrhs, stream=0)
+        assert e.value.code == L.EINVAL
+    assert L._lib.lqcd_device_memory(0, None, None) == L.EINVAL
