@@ -131,9 +131,10 @@ typedef struct {
 } lqcd_solve_info;
 
 /* Launch configuration of a kernel family (LQCD_KERNEL_DSLASH: the Wilson
- * hop; LQCD_KERNEL_STAG: the staggered hop, which ignores rhs_tile and
- * rhs_group; LQCD_KERNEL_BLAS: the site-local kernels) at one storage
- * precision:
+ * hop on one right-hand side; LQCD_KERNEL_DSLASH_RHS: the Wilson hop on
+ * several stacked right-hand sides, nrhs > 1; LQCD_KERNEL_STAG: the
+ * staggered hop, which ignores rhs_tile and rhs_group; LQCD_KERNEL_BLAS: the
+ * site-local kernels) at one storage precision:
  *   block   work-items per block (64, 128, 192 or 256; with order = 1 the
  *           requested size, the block then holds whole x-rows)
  *   swizzle 1: block indices are remapped so that each of the 8 XCDs works
@@ -159,7 +160,7 @@ typedef struct {
     int32_t rhs_group;
 } lqcd_launch;
 
-enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1, LQCD_KERNEL_STAG = 2 };
+enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1, LQCD_KERNEL_STAG = 2, LQCD_KERNEL_DSLASH_RHS = 3 };
 
 /* Message of the last error on this thread ("" if none). */
 LQCD_API const char* lqcd_last_error(void);
@@ -199,11 +200,12 @@ LQCD_API int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg);
 LQCD_API int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                                   int32_t reps, void* stream, lqcd_launch* best, double* best_us);
 
-/* For several right-hand sides: with the block shape of LQCD_KERNEL_DSLASH at
- * op->prec kept, times the even-odd hop on nrhs (2..16) stacked parity
- * fields for every right-hand-side tile compiled (1, 2, 4; FP64 1, 2) and
- * group (0, 2, 4, 8, 16) and keeps the fastest tile and group in the table.
- * best_us: mean time of one launch over all nrhs.  Synchronises stream. */
+/* For several right-hand sides: with the XCD remap and block order of
+ * LQCD_KERNEL_DSLASH_RHS at op->prec kept, times the even-odd hop on nrhs
+ * (2..16) stacked parity fields for every block request (128, 192, 256),
+ * right-hand-side tile compiled (1, 2, 4; FP64 1, 2) and group (0, 2, 4, 8,
+ * 16), and installs the fastest as LQCD_KERNEL_DSLASH_RHS.  best_us: mean
+ * time of one launch over all nrhs.  Synchronises stream. */
 LQCD_API int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in,
                                       void* out, int32_t nrhs, int32_t reps, void* stream, lqcd_launch* best,
                                       double* best_us);

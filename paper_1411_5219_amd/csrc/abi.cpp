@@ -132,9 +132,13 @@ std::mutex g_launch_mu;
 // right-hand sides in groups of 4, FP16 tiles of 2 in groups of 4.
 // The staggered hop (colour vectors of 48 / 24 / 16 bytes) gains less from
 // neighbour reuse: memory order in FP64, row tiles of 192 in FP32 and FP16.
-Launch g_launch[3][3] = {{{256, 1, 1, 1, 4}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
+Launch g_launch[4][3] = {{{256, 1, 1, 1, 4}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},
                          {{256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}, {256, 0, 0, 1, 0}},
-                         {{256, 1, 0, 1, 0}, {192, 1, 1, 1, 0}, {192, 1, 1, 1, 0}}};
+                         {{256, 1, 0, 1, 0}, {192, 1, 1, 1, 0}, {192, 1, 1, 1, 0}},
+                         // several right-hand sides (the autotuner for them also tries
+                         // 128- and 192-thread requests; no default beat these across
+                         // 24^3x8, 32^3x8 and 48^3x12 by more than the run-to-run spread)
+                         {{256, 1, 1, 1, 4}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}}};
 
 int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
 
@@ -197,7 +201,11 @@ struct Op {
     RedScratch rs;
     Launch dcfg, bcfg;
 
-    void tune() { dcfg = launch_for(LQCD_KERNEL_DSLASH, prec); bcfg = launch_for(LQCD_KERNEL_BLAS, prec); }
+    void tune()
+    {
+        dcfg = launch_for(nrhs > 1 ? LQCD_KERNEL_DSLASH_RHS : LQCD_KERNEL_DSLASH, prec);
+        bcfg = launch_for(LQCD_KERNEL_BLAS, prec);
+    }
 
     DslashArgs base() const
     {
@@ -1424,7 +1432,8 @@ int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, const lqcd_so
 
 int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
 {
-    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS && kernel != LQCD_KERNEL_STAG)
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS && kernel != LQCD_KERNEL_STAG &&
+        kernel != LQCD_KERNEL_DSLASH_RHS)
         return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
     const int k = prec_slot(prec);
     if (k < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
@@ -1446,7 +1455,8 @@ int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
 
 int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
 {
-    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS && kernel != LQCD_KERNEL_STAG)
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_BLAS && kernel != LQCD_KERNEL_STAG &&
+        kernel != LQCD_KERNEL_DSLASH_RHS)
         return set_error(LQCD_EINVAL, "unknown kernel %d", kernel);
     const int k = prec_slot(prec);
     if (k < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
@@ -1508,7 +1518,7 @@ int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const voi
     o.nrhs = nrhs;
     o.pb = parity_bytes(g, op->prec);
     o.s = static_cast<hipStream_t>(stream);
-    const Launch shape = launch_for(LQCD_KERNEL_DSLASH, op->prec);
+    const Launch shape = launch_for(LQCD_KERNEL_DSLASH_RHS, op->prec);
     hipEvent_t e0, e1;
     LQCD_HIP(hipEventCreate(&e0));
     LQCD_HIP(hipEventCreate(&e1));
@@ -1516,35 +1526,39 @@ int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const voi
     float win_ms = 0.f;
     bool have = false;
     int result = LQCD_OK;
+    const int blocks[3] = {128, 192, 256};
     const int tiles[3] = {1, 2, 4};
     const int groups[5] = {0, 2, 4, 8, 16};
-    for (int ti = 0; ti < 3 && !result; ++ti) {
-        if (dslash_rhs_tile(op->prec, tiles[ti], nrhs) != tiles[ti]) continue;  // not compiled / larger than nrhs
-        for (int gi = 0; gi < 5 && !result; ++gi) {
-            Launch cfg = shape;
-            cfg.rhs_tile = tiles[ti];
-            cfg.rhs_group = groups[gi];
-            o.dcfg = cfg;
-            auto hop = [&]() {
-                return o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
-                             PRED_ALWAYS);
-            };
-            hipError_t e = hipSuccess;
-            for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hop();
-            if (e == hipSuccess) e = hipEventRecord(e0, o.s);
-            for (int i = 0; i < reps && e == hipSuccess; ++i) e = hop();
-            if (e == hipSuccess) e = hipEventRecord(e1, o.s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                result = set_error(LQCD_EHIP, "autotune: %s", hipGetErrorString(e));
-                break;
-            }
-            if (!have || ms < win_ms) {
-                have = true;
-                win_ms = ms;
-                win = cfg;
+    for (int bi = 0; bi < 3 && !result; ++bi) {
+        for (int ti = 0; ti < 3 && !result; ++ti) {
+            if (dslash_rhs_tile(op->prec, tiles[ti], nrhs) != tiles[ti]) continue;  // not compiled / larger than nrhs
+            for (int gi = 0; gi < 5 && !result; ++gi) {
+                Launch cfg = shape;
+                cfg.block = blocks[bi];
+                cfg.rhs_tile = tiles[ti];
+                cfg.rhs_group = groups[gi];
+                o.dcfg = cfg;
+                auto hop = [&]() {
+                    return o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
+                                 PRED_ALWAYS);
+                };
+                hipError_t e = hipSuccess;
+                for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hop();
+                if (e == hipSuccess) e = hipEventRecord(e0, o.s);
+                for (int i = 0; i < reps && e == hipSuccess; ++i) e = hop();
+                if (e == hipSuccess) e = hipEventRecord(e1, o.s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    result = set_error(LQCD_EHIP, "autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                if (!have || ms < win_ms) {
+                    have = true;
+                    win_ms = ms;
+                    win = cfg;
+                }
             }
         }
     }
@@ -1553,9 +1567,7 @@ int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const voi
     if (result) return result;
     {
         std::lock_guard<std::mutex> lk(g_launch_mu);
-        Launch& slot = g_launch[LQCD_KERNEL_DSLASH][prec_slot(op->prec)];
-        slot.rhs_tile = win.rhs_tile;
-        slot.rhs_group = win.rhs_group;
+        g_launch[LQCD_KERNEL_DSLASH_RHS][prec_slot(op->prec)] = win;
     }
     if (best) {
         best->block = win.block;

@@ -59,7 +59,7 @@ class Launch(ctypes.Structure):
                 ("rhs_tile", ctypes.c_int32), ("rhs_group", ctypes.c_int32)]
 
 
-KERNEL_DSLASH, KERNEL_BLAS, KERNEL_STAG = 0, 1, 2
+KERNEL_DSLASH, KERNEL_BLAS, KERNEL_STAG, KERNEL_DSLASH_RHS = 0, 1, 2, 3
 
 
 class SolveInfo(ctypes.Structure):

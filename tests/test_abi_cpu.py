@@ -123,12 +123,21 @@ def test_launch_validation():
         with pytest.raises(L.LqcdError) as e:
             L.lqcd_set_launch(kernel, prec, **cfg)
         assert e.value.code == L.EINVAL, cfg
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_set_launch(4, 64, 256)
+    assert e.value.code == L.EINVAL
     saved = L.lqcd_get_launch(L.KERNEL_DSLASH, 32)
+    saved_rhs = L.lqcd_get_launch(L.KERNEL_DSLASH_RHS, 32)
     try:
         L.lqcd_set_launch(L.KERNEL_DSLASH, 32, 256, 1, 6, 1, 4)
         assert L.lqcd_get_launch(L.KERNEL_DSLASH, 32)["order"] == 6
+        assert L.lqcd_get_launch(L.KERNEL_DSLASH_RHS, 32) == saved_rhs  # separate slots
+        L.lqcd_set_launch(L.KERNEL_DSLASH_RHS, 32, 128, 1, 1, 2, 8)
+        assert L.lqcd_get_launch(L.KERNEL_DSLASH_RHS, 32) == dict(block=128, swizzle=1, order=1, rhs_tile=2,
+                                                                   rhs_group=8)
     finally:
         L.lqcd_set_launch(L.KERNEL_DSLASH, 32, **saved)
+        L.lqcd_set_launch(L.KERNEL_DSLASH_RHS, 32, **saved_rhs)
 
 
 

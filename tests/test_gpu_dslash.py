@@ -136,9 +136,9 @@ def test_multi_rhs_equals_single(mods, prec, recon, tile, group):
     o = lqcd.op(0.16, 0.005, prec, recon)
     Ud = lat.gauge(U, prec, recon)
     inp = lat.spinor(psi, prec)
-    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, prec)
     try:
-        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **dict(saved, rhs_tile=tile, rhs_group=group))
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **dict(saved, rhs_tile=tile, rhs_group=group))
         out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec, nrhs=5)
         lqcd.dslash_apply(lat.g, o, Ud, inp, out, nrhs=5)
         got = lat.unpack(out, prec, nrhs=5)
@@ -149,14 +149,16 @@ def test_multi_rhs_equals_single(mods, prec, recon, tile, group):
             err = site_rel_err(got[k], lat.unpack(o1, prec))
             assert err <= {64: 1e-15, 32: 1e-6, 16: 2e-3}[prec], (k, err)
     finally:
-        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **saved)
 
 
 @pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
 def test_rhs_autotune(mods, prec, recon):
-    """The right-hand-side autotuner keeps the block shape, installs one of the
-    compiled tiles and groups, and the tuned even-odd hop of 6 right-hand
-    sides still equals the oracle's hop of each."""
+    """The right-hand-side autotuner keeps the XCD remap and block order,
+    installs one of the block requests and compiled tiles and groups in the
+    several-right-hand-side slot (the single-RHS slot untouched), and the
+    tuned even-odd hop of 6 right-hand sides still equals the oracle's hop of
+    each."""
     torch, fields, lqcd = mods
     L4, theta = (8, 6, 10, 4), (0.0, 0.0, 0.0, math.pi)
     U, psi = _setup(L4, theta, seed=4, kind="exp", nrhs=6)
@@ -165,13 +167,16 @@ def test_rhs_autotune(mods, prec, recon):
     o = lqcd.op(0.16, 0.005, prec, recon)
     Ud = lat.gauge(U, prec, recon)
     src = lat.parity_view(lat.spinor(psi, prec), 1, prec, nrhs=6)
-    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, prec)
+    single = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
     try:
         scratch = lat.empty(lqcd.FIELD_SPINOR_PARITY, prec, nrhs=6)
         best, us = lqcd.lqcd_autotune_dslash_rhs(lat.g, o, Ud, src, scratch, 6, reps=3)
-        now = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec)
+        now = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, prec)
         assert now == best and us > 0
-        assert {k: now[k] for k in ("block", "swizzle", "order")} == {k: saved[k] for k in ("block", "swizzle", "order")}
+        assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec) == single
+        assert {k: now[k] for k in ("swizzle", "order")} == {k: saved[k] for k in ("swizzle", "order")}
+        assert now["block"] in (128, 192, 256)
         assert now["rhs_tile"] in ((1, 2) if prec == 64 else (1, 2, 4)) and now["rhs_group"] in (0, 2, 4, 8, 16)
         out = lat.zeros(lqcd.FIELD_SPINOR_FULL, prec, nrhs=6)
         pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, prec)
@@ -183,7 +188,7 @@ def test_rhs_autotune(mods, prec, recon):
             ref = W.hop_eo(U, psi[k], L4, theta, 0)
             assert site_rel_err(got[k], ref) <= TOL[prec], k
     finally:
-        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, prec, **saved)
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **saved)
 
 
 def test_pack_roundtrip(mods):
