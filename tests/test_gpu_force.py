@@ -175,3 +175,23 @@ def test_md_reversible(md):
     U2, P2 = run.leapfrog(U1, -P1, phi, 0.05, 4)
     assert np.max(np.abs(U2 - U)) <= 1e-9
     assert np.max(np.abs(P2 + P)) <= 1e-9
+
+
+def test_trajectory(md):
+    """A whole trajectory (momentum and pseudo-fermion heatbath, leapfrog,
+    Metropolis) at a small step: |dH| small, the accept decision follows dH,
+    and the accepted links stay in SU(3)."""
+    hmc, run, U, P, phi, _ = md
+    rng = np.random.default_rng(43)
+    U1, accepted, dH = run.trajectory(U, rng, tau=0.1, nsteps=20)
+    print(f"\n[md] trajectory dH = {dH:.3e} accepted = {accepted}", flush=True)
+    assert abs(dH) < 0.1
+    if dH <= 0:
+        assert accepted
+    if accepted:
+        eye = np.eye(3)
+        assert np.allclose(U1 @ np.conj(np.swapaxes(U1, -1, -2)), eye, atol=1e-12)
+        assert np.allclose(np.linalg.det(U1), 1.0, atol=1e-12)
+        assert not np.array_equal(U1, U)
+    else:
+        assert U1 is U
