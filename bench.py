@@ -34,6 +34,11 @@ step wall time.  The JSON line also carries the roofline of the FP64 Dslash
 kernel, time-to-solution of every solve with its comparison (FP64 vs mixed,
 batched vs separate solves, measured once outside the timed steps), and the
 FP64 CPU oracle's throughput on a bounded sample of the FP64 solve.
+
+The oracle appears here only as the CPU baseline timed beside the GPU
+figures (cpu_baseline, the staggered and force samples, the oracle hop of
+--sweep, the oracle solves of --oracle-solves); nothing it computes feeds the
+library's path.
 """
 
 from __future__ import annotations
