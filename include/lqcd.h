@@ -99,7 +99,8 @@ typedef struct {
  *   eo             1: even-odd Schur complement; 0: full lattice
  *   inner_prec     64: plain FP64; 32 or 16: mixed precision with an inner
  *                  Dslash in FP32 or FP16 storage and FP64 reliable updates
- *   inner_recon    18 or 12: links of the inner Dslash
+ *   inner_recon    18 or 12: links of the inner Dslash (built from the FP64
+ *                  links, 18- or 12-real, at the start of the solve)
  *   nrhs           right-hand sides (1..16), solved together
  *   delta_reliable reliable-update trigger (||r_low|| < delta * max ||r_low||)
  *   use_graph      1: replay iterations from a captured HIP graph

@@ -640,7 +640,6 @@ struct CgSystem {
             t = eo ? sp.v[4] : nullptr;
             bhat = eo ? sp.v[5] : nullptr;
         } else {
-            if (opi->recon != 18) return set_error(LQCD_EUNSUPPORTED, "mixed precision reads FP64/18 links");
             t64 = sp.v[1];
             bhat = sp.v[2];
             lo = o;
@@ -663,7 +662,7 @@ struct CgSystem {
     {
         int rc = solver_setup(o, prm, eo, mixed, bc, xc, bhat, mixed ? t64 : t);
         if (rc) return rc;
-        if (mixed) LQCD_K(launch_convert_gauge(lo.prec, lo.recon, o.g, o.U, sp.Ulo, o.s));
+        if (mixed) LQCD_K(launch_convert_gauge(lo.prec, lo.recon, o.g, o.U, o.recon, sp.Ulo, o.s));
         return LQCD_OK;
     }
 

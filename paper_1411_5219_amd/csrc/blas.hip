@@ -654,7 +654,10 @@ hipError_t launch_unpack_colour(int prec, const Geom& g, const void* in, void* c
     return pack_kind<KIND_COLOUR>(prec, false, g, canon, in, nullptr, nrhs, s);
 }
 
-template <int PREC, int RECON, bool FROM_CANON>
+// Links into storage (PREC, RECON), from canonical complex128 (FROM_CANON)
+// or from the internal FP64 field with SRC_RECON reals per link (a 12-real
+// source has its third row rebuilt in FP64 first).
+template <int PREC, int RECON, bool FROM_CANON, int SRC_RECON = 18>
 __global__ void __launch_bounds__(256) k_pack_gauge(const Geom g, const double2* canon, const void* U64, void* out)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -670,22 +673,22 @@ __global__ void __launch_bounds__(256) k_pack_gauge(const Geom g, const double2*
 #pragma unroll
         for (int k = 0; k < 9; ++k) U.u[k / 3][k % 3] = {c[k].x, c[k].y};
     } else {
-        LinkIO<64, 18>::load(U64, g.S, blk, h, U);
+        LinkIO<64, SRC_RECON>::load(U64, g.S, blk, h, U);
     }
     LinkIO<PREC, RECON>::store(out, g.S, blk, h, U);
 }
 
-template <bool FC>
+template <bool FC, int SRC = 18>
 static hipError_t pack_gauge_any(int prec, int recon, const Geom& g, const void* canon, const void* U64, void* out,
                                  hipStream_t s)
 {
     dim3 b(256), gr((unsigned)((g.Vh + 255) / 256), 8);
     const double2* c = static_cast<const double2*>(canon);
-    if (prec == 64 && recon == 18) hipLaunchKernelGGL((k_pack_gauge<64, 18, FC>), gr, b, 0, s, g, c, U64, out);
-    else if (prec == 64 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<64, 12, FC>), gr, b, 0, s, g, c, U64, out);
-    else if (prec == 32 && recon == 18) hipLaunchKernelGGL((k_pack_gauge<32, 18, FC>), gr, b, 0, s, g, c, U64, out);
-    else if (prec == 32 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<32, 12, FC>), gr, b, 0, s, g, c, U64, out);
-    else if (prec == 16 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<16, 12, FC>), gr, b, 0, s, g, c, U64, out);
+    if (prec == 64 && recon == 18) hipLaunchKernelGGL((k_pack_gauge<64, 18, FC, SRC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 64 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<64, 12, FC, SRC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 32 && recon == 18) hipLaunchKernelGGL((k_pack_gauge<32, 18, FC, SRC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 32 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<32, 12, FC, SRC>), gr, b, 0, s, g, c, U64, out);
+    else if (prec == 16 && recon == 12) hipLaunchKernelGGL((k_pack_gauge<16, 12, FC, SRC>), gr, b, 0, s, g, c, U64, out);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -695,9 +698,12 @@ hipError_t launch_pack_gauge(int prec, int recon, const Geom& g, const void* can
     return pack_gauge_any<true>(prec, recon, g, canon, nullptr, out, s);
 }
 
-hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, void* out, hipStream_t s)
+hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, int src_recon, void* out,
+                                hipStream_t s)
 {
-    return pack_gauge_any<false>(prec, recon, g, nullptr, U64, out, s);
+    if (src_recon == 12) return pack_gauge_any<false, 12>(prec, recon, g, nullptr, U64, out, s);
+    if (src_recon == 18) return pack_gauge_any<false, 18>(prec, recon, g, nullptr, U64, out, s);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

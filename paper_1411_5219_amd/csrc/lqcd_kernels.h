@@ -320,7 +320,8 @@ hipError_t launch_pack_colour(int prec, const Geom& g, const void* canon, void* 
 hipError_t launch_unpack_colour(int prec, const Geom& g, const void* in, void* canon, int nrhs, hipStream_t s);
 hipError_t launch_pack_gauge(int prec, int recon, const Geom& g, const void* canon, void* out, hipStream_t s);
 // Re-encode an internal FP64/18 gauge field at another precision / recon.
-hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, void* out, hipStream_t s);
+hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* U64, int src_recon, void* out,
+                                hipStream_t s);
 
 // Fill memory with zero bytes through a kernel (graph-capture safe).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -27,12 +27,12 @@ def mods():
     return torch, fields, lqcd
 
 
-def run_solve(mods, L4, theta, U, b, kappa, mu, method="cg", nrhs=1, stream=None, **kw):
+def run_solve(mods, L4, theta, U, b, kappa, mu, method="cg", nrhs=1, stream=None, outer_recon=18, **kw):
     torch, fields, lqcd = mods
     lat = fields.Lattice(L4, theta)
-    o = lqcd.op(kappa, mu, 64, 18)
+    o = lqcd.op(kappa, mu, 64, outer_recon)
     p = lqcd.solve_params(nrhs=nrhs, **kw)
-    Ud = lat.gauge(U)
+    Ud = lat.gauge(U, 64, outer_recon)
     bd = lat.spinor(b)
     xd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=nrhs)
     ws = lat.workspace(o, p)
@@ -87,6 +87,23 @@ def test_twisted_mass_eo_mixed(mods, inner):
     tr = true_res(U, x, b, L4, theta, kappa, mu)
     print(f"  iters={info[0]['iters']} updates={info[0]['reliable_updates']} true={tr:.2e}", flush=True)
     assert tr <= 1e-10
+
+
+@pytest.mark.parametrize("inner", [(64, 18), (32, 12), (32, 18), (16, 12)])
+def test_mixed_on_12_real_fp64_links(mods, inner):
+    """The FP64 system on 12-real links (third row rebuilt in FP64), plain and
+    with every inner precision (the inner links are built from the 12-real
+    field): certified by the oracle's M on the original 18-real links, the
+    difference being rounding of the rebuilt row."""
+    L4, theta, kappa, mu = (8, 8, 8, 4), (0, 0, 0, math.pi), 0.16, 0.005
+    U = gauge_field(L4, "exp", eps=0.4, seed=1001)
+    b = gaussian_spinor(L4, seed=2001)
+    print(f"\n[case] 8^3x4 tm on FP64/12 links, inner={inner}", flush=True)
+    rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "cg", outer_recon=12, tol=1e-10, maxiter=20000,
+                            inner_prec=inner[0], inner_recon=inner[1])
+    assert rc == 0, info
+    tr = true_res(U, x, b, L4, theta, kappa, mu)
+    assert tr <= 1e-10 and abs(tr - info[0]["true_resid"]) <= 1e-13
 
 
 def test_bicgstab_twisted_eo(mods):
