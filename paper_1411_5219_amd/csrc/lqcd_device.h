@@ -448,12 +448,32 @@ struct Link {
 };
 
 // Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
+// conj(a b - c d), the entry of the third row of an SU(3) matrix rebuilt
+// from the first two.  In FP32 each real part is one chain of fused
+// multiply-adds (1 multiply + 3 FMAs; as written it compiles to 2
+// multiplies, 2 FMAs and a subtract); FP64 keeps the written form, for the
+// register budget of its hop (see su3_row).
+template <class R>
+__device__ __forceinline__ cplx<R> conj_cross(cplx<R> a, cplx<R> b, cplx<R> c, cplx<R> d)
+{
+    if constexpr (sizeof(R) == 8) return conj(a * b - c * d);
+    R re = a.x * b.x;
+    re = fmar(-a.y, b.y, re);
+    re = fmar(-c.x, d.x, re);
+    re = fmar(c.y, d.y, re);
+    R im = -(a.x * b.y);
+    im = fmar(-a.y, b.x, im);
+    im = fmar(c.x, d.y, im);
+    im = fmar(c.y, d.x, im);
+    return {re, im};
+}
+
 template <class R>
 __device__ __forceinline__ void reconstruct_row2(Link<R>& U)
 {
-    U.u[2][0] = conj(U.u[0][1] * U.u[1][2] - U.u[0][2] * U.u[1][1]);
-    U.u[2][1] = conj(U.u[0][2] * U.u[1][0] - U.u[0][0] * U.u[1][2]);
-    U.u[2][2] = conj(U.u[0][0] * U.u[1][1] - U.u[0][1] * U.u[1][0]);
+    U.u[2][0] = conj_cross(U.u[0][1], U.u[1][2], U.u[0][2], U.u[1][1]);
+    U.u[2][1] = conj_cross(U.u[0][2], U.u[1][0], U.u[0][0], U.u[1][2]);
+    U.u[2][2] = conj_cross(U.u[0][0], U.u[1][1], U.u[0][1], U.u[1][0]);
 }
 
 template <int PREC, int RECON>
