@@ -354,7 +354,8 @@ def lqcd_autotune_stag(g, o, U, inp, out, reps=10, stream=None):
 
 
 def lqcd_autotune_dslash_rhs(g, o, U, inp, out, nrhs, reps=10, stream=None):
-    """Tunes the right-hand-side tile and group for nrhs stacked fields; returns (launch, us per launch)."""
+    """Tunes the launch shape of hops on nrhs stacked fields (block request, tile, group) and installs it
+    as KERNEL_DSLASH_RHS; returns (launch, us per launch)."""
     best = Launch()
     us = ctypes.c_double()
     _check(_lib.lqcd_autotune_dslash_rhs(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(nrhs),
