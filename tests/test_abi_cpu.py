@@ -204,3 +204,20 @@ def test_force_and_gamma5_validation():
             L.lqcd_gamma5(g, inp, 32, nrhs=nrhs, stream=0)
         assert e.value.code == L.EINVAL
     assert L._lib.lqcd_device_memory(0, None, None) == L.EINVAL
+
+
+def test_rhs_launch_slot_validation():
+    """The several-right-hand-side launch family takes the Dslash's shape
+    rules, and its autotuner refuses bad arguments before any device work."""
+    from paper_1411_5219_amd import lqcd as L
+    for cfg in (dict(block=96), dict(block=256, rhs_tile=3), dict(block=256, rhs_group=17),
+                dict(block=256, order=65)):
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_set_launch(L.KERNEL_DSLASH_RHS, 32, **cfg)
+        assert e.value.code == L.EINVAL, cfg
+    g = L.geom((4, 4, 4, 4))
+    o = L.op(0.16, 0.005, 32, 12)
+    for nrhs, reps, inp, out in ((1, 3, 16, 32), (17, 3, 16, 32), (4, 0, 16, 32), (4, 3, None, 32), (4, 3, 16, 16)):
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_autotune_dslash_rhs(g, o, 48, inp, out, nrhs, reps=reps, stream=0)
+        assert e.value.code == L.EINVAL, (nrhs, reps, inp, out)
