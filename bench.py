@@ -25,7 +25,9 @@ shifts against the same 8 systems solved one at a time; it is reported in
 its own block and is not part of `value`.  So is the N_f = 2 twisted-mass
 pseudo-fermion force on the same lattice: the force kernel alone (HIP
 events) and one whole force evaluation as an HMC step makes it (two mixed
-FP32/12 solves to 1e-10 and the kernel).
+FP32/12 solves to 1e-10 and the kernel).  And the uneven batch once more on
+small lattices (8^3x4, 6^3x8, 8^3x8, 10^3x4), where a solve is bound by
+launch latency rather than memory.
 
 `value` is whole-step throughput in the metric's unit: compulsory Dslash
 bytes of every hop in the step (input spinor, links, output spinor per
@@ -70,6 +72,9 @@ UNEVEN = [((16, 16, 16, 8), 0.3, 0.15), ((20, 20, 20, 8), 0.4, 0.16), ((24, 24, 
 COLOUR_B = {64: 48, 32: 24, 16: 16}
 STAG_HOP_BYTES = {k: 2 * COLOUR_B[k[0]] + 8 * v for k, v in LINK_B.items()}
 STAG_MASS = 0.1
+# small systems for the batching comparison in the launch-bound regime
+UNEVEN_SMALL = [((8, 8, 8, 4), 0.3, 0.15), ((6, 6, 6, 8), 0.4, 0.16), ((8, 8, 8, 8), 0.5, 0.155),
+                ((10, 10, 10, 4), 0.4, 0.16)]
 # reliable-update threshold per inner precision: the largest drop of the
 # low-precision residual before the FP64 true residual is recomputed
 # (measured on 48^3x12: FP32 inner 10 -> 5 updates at the same 53
@@ -159,6 +164,55 @@ def oracle_staggered_sample(U, chi, L, theta, mass, shifts, cg_iters, ms_iters, 
         per = t / (n + 1)
         out[name] = {"iterations_run": n, "seconds": t, "seconds_per_iteration": per,
                      "seconds_extrapolated": per * (gpu_iters + 1), "library_iterations": gpu_iters}
+    return out
+
+
+def uneven_small(stream, mu, tol, delta):
+    """The uneven batch on small lattices (launch-latency bound): one batched
+    CGNR replayed from a HIP graph against the systems solved one after the
+    other, both the median of 3; 4 Gaussian sources per system, FP32/12
+    inner."""
+    import numpy as np
+    import torch
+
+    from lattice_inputs import gauge_field, gaussian_spinor
+    from paper_1411_5219_amd import fields, lqcd
+
+    p = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=4, use_graph=1,
+                          delta_reliable=delta)
+    gs, os_, Us, bs, xs, lats = [], [], [], [], [], []
+    with torch.cuda.stream(stream):
+        for i, (Li, epsi, kappai) in enumerate(UNEVEN_SMALL):
+            lt = fields.Lattice(Li, THETA, device=torch.device("cuda:0"))
+            gs.append(lt.g)
+            os_.append(lqcd.op(kappai, mu))
+            Us.append(lt.gauge(gauge_field(Li, "exp", eps=epsi, seed=1104 + 10 * i)))
+            bs.append(lt.spinor(gaussian_spinor(Li, seed=2104 + 10 * i, nrhs=4)))
+            xs.append(lt.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=4))
+            lats.append(lt)
+        ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(gs, os_, p), dtype=torch.uint8, device="cuda")
+        wsu = [lats[i].workspace(os_[i], p) for i in range(len(lats))]
+    tb, ts, iters = [], [], None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = lqcd.cg_solve_batch(gs, os_, Us, bs, xs, p, ws, stream=stream)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        if rc != 0:
+            raise RuntimeError(f"small uneven batch failed: {infos}")
+        iters = [max(i["iters"] for i in inf) for inf in infos]
+        t0 = time.perf_counter()
+        for i in range(len(lats)):
+            rc, info = lqcd.cg_solve(gs[i], os_[i], Us[i], bs[i], xs[i], p, wsu[i], stream=stream)
+            if rc != 0:
+                raise RuntimeError(f"small system {i} failed: {info}")
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    out = {"lattices": [list(x[0]) for x in UNEVEN_SMALL], "rhs_per_lattice": 4, "inner": "FP32/12",
+           "graph_replay": True, "seconds_median": float(np.median(tb)), "iters_max": iters,
+           "per_system_solves_seconds": float(np.median(ts))}
+    out["speedup_vs_per_system"] = out["per_system_solves_seconds"] / out["seconds_median"]
     return out
 
 
@@ -728,6 +782,8 @@ def main():
     force = tm_force(lat, U, b, kappa, mu, stream, log, oracle_links=0 if args.no_cpu_baseline else 2000)
     log("stream probe")
     probe = stream_probe(stream)
+    log("small uneven batch")
+    small = uneven_small(stream, mu, tol, DELTA[32])
 
     hop_stats = {}
     for k, evs in rec["hops"].items():
@@ -794,6 +850,7 @@ def main():
         "solves": solve_stats,
         "multi_rhs": multi,
         "uneven_batch": uneven,
+        "uneven_batch_small": small,
         "staggered": stag,
         "tm_force": force,
         "stream_probe": probe,
