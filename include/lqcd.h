@@ -102,7 +102,26 @@ typedef struct {
  *   inner_recon    18 or 12: links of the inner Dslash (built from the FP64
  *                  links, 18- or 12-real, at the start of the solve)
  *   nrhs           right-hand sides (1..16), solved together
- *   delta_reliable reliable-update trigger (||r_low|| < delta * max ||r_low||)
+ *   delta_reliable reliable-update trigger (||r_low|| < delta * max ||r_low||
+ *                  since the last update), in (0, 1)
+ * Mixed precision only (the inner solve is CGNR at low precision inside an
+ * outer FP64 defect correction; reliable updates fold the low-precision x
+ * into the FP64 x and replace the low-precision residual by the FP64 one):
+ *   tol_inner      0: one outer step (the search direction survives every
+ *                  reliable update); in (0, 1): an outer step ends when
+ *                  ||r_low|| <= tol_inner ||r|| of the step's start, and the
+ *                  next starts from the FP64 residual with a fresh search
+ *                  direction
+ *   stag_window    stagnation test of the inner solve: stag_window iterations
+ *                  without a reliable update (no reduction of ||r_low|| by
+ *                  delta) count as a stagnation, and so does a reliable update
+ *                  whose FP64 residual is not below the previous one; each
+ *                  stagnation restarts the search direction at the next
+ *                  update.  0: 500 iterations; < 0: no iteration window
+ *   max_stagnations inner_prec 16: after this many stagnations the solve
+ *                  continues from its current x with FP32 inner storage (the
+ *                  workspace then holds FP32 inner fields).  0: 3; < 0: never.
+ *                  Batched solves (cg_solve_batch) never fall back.
  *   use_graph      1: replay iterations from a captured HIP graph
  *   check_every    iterations enqueued between status read-backs (>= 1) */
 typedef struct {
@@ -115,20 +134,28 @@ typedef struct {
     int32_t use_graph;
     double delta_reliable;
     int32_t check_every;
-    int32_t reserved;
+    int32_t stag_window;
+    double tol_inner;
+    int32_t max_stagnations;
+    int32_t reserved;          /* set to 0 */
 } lqcd_solve_params;
 
 /* Filled by the solvers (one per right-hand side / system). */
 typedef struct {
     int32_t status;            /* mirrors the return code */
-    int32_t iters;             /* Krylov iterations */
+    int32_t iters;             /* Krylov iterations (inner iterations for mixed precision) */
     int32_t reliable_updates;  /* FP64 residual replacements (mixed precision) */
-    int32_t restarts;          /* restarts after a failed true-residual check */
+    int32_t restarts;          /* restarts after a failed true-residual check (multi-shift:
+                                  refinement passes of this shift) */
     double true_resid;         /* ||b - M x||_2 / ||b||_2 in FP64, full lattice */
     double seconds;            /* wall time of the call */
     double hops_outer;         /* Dslash applications at the outer (FP64) precision, in units
                                   of one even-odd hop over V/2 output sites */
     double hops_inner;         /* same, at the inner precision (mixed precision only) */
+    int32_t outer_iters;       /* outer defect-correction steps (1 + steps ended by tol_inner) */
+    int32_t stagnations;       /* stagnations of the inner solve detected */
+    int32_t fallbacks;         /* 1: the FP16 inner solve continued at FP32 storage */
+    int32_t reserved;
 } lqcd_solve_info;
 
 /* Launch configuration of a kernel family (LQCD_KERNEL_DSLASH: the Wilson

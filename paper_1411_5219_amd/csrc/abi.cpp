@@ -46,6 +46,7 @@ int set_error(int code, const char* fmt, ...)
 #endif
 
 constexpr int kMaxRhs = 16;
+constexpr int kMaxRefine = 4;                  // refinement passes of a multi-shift system
 constexpr int kMaxSys = 16;                    // systems in one batched solve
 constexpr int kPinned = kMaxRhs * kMaxSys;     // control blocks read back at once
 constexpr int kMinBlock = 64;  // smallest block size any launcher uses (partials sizing)
@@ -349,6 +350,21 @@ int pinned_ctl(Ctl** out)
 
 enum Method { M_CG = 0, M_BICG = 1 };
 
+// Defaults of the stagnation handling of mixed-precision solves.
+constexpr int kDefaultStagWindow = 500;   // iterations without a reliable update
+constexpr int kDefaultMaxStag = 3;        // stagnations before FP16 storage falls back to FP32
+
+int stag_window_of(const lqcd_solve_params* p)
+{
+    return p->stag_window == 0 ? kDefaultStagWindow : p->stag_window < 0 ? 0 : p->stag_window;
+}
+int max_stag_of(const lqcd_solve_params* p)
+{
+    return p->max_stagnations == 0 ? kDefaultMaxStag : p->max_stagnations < 0 ? 0 : p->max_stagnations;
+}
+// An FP16 inner solve of a single system may continue at FP32 storage.
+bool may_fall_back(const lqcd_solve_params* p) { return p->inner_prec == 16 && max_stag_of(p) > 0; }
+
 // Workspace plan of one solver call: the reductions first, then the vectors.
 struct SolverPlan {
     RedScratch rs;
@@ -358,7 +374,8 @@ struct SolverPlan {
     size_t bytes = 0;
 };
 
-int plan_solver(const Geom& g, const lqcd_op* op, const lqcd_solve_params* prm, int method, void* ws, SolverPlan* sp)
+int plan_solver(const Geom& g, const lqcd_op* op, const lqcd_solve_params* prm, int method, void* ws, SolverPlan* sp,
+                bool single = true)
 {
     Arena ar{static_cast<char*>(ws), 0, 0};
     const int nrhs = prm->nrhs;
@@ -374,10 +391,13 @@ int plan_solver(const Geom& g, const lqcd_op* op, const lqcd_solve_params* prm, 
     else nv = eo ? 8 : 6;
     for (int i = 0; i < nv; ++i) sp->v[i] = ar.take((size_t)vec);
     if (mixed) {
-        const int64_t lpb = parity_bytes(g, prm->inner_prec);
+        // an FP16 inner solve that may fall back to FP32 storage holds
+        // FP32-sized inner fields and links from the start
+        const int lp = single && may_fall_back(prm) ? 32 : prm->inner_prec;
+        const int64_t lpb = parity_bytes(g, lp);
         // xl rl pl wl zl tl
         for (int i = 0; i < 6; ++i) sp->lo[i] = ar.take((size_t)(lpb * nrhs));
-        sp->Ulo = ar.take((size_t)gauge_bytes(g, prm->inner_prec, prm->inner_recon));
+        sp->Ulo = ar.take((size_t)gauge_bytes(g, lp, prm->inner_recon));
     }
     (void)op;
     sp->bytes = align_up(ar.off, 256);
@@ -397,6 +417,8 @@ int check_params(const lqcd_solve_params* p, int method)
         if (rc) return rc;
         if (!(p->delta_reliable > 0.0 && p->delta_reliable < 1.0))
             return set_error(LQCD_EINVAL, "delta_reliable must be in (0, 1)");
+        if (!(p->tol_inner >= 0.0 && p->tol_inner < 1.0))
+            return set_error(LQCD_EINVAL, "tol_inner must be in [0, 1)");
     }
     return LQCD_OK;
 }
@@ -494,7 +516,7 @@ unsigned reopen_mask(const Ctl* ctl, int nrhs, const lqcd_solve_params* prm)
 }
 
 void fill_info(const Ctl* ctl, int nrhs, int method, bool eo, bool mixed, int restarts, double secs,
-               const lqcd_solve_params* prm, lqcd_solve_info* info, int* worst)
+               const lqcd_solve_params* prm, lqcd_solve_info* info, int* worst, unsigned fallbacks = 0)
 {
     for (int i = 0; i < nrhs; ++i) {
         lqcd_solve_info& in = info[i];
@@ -516,6 +538,10 @@ void fill_info(const Ctl* ctl, int nrhs, int method, bool eo, bool mixed, int re
             in.hops_outer = prep + starts * (2.0 + finish) + 2.0 * ctl[i].nupdates;
             in.hops_inner = starts * 2.0 + 4.0 * it;
         }
+        in.outer_iters = 1 + ctl[i].nouter;
+        in.stagnations = ctl[i].nstag;
+        in.fallbacks = fallbacks ? ((fallbacks >> i) & 1u) : 0;
+        in.reserved = 0;
         int st = ctl[i].status;
         if (st == LQCD_OK && in.true_resid > prm->tol) st = LQCD_ENOCONV;
         if (st == LQCD_OK && !std::isfinite(in.true_resid)) st = LQCD_ENONFINITE;
@@ -528,12 +554,22 @@ void fill_info(const Ctl* ctl, int nrhs, int method, bool eo, bool mixed, int re
 // prepared source bhat = b_e + kappa H_eo A^-1 b_o with x_e = 0 (t is an odd
 // scratch field); full lattice: x = 0.
 int solver_setup(const Op& o, const lqcd_solve_params* prm, bool eo, bool mixed, char* bc, char* xc, void* bhat,
-                 void* t)
+                 void* t, bool allow_fallback = false)
 {
     const int nrhs = o.nrhs;
     const int64_t pb = o.pb, fb = 2 * pb;
     hipStream_t s = o.s;
-    LQCD_K(launch_ctl_init(o.rs.ctl, nrhs, prm->tol, mixed ? prm->delta_reliable : 0.0, prm->maxiter, s));
+    CtlInit ci{};
+    ci.tol = prm->tol;
+    ci.iter_limit = prm->maxiter;
+    if (mixed) {
+        ci.delta = prm->delta_reliable;
+        ci.tol_inner = prm->tol_inner;
+        ci.stag_window = stag_window_of(prm);
+        ci.max_stag = max_stag_of(prm);
+        ci.fallback_ok = allow_fallback && may_fall_back(prm) ? 1 : 0;
+    }
+    LQCD_K(launch_ctl_init(o.rs.ctl, nrhs, ci, s));
     {
         BlasArgs a = o.blas_base(2);
         a.pred = PRED_ALWAYS;
@@ -658,11 +694,25 @@ struct CgSystem {
         return LQCD_OK;
     }
 
-    int setup()
+    int setup(bool allow_fallback = false)
     {
-        int rc = solver_setup(o, prm, eo, mixed, bc, xc, bhat, mixed ? t64 : t);
+        int rc = solver_setup(o, prm, eo, mixed, bc, xc, bhat, mixed ? t64 : t, allow_fallback);
         if (rc) return rc;
         if (mixed) LQCD_K(launch_convert_gauge(lo.prec, lo.recon, o.g, o.U, o.recon, sp.Ulo, o.s));
+        return LQCD_OK;
+    }
+
+    // Continue at FP32 inner storage: the low-precision x of every right-hand
+    // side is folded into the FP64 x, the inner links are rebuilt at FP32
+    // (the workspace was planned for FP32 inner fields), and the next start()
+    // begins from the FP64 residual.
+    int fall_back_to_fp32()
+    {
+        LQCD_K(fold(PRED_ALWAYS));
+        lo.prec = 32;
+        lo.pb = parity_bytes(o.g, 32);
+        lo.tune();
+        LQCD_K(launch_convert_gauge(lo.prec, lo.recon, o.g, o.U, o.recon, sp.Ulo, o.s));
         return LQCD_OK;
     }
 
@@ -802,15 +852,28 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
     std::vector<Ctl> ctl;
     int restarts = 0;
 
+    unsigned fallbacks = 0;
     if (method == M_CG) {
         CgSystem cs;
         if ((rc = cs.init(g, opi, U, b, x, prm, sp, s))) return rc;
-        if ((rc = cs.setup())) return rc;
+        if ((rc = cs.setup(true))) return rc;
         for (;;) {
             if ((rc = cs.start())) return rc;
             rc = drive(s, sp.rs.ctl, 1, nrhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0,
                        [&]() -> int { return cs.iter(); });
             if (rc) return rc;
+            if ((rc = read_ctls(s, sp.rs.ctl, nrhs, ctl))) return rc;
+            unsigned fb = 0;
+            for (int i = 0; i < nrhs; ++i)
+                if (ctl[i].status == kStatusFallback) fb |= 1u << i;
+            if (fb) {
+                // stagnation at FP16 storage: the stalled right-hand sides
+                // continue at FP32 from their current x
+                if ((rc = cs.fall_back_to_fp32())) return rc;
+                fallbacks |= fb;
+                LQCD_K(launch_ctl_reopen(sp.rs.ctl, nrhs, fb, s, true));
+                continue;
+            }
             if ((rc = cs.finish())) return rc;
             if ((rc = read_ctls(s, sp.rs.ctl, nrhs, ctl))) return rc;
             const unsigned reopen = reopen_mask(ctl.data(), nrhs, prm);
@@ -883,7 +946,7 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
     }
 
     int worst = LQCD_OK;
-    fill_info(ctl.data(), nrhs, method, eo, mixed, restarts, now_s() - t0, prm, info, &worst);
+    fill_info(ctl.data(), nrhs, method, eo, mixed, restarts, now_s() - t0, prm, info, &worst, fallbacks);
     if (worst != LQCD_OK) set_error(worst, "solve did not converge for every right-hand side (status %d)", worst);
     return worst;
 }
@@ -912,7 +975,7 @@ int plan_batch(int nsys, const Geom* g, const lqcd_op* ops, const lqcd_solve_par
     for (int s = 0; s < nsys; ++s) {
         ar.off = align_up(ar.off, 256);
         void* base = ws ? static_cast<char*>(ws) + ar.off : nullptr;
-        plan_solver(g[s], &ops[s], prm, M_CG, base, &L->plans[s]);
+        plan_solver(g[s], &ops[s], prm, M_CG, base, &L->plans[s], false);
         L->plans[s].rs.ctl = L->ctl ? L->ctl + s * kMaxRhs : nullptr;
         ar.off += L->plans[s].bytes;
     }
@@ -1358,6 +1421,47 @@ StagOp stag_bind(const Geom& g, const lqcd_stag_op* op, const void* U, const Sta
     return o;
 }
 
+// Argument checks of dslash_eo_apply.
+int eo_apply_check(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                   int32_t out_parity, int32_t op_kind, int32_t nrhs, Geom* g)
+{
+    int rc = make_geom(geom, g);
+    if (rc) return rc;
+    if ((rc = check_op(op))) return rc;
+    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
+    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
+    if (out_parity != 0 && out_parity != 1) return set_error(LQCD_EINVAL, "out_parity must be 0 or 1");
+    if (nrhs < 1 || nrhs > kMaxRhs) return set_error(LQCD_EINVAL, "nrhs %d not in [1, %d]", nrhs, kMaxRhs);
+    if (op_kind != LQCD_OP_HOP && op_kind != LQCD_OP_SCHUR) return set_error(LQCD_EINVAL, "unknown op_kind %d", op_kind);
+    if (op_kind == LQCD_OP_SCHUR && out_parity != 0)
+        return set_error(LQCD_EINVAL, "the Schur complement acts on even sites (out_parity 0)");
+    return LQCD_OK;
+}
+
+// The hop or Schur complement; tmp holds nrhs odd parity fields at op->prec (Schur).
+int eo_apply_run(const Geom& g, const lqcd_op* op, const void* U, const void* in, void* out, int32_t out_parity,
+                 int32_t op_kind, int32_t dagger, int32_t nrhs, void* tmp, void* stream)
+{
+    Op o;
+    o.g = g;
+    o.prec = op->prec;
+    o.recon = op->recon;
+    o.U = U;
+    o.kappa = op->kappa;
+    o.mu = op->mu;
+    o.nrhs = nrhs;
+    o.pb = parity_bytes(g, op->prec);
+    o.s = static_cast<hipStream_t>(stream);
+    o.tune();
+    if (op_kind == LQCD_OP_HOP) {
+        LQCD_K(o.hop(out_parity, in, out, dagger != 0, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE,
+                     FIN_STORE, PRED_ALWAYS));
+        return LQCD_OK;
+    }
+    LQCD_K(o.schur(in, out, tmp, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS));
+    return LQCD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1670,40 +1774,17 @@ int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, con
                     int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs, void* ws, void* stream)
 {
     Geom g;
-    int rc = make_geom(geom, &g);
+    int rc = eo_apply_check(geom, op, U, in, out, out_parity, op_kind, nrhs, &g);
     if (rc) return rc;
-    if ((rc = check_op(op))) return rc;
-    if (!U || !in || !out) return set_error(LQCD_EINVAL, "NULL field pointer");
-    if (in == out) return set_error(LQCD_EINVAL, "in and out must not alias");
-    if (out_parity != 0 && out_parity != 1) return set_error(LQCD_EINVAL, "out_parity must be 0 or 1");
-    if (nrhs < 1 || nrhs > kMaxRhs) return set_error(LQCD_EINVAL, "nrhs %d not in [1, %d]", nrhs, kMaxRhs);
-    Op o;
-    o.g = g;
-    o.prec = op->prec;
-    o.recon = op->recon;
-    o.U = U;
-    o.kappa = op->kappa;
-    o.mu = op->mu;
-    o.nrhs = nrhs;
-    o.pb = parity_bytes(g, op->prec);
-    o.s = static_cast<hipStream_t>(stream);
-    o.tune();
-    if (op_kind == LQCD_OP_HOP) {
-        LQCD_K(o.hop(out_parity, in, out, dagger != 0, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE,
-                     FIN_STORE, PRED_ALWAYS));
-        return LQCD_OK;
-    }
+    void* tmp = nullptr;
     if (op_kind == LQCD_OP_SCHUR) {
-        if (out_parity != 0) return set_error(LQCD_EINVAL, "the Schur complement acts on even sites (out_parity 0)");
         if (!ws) return set_error(LQCD_EINVAL, "LQCD_OP_SCHUR needs a workspace");
         Arena ar{static_cast<char*>(ws), 0, 0};
         RedScratch rs;
         plan_reductions(ar, g, kMaxRhs, &rs);
-        void* tmp = ar.take((size_t)(o.pb * nrhs));
-        LQCD_K(o.schur(in, out, tmp, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS));
-        return LQCD_OK;
+        tmp = ar.take((size_t)(parity_bytes(g, op->prec) * nrhs));
     }
-    return set_error(LQCD_EINVAL, "unknown op_kind %d", op_kind);
+    return eo_apply_run(g, op, U, in, out, out_parity, op_kind, dagger, nrhs, tmp, stream);
 }
 
 int cg_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
@@ -1954,21 +2035,69 @@ int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const v
         LQCD_K(o.normal(xc + i * pb, nullptr, sp.t, sl.s[i], -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS, ctl + i));
     std::vector<Ctl> h;
     if ((rc = read_ctls(o.s, ctl, nshift, h))) return rc;
+    const int ms_iters = h[base].iter;
+    std::vector<int> iters(nshift), ms_own(nshift), passes(nshift, 0);
+    for (int i = 0; i < nshift; ++i) iters[i] = ms_own[i] = h[i].iter;
+    auto true_res = [&](const Ctl& c) { return c.bb > 0 ? std::sqrt(c.true_rr / c.bb) : 0.0; };
+
+    // Every shift must meet tol by its FP64 true residual.  A shift whose
+    // recursion stopped on |zeta| ||r|| but whose recomputed residual misses
+    // (rounding of the shifted recurrences) is refined by a single-shift CG on
+    // (N + s_i) started from its x_i; p_i, no longer needed by the family,
+    // serves as its search direction.
+    for (int pass = 0; pass < kMaxRefine; ++pass) {
+        bool any = false;
+        for (int i = 0; i < nshift; ++i) {
+            if (h[i].status != LQCD_OK || true_res(h[i]) <= prm->tol || iters[i] >= prm->maxiter) continue;
+            any = true;
+            ++passes[i];
+            Ctl* ci = ctl + i;
+            StagPlan si = sp;
+            si.rs.ctl = ci;
+            si.p = static_cast<char*>(sp.p) + i * pb;
+            char* xi = xc + i * pb;
+            CtlInit in{};
+            in.tol = prm->tol;
+            in.iter_limit = prm->maxiter - iters[i];
+            ShiftList one{};
+            LQCD_K(launch_ctl_init(ci, 1, in, o.s));
+            LQCD_K(launch_ctl_init_shifts(ci, 1, 0, one, o.s));
+            LQCD_K(o.blas(BLAS_NORM, 1, PRED_ALWAYS, FIN_BB_FULL, ci, bc, pb));
+            // r = b - (N + s_i) x_i ; p = r ; rr
+            LQCD_K(o.normal(xi, sp.r, sp.t, sl.s[i], -1.0, bc, RED_NONE, FIN_STORE, PRED_ACTIVE, ci));
+            LQCD_K(o.blas(BLAS_COPY, 1, PRED_ACTIVE, FIN_STORE, ci, sp.r, pb, si.p, pb));
+            LQCD_K(o.blas(BLAS_NORM, 1, PRED_ACTIVE, FIN_MS_INIT_KEEP, ci, sp.r, pb));
+            const int chunk = prm->check_every > 0 ? prm->check_every : 8;
+            rc = drive(o.s, ci, 1, 1, 1, chunk, in.iter_limit, prm->use_graph != 0,
+                       [&]() { return stag_ms_iter(o, si, xi, 1, 0, sl.s[i]); });
+            if (rc) return rc;
+            LQCD_K(o.normal(xi, nullptr, sp.t, sl.s[i], -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS, ci));
+            std::vector<Ctl> hi;
+            if ((rc = read_ctls(o.s, ci, 1, hi))) return rc;
+            iters[i] += hi[0].iter;
+            h[i] = hi[0];
+        }
+        if (!any) break;
+    }
+
     const double secs = now_s() - t0;
     int worst = LQCD_OK;
     for (int i = 0; i < nshift; ++i) {
         lqcd_solve_info& in = info[i];
-        in.iters = h[i].iter;
+        in = lqcd_solve_info{};
+        in.iters = iters[i];
         in.reliable_updates = 0;
-        in.restarts = 0;
-        in.true_resid = h[i].bb > 0 ? std::sqrt(h[i].true_rr / h[i].bb) : 0.0;
+        in.restarts = passes[i];
+        in.true_resid = true_res(h[i]);
         in.seconds = secs;
-        // the shared iterations are counted on every system: 2 hops each, plus its true residual
-        in.hops_outer = 2.0 * h[base].iter + 2.0;
+        // the shared iterations are counted on every system: 2 hops each, plus
+        // its true residual; a refinement adds its own iterations, residual
+        // and true residual
+        in.hops_outer = 2.0 * ms_iters + 2.0 + 2.0 * (iters[i] - ms_own[i]) + 4.0 * passes[i];
         in.hops_inner = 0.0;
+        in.outer_iters = 1;
         int st = h[i].status;
-        // the recursion residual decides; the recomputed one may sit above tol by rounding
-        if (st == LQCD_OK && !(in.true_resid <= 10.0 * prm->tol)) st = LQCD_ENOCONV;
+        if (st == LQCD_OK && !(in.true_resid <= prm->tol)) st = LQCD_ENOCONV;
         in.status = st;
         if (st != LQCD_OK && worst == LQCD_OK) worst = st;
     }

@@ -138,7 +138,8 @@ __device__ __forceinline__ void blas_block(const BlasArgs& a, int bx, int nbx, i
             for (int k = 0; k < NC; ++k) F::at(r, k) = F::at(r, k) - al * F::at(v, k);
             F::store(P(a.w, a.st_w), S, h, r);
         } else if (OP == BLAS_BI_XR) {
-            const cplx<R> al = cval<R>(ctl->balpha), om = cval<R>(ctl->omega);
+            // omega of this step (0 when ||t|| = 0: x += alpha p, r = s)
+            const cplx<R> al = cval<R>(ctl->balpha), om = cval<R>(ctl->omega_step);
             Vec x, p, sv, t, r0, r;
             F::load(P(a.x, a.st_x), S, h, x);
             F::load(P(a.y, a.st_y), S, h, p);
@@ -727,21 +728,26 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit)
+__global__ void k_ctl_init(Ctl* ctl, int nrhs, CtlInit in)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrhs) return;
-    Ctl c = {};
-    c.tol2 = tol * tol;
-    c.delta2 = delta * delta;
-    c.iter_limit = iter_limit;
-    ctl[i] = c;
+    ctl[i] = ctl_make(in);
+}
+
+hipError_t launch_ctl_init(Ctl* ctl, int nrhs, const CtlInit& in, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_init, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, in);
+    return hipGetLastError();
 }
 
 hipError_t launch_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_init, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, tol, delta, iter_limit);
-    return hipGetLastError();
+    CtlInit in{};
+    in.tol = tol;
+    in.delta = delta;
+    in.iter_limit = iter_limit;
+    return launch_ctl_init(ctl, nrhs, in, s);
 }
 
 __global__ void k_ctl_init_shifts(Ctl* ctl, int n, int base, ShiftList shifts)
@@ -761,18 +767,21 @@ hipError_t launch_ctl_init_shifts(Ctl* ctl, int n, int base, const ShiftList& sh
     return hipGetLastError();
 }
 
-__global__ void k_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask)
+__global__ void k_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, int no_fallback)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrhs || !((mask >> i) & 1u)) return;
     ctl[i].done = 0;
     ctl[i].status = 0;
     ctl[i].update = 0;
+    ctl[i].reset_p = 0;
+    ctl[i].outer_req = 0;
+    if (no_fallback) ctl[i].fallback_ok = 0;
 }
 
-hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s)
+hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s, bool no_fallback)
 {
-    hipLaunchKernelGGL(k_ctl_reopen, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, mask);
+    hipLaunchKernelGGL(k_ctl_reopen, dim3((nrhs + 63) / 64), dim3(64), 0, s, ctl, nrhs, mask, no_fallback ? 1 : 0);
     return hipGetLastError();
 }
 

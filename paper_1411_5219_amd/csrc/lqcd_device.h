@@ -238,6 +238,14 @@ struct SpinorIO<32> {
     }
 };
 
+// Scale of a site stored at FP16: its largest magnitude, or 0 (the site is
+// stored as zero) when that is below the smallest normal FP32.  Such sites
+// are rounding debris of cancellations that keep shrinking by kappa^2 per
+// operator application (a point source on a large lattice reaches FP32
+// denormals within a few applications), and the reciprocal of a denormal
+// overflows to infinity.
+__device__ __forceinline__ float fp16_site_scale(float m) { return m >= 1.17549435e-38f ? m : 0.f; }
+
 // FP16 storage, FP32 arithmetic: the 24 reals of a site are stored as
 // halves relative to one FP32 scale per site (the largest magnitude), so
 // the stored values lie in [-1, 1] and the relative precision is per site.
@@ -281,6 +289,7 @@ struct SpinorIO<16> {
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.s[a][c].x), fabsf(v.s[a][c].y)));
+        m = fp16_site_scale(m);
         const float inv = m > 0.f ? 1.0f / m : 0.f;
         const rsrc_t r = make_rsrc(base, 52 * S);
         const uint32_t o = static_cast<uint32_t>(site) * 16u;
@@ -382,6 +391,7 @@ struct ColourIO<16> {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) m = fmaxf(m, fmaxf(fabsf(v.c[k].x), fabsf(v.c[k].y)));
+        m = fp16_site_scale(m);
         const float inv = m > 0.f ? 1.0f / m : 0.f;
         uint32_t w[3];
 #pragma unroll

@@ -1,11 +1,13 @@
-// Kernel argument blocks, the device-resident solver control block, and the
-// host-side launchers of every kernel in the library.
+// Kernel argument blocks and the host-side launchers of every kernel in the
+// library (the solvers' control block is in solver_ctl.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <vector>
+
+#include "solver_ctl.h"
 
 namespace lqcd {
 
@@ -31,65 +33,12 @@ struct SpinCoef {
 //   RED_DOT_AUX : <aux, out>                      (re, im)
 enum Red { RED_NONE = 0, RED_NORM = 1, RED_NORM_DS = 2, RED_DOT_AUX = 3 };
 
-// What the last block does with the totals of a reduction.
-enum Fin {
-    FIN_STORE = 0,        // copy totals to Ctl::red[]
-    FIN_CG_ZZ = 1,        // zz = ||z||^2 (start of CGNR)
-    FIN_CG_ALPHA = 2,     // ww = ||w||^2, alpha = zz / ww
-    FIN_CG_RR = 3,        // rr = ||r||^2, iteration done: convergence / reliable-update test
-    FIN_CG_BETA = 4,      // zz' = ||z'||^2, beta = zz' / zz, zz = zz'
-    FIN_TRUE_RR = 5,      // true_rr = ||b - M x||^2 (FP64)
-    FIN_BI_ALPHA = 6,     // alpha = rho / <r0, v>
-    FIN_BI_OMEGA = 7,     // omega = <t, s> / ||t||^2
-    FIN_BI_RHO = 8,       // rr, rho_old = rho, rho = <r0, r>, convergence / breakdown test
-    FIN_BI_INIT = 9,      // rr and rho at the start of BiCGStab
-    FIN_RU_RR = 10,       // reliable update: rr = ||r||^2 in FP64 after the update
-    FIN_BB_E = 11,        // red[0] = ||b_e||^2 (first half of ||b||^2)
-    FIN_BB = 12,          // bb = red[0] + ||b_o||^2, thresh = tol^2 * bb
-    FIN_BB_FULL = 13,     // bb = ||b||^2 of a full-lattice field, thresh = tol^2 * bb
-    FIN_RR_INIT = 14,     // rr = rr_max = ||r||^2 (start of a reliable-update solve)
-    // multi-shift CG, run by the base system's finalize for every shift
-    FIN_MS_INIT = 15,     // rr = ||b||^2 = bb of every shift, thresh = tol^2 bb, zeta = 1
-    FIN_MS_INIT_KEEP = 16,// rr = ||r||^2, zeta = 1; bb and thresh already set
-    FIN_MS_ALPHA = 17,    // alpha = rr / <p, A p>; zeta_{k+1}, alpha_i of every shift
-    FIN_MS_BETA = 18,     // rr' = ||r||^2, beta, beta_i, zeta shift, per-shift convergence
-};
-
 // Predicates on the control block evaluated at the top of a kernel.
 enum Pred {
     PRED_ALWAYS = 0,      // ignore the control block
     PRED_ACTIVE = 1,      // skip when done
     PRED_UPDATE = 2,      // run only while a reliable update is pending (and not done)
     PRED_NO_UPDATE = 3,   // run only while no update is pending (and not done)
-};
-
-// Device-resident control block of one solve (one per right-hand side).
-// Kernels read their scalars from here, so no host round trip is needed
-// inside an iteration.
-struct Ctl {
-    double bb;        // ||b||^2 of the full system (stopping reference)
-    double thresh;    // tol^2 * bb
-    double zz, ww, rr, alpha, beta;
-    double rr_max;    // largest ||r||^2 since the last reliable update
-    double delta2;    // reliable-update trigger: rr < delta2 * rr_max
-    double tol2;      // tol^2
-    double true_rr;
-    double rho[2], rho_old[2], balpha[2], omega[2], r0v[2], ts[2], tt;
-    double red[6];    // FIN_STORE totals
-    // Multi-shift CG (one Ctl per shifted system, ms_n of them in a row; the
-    // base system, the smallest shift, at index ms_base): this system's shift
-    // minus the base shift and its residual ratios to the base residual,
-    // zeta_{k-1}, zeta_k and, inside an iteration, zeta_{k+1}; the base also
-    // keeps the base CG's alpha_{k-1} and beta_{k-1}.
-    double sigma, zeta_prev, zeta, zeta_next, alpha_prev, beta_prev;
-    int ms_index, ms_n, ms_base;
-    int iter;         // completed iterations
-    int done;         // 1 when converged (or failed): every kernel becomes a no-op
-    int status;       // 0, or a negative LQCD error code
-    int update;       // reliable update pending
-    int nupdates;     // reliable updates performed
-    int iter_limit;   // stop (done, status ENOCONV) at this many iterations
-    int pad[1];
 };
 
 struct RedArgs {
@@ -326,7 +275,10 @@ hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* 
 // Fill memory with zero bytes through a kernel (graph-capture safe).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
-// Initialise control blocks on the device.
+// Initialise control blocks on the device (every right-hand side from in;
+// the short form: a plain or reliable-update solve without stagnation
+// handling or outer steps).
+hipError_t launch_ctl_init(Ctl* ctl, int nrhs, const CtlInit& in, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, int nrhs, double tol, double delta, int iter_limit, hipStream_t s);
 // Multi-shift control blocks: ctl[i].sigma = shifts[i] - shifts[base],
 // ms_index = i, ms_n = n, ms_base = base (after launch_ctl_init).
@@ -336,7 +288,8 @@ struct ShiftList {
 };
 hipError_t launch_ctl_init_shifts(Ctl* ctl, int n, int base, const ShiftList& shifts, hipStream_t s);
 // Re-open the solves whose bit is set in mask (done = 0, status = 0) after a
-// failed true-residual check.
-hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s);
+// failed true-residual check or a fall back to FP32 storage (no_fallback:
+// the reopened solves may not fall back again).
+hipError_t launch_ctl_reopen(Ctl* ctl, int nrhs, unsigned mask, hipStream_t s, bool no_fallback = false);
 
 }  // namespace lqcd

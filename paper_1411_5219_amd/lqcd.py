@@ -51,7 +51,8 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32), ("eo", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("inner_recon", ctypes.c_int32), ("nrhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("stag_window", ctypes.c_int32), ("tol_inner", ctypes.c_double),
+                ("max_stagnations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Launch(ctypes.Structure):
@@ -65,7 +66,9 @@ KERNEL_DSLASH, KERNEL_BLAS, KERNEL_STAG, KERNEL_DSLASH_RHS = 0, 1, 2, 3
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("hops_outer", ctypes.c_double), ("hops_inner", ctypes.c_double)]
+                ("hops_outer", ctypes.c_double), ("hops_inner", ctypes.c_double),
+                ("outer_iters", ctypes.c_int32), ("stagnations", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -166,9 +169,10 @@ def op(kappa, mu=0.0, prec=64, recon=18) -> Op:
 
 
 def solve_params(tol=1e-10, maxiter=10000, eo=1, inner_prec=64, inner_recon=12, nrhs=1, use_graph=0,
-                 delta_reliable=0.1, check_every=8) -> SolveParams:
+                 delta_reliable=0.1, check_every=8, stag_window=0, tol_inner=0.0, max_stagnations=0) -> SolveParams:
     return SolveParams(float(tol), int(maxiter), int(eo), int(inner_prec), int(inner_recon), int(nrhs),
-                       int(use_graph), float(delta_reliable), int(check_every), 0)
+                       int(use_graph), float(delta_reliable), int(check_every), int(stag_window), float(tol_inner),
+                       int(max_stagnations), 0)
 
 
 def lqcd_last_error() -> str:

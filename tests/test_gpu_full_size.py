@@ -110,6 +110,48 @@ def test_force_48x12_sampled(mods, big):
         assert site_rel_err(got, ref, ncomp=9) <= 1e-12, mu
 
 
+@pytest.mark.parametrize("inner", [(64, 18), (32, 12), (16, 12)])
+def test_single_source_32x8_certified(mods, inner):
+    """32^3 x 8 (the smaller mixed-precision lattice), one Gaussian source:
+    plain FP64 and FP32 / FP16-storage inner solves with FP64 reliable
+    updates, each certified by the oracle's M, in bench.py's configuration."""
+    torch, fields, lqcd = mods
+    print(f"\n[case] 32^3x8 solve inner={inner}", flush=True)
+    U = gauge_field(L32, "exp", eps=0.4, seed=1002)
+    b = gaussian_spinor(L32, seed=2002)
+    lat = fields.Lattice(L32, THETA)
+    o = lqcd.op(KAPPA, MU)
+    p = lqcd.solve_params(tol=TOL, maxiter=100000, eo=1, inner_prec=inner[0], inner_recon=inner[1],
+                          delta_reliable=DELTA[inner[0]])
+    xd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    rc, info = lqcd.cg_solve(lat.g, o, lat.gauge(U), lat.spinor(b), xd, p, lat.workspace(o, p))
+    assert rc == lqcd.OK, info
+    tr = W.true_residual(U, lat.unpack(xd), b, L32, THETA, KAPPA, MU)
+    print(f"  iters={info[0]['iters']} updates={info[0]['reliable_updates']} true={tr:.3e}", flush=True)
+    assert tr <= TOL and abs(tr - info[0]["true_resid"]) <= 1e-3 * TOL
+
+
+@pytest.mark.parametrize("sc", [(0, 0), (2, 1)])
+def test_fp16_point_source_32x8_certified(mods, sc):
+    """FP16-storage inner solve on a unit point source at the origin (the
+    multi-right-hand-side workload's parameters, 32^3 x 8): the per-site
+    FP16 scale carries the source's dynamic range; certified by the oracle."""
+    torch, fields, lqcd = mods
+    print(f"\n[case] 32^3x8 fp16 point source spin/colour={sc}", flush=True)
+    U = gauge_field(L32, "exp", eps=0.4, seed=1003)
+    b = point_source(L32, *sc)
+    lat = fields.Lattice(L32, THETA)
+    o = lqcd.op(KAPPA, MU)
+    p = lqcd.solve_params(tol=TOL, maxiter=100000, eo=1, inner_prec=16, inner_recon=12, delta_reliable=DELTA[16])
+    xd = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    rc, info = lqcd.cg_solve(lat.g, o, lat.gauge(U), lat.spinor(b), xd, p, lat.workspace(o, p))
+    assert rc == lqcd.OK, info
+    tr = W.true_residual(U, lat.unpack(xd), b, L32, THETA, KAPPA, MU)
+    print(f"  iters={info[0]['iters']} updates={info[0]['reliable_updates']} stag={info[0]['stagnations']} "
+          f"fallbacks={info[0]['fallbacks']} true={tr:.3e}", flush=True)
+    assert tr <= TOL
+
+
 def test_multi_rhs_32x8_certified(mods):
     """16 right-hand sides (12 unit point sources at the origin, one per spin
     and colour, and 4 Gaussian) on 32^3 x 8, FP32/12 inner: each certified."""
@@ -210,5 +252,5 @@ def test_staggered_48x12_certified(mods, big):
         assert np.all(xi[~e_sites] == 0)
         r = b_e - (OS.normal_e(U, xi, L48, THETA, mass) + sh * xi)
         res = np.linalg.norm(r.ravel()) / bn
-        assert res <= 2 * TOL, (i, sh, res)  # the recursion stops at TOL; rounding drift is far below TOL
+        assert res <= TOL, (i, sh, res, infos[i])
         assert abs(res - infos[i]["true_resid"]) <= 1e-3 * TOL, (i, res, infos[i])

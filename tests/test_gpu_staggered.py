@@ -197,11 +197,12 @@ def test_multishift(mods, shifts, use_graph):
         full[:pb] = xd[i * pb:(i + 1) * pb]
         x = lat.unpack_colour(full)
         res = np.linalg.norm((b - A(x) - sh * x).ravel()) / np.linalg.norm(b.ravel())
-        assert res <= 2 * tol, (i, sh, res, infos[i])
+        assert res <= tol, (i, sh, res, infos[i])
         assert abs(res - infos[i]["true_resid"]) <= 1e-3 * tol + 1e-15
         rel = np.linalg.norm((x - xs_ref[i]).ravel()) / np.linalg.norm(xs_ref[i].ravel())
         assert rel < 1e-6, (i, rel)
-        assert abs(infos[i]["iters"] - out_ref[i][0]) <= 2, (infos[i], out_ref[i])
+        if infos[i]["restarts"] == 0:  # no refinement: the shared recursion alone
+            assert abs(infos[i]["iters"] - out_ref[i][0]) <= 2, (infos[i], out_ref[i])
 
 
 def test_launch_shapes_bitwise_and_autotune(mods):
