@@ -264,6 +264,22 @@ LQCD_API int dslash_apply(const lqcd_geom* geom, const lqcd_op* op, const void* 
 LQCD_API int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                     int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs, void* ws, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation and arguments as dslash_eo_apply, without ws.  LQCD_OP_SCHUR keeps
+ * its odd-parity temporary (nrhs parity fields at op->prec) in one 64 MiB
+ * array of device memory that the library holds per GPU until the process
+ * ends; a request larger than that fails with LQCD_EINVAL before any device
+ * work (FP64 fits nrhs * V/2 up to about 349,000 sites, e.g. 32^3 x 8 with two
+ * right-hand sides; FP32 fits 48^3 x 12 with one).  The first call on a
+ * device looks up that device's copy of the array.  Every call on one GPU
+ * uses the same array: calls that overlap in time on one GPU (other streams
+ * or threads) race and must be serialised by the caller.  No hipMalloc,
+ * hipFree or other allocation. */
+LQCD_API int dslash_eo_apply_noalloc(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in,
+                                     void* out, int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs,
+                                     void* stream);
+
 /* Solve M x = b (nrhs stacked full-lattice FP64 fields, U internal FP64 at
  * op->recon; op->prec must be 64) by CG on the normal equations (CGNR),
  * tracking r = b - M x; stops on the FP64 true residual.  x is overwritten

@@ -1421,7 +1421,7 @@ StagOp stag_bind(const Geom& g, const lqcd_stag_op* op, const void* U, const Sta
     return o;
 }
 
-// Argument checks of dslash_eo_apply.
+// Argument checks shared by dslash_eo_apply and its variant without allocation.
 int eo_apply_check(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                    int32_t out_parity, int32_t op_kind, int32_t nrhs, Geom* g)
 {
@@ -1459,6 +1459,44 @@ int eo_apply_run(const Geom& g, const lqcd_op* op, const void* U, const void* in
         return LQCD_OK;
     }
     LQCD_K(o.schur(in, out, tmp, dagger != 0, 1.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS));
+    return LQCD_OK;
+}
+
+// Device memory of dslash_eo_apply_noalloc: the odd-parity temporary of the
+// Schur complement lives here instead of in a caller workspace.  Each GPU the
+// library runs on holds its own copy for the life of the process; every call
+// on one GPU uses the same bytes (the temporary is fully rewritten by each
+// call, so nothing needs clearing; calls that overlap on one GPU race).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of this GPU's copy of scratch, looked up once per device
+// (the host-side name of the array is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(LQCD_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return set_error(LQCD_EUNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_error(LQCD_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                             hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return LQCD_OK;
 }
 
@@ -1783,6 +1821,25 @@ int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, con
         RedScratch rs;
         plan_reductions(ar, g, kMaxRhs, &rs);
         tmp = ar.take((size_t)(parity_bytes(g, op->prec) * nrhs));
+    }
+    return eo_apply_run(g, op, U, in, out, out_parity, op_kind, dagger, nrhs, tmp, stream);
+}
+
+int dslash_eo_apply_noalloc(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
+                            int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs, void* stream)
+{
+    Geom g;
+    int rc = eo_apply_check(geom, op, U, in, out, out_parity, op_kind, nrhs, &g);
+    if (rc) return rc;
+    void* tmp = nullptr;
+    if (op_kind == LQCD_OP_SCHUR) {
+        const size_t need = (size_t)(parity_bytes(g, op->prec) * nrhs);
+        if (need > kScratchBytes)
+            return set_error(LQCD_EINVAL,
+                             "dslash_eo_apply_noalloc: the odd-parity temporary needs %zu bytes, more than the "
+                             "library's %zu-byte device array (use dslash_eo_apply with a workspace)",
+                             need, kScratchBytes);
+        if ((rc = scratch_address(&tmp))) return rc;
     }
     return eo_apply_run(g, op, U, in, out, out_parity, op_kind, dagger, nrhs, tmp, stream);
 }

@@ -31,7 +31,8 @@ SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_device_memory", "lqcd_field_
            "lqcd_pack_spinor", "lqcd_unpack_spinor", "dslash_apply", "dslash_eo_apply", "cg_solve",
            "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
            "lqcd_unpack_colour", "stag_apply", "stag_eo_apply", "lqcd_workspace_bytes_stag", "stag_cg_solve",
-           "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs", "lqcd_gamma5", "tm_force"]
+           "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs", "lqcd_gamma5", "tm_force",
+           "dslash_eo_apply_noalloc"]
 
 
 class Geom(ctypes.Structure):
@@ -103,6 +104,7 @@ def _load():
         "lqcd_unpack_spinor": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "dslash_apply": ([G, O, vp, vp, vp, i32, i32, vp, vp], ctypes.c_int),
         "dslash_eo_apply": ([G, O, vp, vp, vp, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+        "dslash_eo_apply_noalloc": ([G, O, vp, vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
         "cg_solve": ([G, O, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "bicgstab_solve": ([G, O, vp, vp, vp, P, I, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "lqcd_workspace_bytes_batch": ([i32, G, O, P, szp], ctypes.c_int),
@@ -242,6 +244,13 @@ def dslash_eo_apply(g, o, U, inp, out, out_parity, op_kind=OP_HOP, dagger=0, nrh
     return _check(_lib.dslash_eo_apply(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out),
                                        int(out_parity), int(op_kind), int(dagger), int(nrhs), _ptr(ws),
                                        _stream(stream)))
+
+
+def dslash_eo_apply_noalloc(g, o, U, inp, out, out_parity, op_kind=OP_HOP, dagger=0, nrhs=1, stream=None):
+    """dslash_eo_apply without a workspace (the library's own device array holds the temporary)."""
+    return _check(_lib.dslash_eo_apply_noalloc(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out),
+                                               int(out_parity), int(op_kind), int(dagger), int(nrhs),
+                                               _stream(stream)))
 
 
 def _solve(fn, g, o, U, b, x, params, ws, stream):
