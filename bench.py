@@ -432,6 +432,99 @@ def stream_probe(stream, reps=10):
     return out
 
 
+def config_solves(stream, log, kappa, mu, tol, multi):
+    """Solves measured once after the timed steps (seconds from each call to
+    its return, median of 3 where cheap):
+      * 24^3 x 8, one Gaussian source: FP64 even-odd CGNR to 1e-10 and
+        BiCGStab on the same system, capped at 3000 iterations (its status and
+        the residual it reached are reported: at kappa = 0.16 the Schur
+        complement has eigenvalues on both sides of the imaginary axis and
+        BiCGStab stalls, as the oracle's does);
+      * 32^3 x 8, one Gaussian source: plain FP64 CGNR against FP32/12 and
+        FP16/12 inner solves with FP64 reliable updates;
+      * the 16 sources of the multi-RHS workload (32^3 x 8) solved one at a
+        time by plain FP64 CGNR, against the 16-RHS FP32-inner solve."""
+    import numpy as np
+    import torch
+
+    from lattice_inputs import gauge_field, gaussian_spinor
+    from paper_1411_5219_amd import fields, lqcd
+
+    out = {}
+    o = lqcd.op(kappa, mu)
+
+    def run(lat, U, b, p, x, ws, reps=3, fn=lqcd.cg_solve):
+        res = []
+        for _ in range(reps):
+            rc, info = fn(lat.g, o, U, b, x, p, ws, stream=stream)
+            res.append((rc, info))
+        secs = float(np.median([r[1][0]["seconds"] for r in res]))
+        rc, info = res[-1]
+        return rc, info[0], secs
+
+    log("config solves: 24^3x8 CGNR and BiCGStab")
+    L = (24, 24, 24, 8)
+    with torch.cuda.stream(stream):
+        lat = fields.Lattice(L, THETA)
+        U = lat.gauge(gauge_field(L, "exp", eps=0.4, seed=1001))
+        b = lat.spinor(gaussian_spinor(L, seed=2001))
+        x = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+        p = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64)
+        pbi = lqcd.solve_params(tol=tol, maxiter=3000, eo=1, inner_prec=64)
+        ws = lat.workspace(o, p)
+        wsb = lat.workspace(o, pbi)
+    rc, info, secs = run(lat, U, b, p, x, ws)
+    cg = {"status": rc, "seconds_median": secs, "iters": info["iters"], "true_resid": info["true_resid"]}
+    rc, info, secs = run(lat, U, b, pbi, x, wsb, reps=1, fn=lqcd.bicgstab_solve)
+    bi = {"status": lqcd.ERROR_NAMES.get(rc, rc), "seconds": secs, "iters": info["iters"],
+          "true_resid_reached": info["true_resid"], "maxiter": 3000}
+    out["config1_24x8"] = {"lattice": list(L), "cgnr_fp64": cg, "bicgstab_fp64": bi}
+    del lat, U, b, x, ws, wsb
+
+    log("config solves: 32^3x8 FP64 vs mixed")
+    L = (32, 32, 32, 8)
+    with torch.cuda.stream(stream):
+        lat = fields.Lattice(L, THETA)
+        U = lat.gauge(gauge_field(L, "exp", eps=0.4, seed=1002))
+        b = lat.spinor(gaussian_spinor(L, seed=2002))
+        x = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+    row = {"lattice": list(L)}
+    for name, prm in (("fp64", lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64)),
+                      ("mixed_fp32", lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12,
+                                                       delta_reliable=DELTA[32])),
+                      ("mixed_fp16", lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=16, inner_recon=12,
+                                                       delta_reliable=DELTA[16]))):
+        with torch.cuda.stream(stream):
+            ws = lat.workspace(o, prm)
+        rc, info, secs = run(lat, U, b, prm, x, ws)
+        if rc != 0:
+            raise RuntimeError(f"32^3x8 {name} solve failed: rc={rc} info={info}")
+        row[name] = {"seconds_median": secs, "iters": info["iters"], "reliable_updates": info["reliable_updates"],
+                     "true_resid": info["true_resid"]}
+    for name in ("mixed_fp32", "mixed_fp16"):
+        row[name]["speedup_vs_fp64"] = row["fp64"]["seconds_median"] / row[name]["seconds_median"]
+    out["config2a_32x8"] = row
+    del lat, U, b, x
+
+    log("config solves: 16 sources one at a time, plain FP64")
+    latm, Umd, b1 = multi
+    with torch.cuda.stream(stream):
+        x = latm.zeros(lqcd.FIELD_SPINOR_FULL, 64)
+        p = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64)
+        ws = latm.workspace(o, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for bk in b1:
+        rc, info = lqcd.cg_solve(latm.g, o, Umd, bk, x, p, ws, stream=stream)
+        if rc != 0:
+            raise RuntimeError(f"FP64 single-source solve failed: rc={rc}")
+        iters.append(info[0]["iters"])
+    torch.cuda.synchronize()
+    out["multi_rhs_fp64_single_solves"] = {"seconds": time.perf_counter() - t0, "iters_max": max(iters)}
+    return out
+
+
 SWEEP = [(16, 16, 16, 8), (24, 24, 24, 8), (32, 32, 32, 8), (48, 48, 48, 12), (64, 64, 64, 16)]
 
 
@@ -780,6 +873,8 @@ def main():
     stag = staggered(lat, U, np.asarray(b)[:, 0, :].copy(), stream, args.hops, log, oracle_budget=oracle_side)
     log("twisted-mass pseudo-fermion force")
     force = tm_force(lat, U, b, kappa, mu, stream, log, oracle_links=0 if args.no_cpu_baseline else 2000)
+    log("config solves")
+    extra = config_solves(stream, log, kappa, mu, tol, (latm, Umd, b1))
     log("stream probe")
     probe = stream_probe(stream)
     log("small uneven batch")
@@ -812,6 +907,8 @@ def main():
              "true_resid_max": max(i["true_resid"] for i in mr[-1]),
              "single_solves_seconds": t_single, "single_iters_max": max(single_iters)}
     multi["speedup_vs_single_solves"] = t_single / multi["seconds_median"]
+    multi["fp64_single_solves_seconds"] = extra["multi_rhs_fp64_single_solves"]["seconds"]
+    multi["speedup_vs_fp64_single_solves"] = multi["fp64_single_solves_seconds"] / multi["seconds_median"]
     un = rec["uneven"]
     uneven = {"lattices": [list(x[0]) for x in UNEVEN], "eps": [x[1] for x in UNEVEN],
               "kappa": [x[2] for x in UNEVEN], "rhs_per_lattice": 4, "inner": "FP32/12", "graph_replay": True,
@@ -851,6 +948,8 @@ def main():
         "multi_rhs": multi,
         "uneven_batch": uneven,
         "uneven_batch_small": small,
+        "config1_24x8": extra["config1_24x8"],
+        "config2a_32x8": extra["config2a_32x8"],
         "staggered": stag,
         "tm_force": force,
         "stream_probe": probe,

@@ -123,7 +123,16 @@ typedef struct {
  *                  workspace then holds FP32 inner fields).  0: 3; < 0: never.
  *                  Batched solves (cg_solve_batch) never fall back.
  *   use_graph      1: replay iterations from a captured HIP graph
- *   check_every    iterations enqueued between status read-backs (>= 1) */
+ *   check_every    iterations enqueued between status read-backs (>= 1)
+ *   persistent     cg_solve_batch only (other solvers: 0).  0: every step of
+ *                  an iteration is one batched launch (replayed from a graph
+ *                  with use_graph); 1: all iterations run in one persistent
+ *                  cooperative launch (grid barriers between the steps, no
+ *                  host round trip until every system is done; needs nrhs >= 2,
+ *                  inner FP32/12 and outer 18-real links, else
+ *                  LQCD_EUNSUPPORTED); 2: as 1 with the kernel's give-up word
+ *                  set at launch, so that its first grid barrier gives up and
+ *                  the call fails with LQCD_EHIP (the failure path, for tests) */
 typedef struct {
     double tol;
     int32_t maxiter;
@@ -137,7 +146,7 @@ typedef struct {
     int32_t stag_window;
     double tol_inner;
     int32_t max_stagnations;
-    int32_t reserved;          /* set to 0 */
+    int32_t persistent;
 } lqcd_solve_params;
 
 /* Filled by the solvers (one per right-hand side / system). */
@@ -155,7 +164,7 @@ typedef struct {
     int32_t outer_iters;       /* outer defect-correction steps (1 + steps ended by tol_inner) */
     int32_t stagnations;       /* stagnations of the inner solve detected */
     int32_t fallbacks;         /* 1: the FP16 inner solve continued at FP32 storage */
-    int32_t reserved;
+    int32_t persistent_launches; /* persistent launches of a batched solve (one per start) */
 } lqcd_solve_info;
 
 /* Launch configuration of a kernel family (LQCD_KERNEL_DSLASH: the Wilson
@@ -179,6 +188,17 @@ typedef struct {
  *   rhs_group Dslash only: 0, or G in 2..16: with several right-hand-side
  *           tiles, G tiles run back to back on each spatial block, so the
  *           links loaded for the first are re-read from L2 by the others.
+ *   ygroup  hop kernels with order = 1: 0 or 1 (none), or G in 2..64: G
+ *           neighbouring chunks of x-rows along y run right after t (then z),
+ *           so the rows a chunk's y-hops read beyond its edge come from L2;
+ *           the largest divisor of the chunk count not above G is used.
+ *   rhs_lanes Dslash with rhs_tile = 1 only: 0 or 1 (none), or 2, 4, 8, 16:
+ *           the right-hand sides of a site run in that many adjacent lanes of
+ *           one wavefront (the next power of two of nrhs, at most this), whose
+ *           link loads are one request: each link comes from memory once per
+ *           hop for all of them.  Needs order = 1 (blocks of whole x-rows of
+ *           sites, block = the site budget times the lanes); where no row
+ *           tile fits, the launch uses tiles in registers instead.
  * Process-wide; the defaults come from measurements on MI355X. */
 typedef struct {
     int32_t block;
@@ -186,6 +206,8 @@ typedef struct {
     int32_t order;
     int32_t rhs_tile;
     int32_t rhs_group;
+    int32_t ygroup;
+    int32_t rhs_lanes;
 } lqcd_launch;
 
 enum { LQCD_KERNEL_DSLASH = 0, LQCD_KERNEL_BLAS = 1, LQCD_KERNEL_STAG = 2, LQCD_KERNEL_DSLASH_RHS = 3 };
@@ -232,8 +254,9 @@ LQCD_API int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, cons
  * LQCD_KERNEL_DSLASH_RHS at op->prec kept, times the even-odd hop on nrhs
  * (2..16) stacked parity fields for every block request (128, 192, 256),
  * right-hand-side tile compiled (1, 2, 4; FP64 1, 2) and group (0, 2, 4, 8,
- * 16), and installs the fastest as LQCD_KERNEL_DSLASH_RHS.  best_us: mean
- * time of one launch over all nrhs.  Synchronises stream. */
+ * 16), and tile 1 across 2, 4, 8, 16 lanes (up to the next power of two of
+ * nrhs; with order >= 1), and installs the fastest as LQCD_KERNEL_DSLASH_RHS.
+ * best_us: mean time of one launch over all nrhs.  Synchronises stream. */
 LQCD_API int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in,
                                       void* out, int32_t nrhs, int32_t reps, void* stream, lqcd_launch* best,
                                       double* best_us);
@@ -300,7 +323,8 @@ LQCD_API int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void
  * the workspace), and with params->use_graph the iterations are replayed from
  * a captured HIP graph; each system stops on its own FP64 true residual.
  * info: nsys * nrhs entries, system-major.  ws: lqcd_workspace_bytes_batch
- * bytes of device memory. */
+ * bytes of device memory.  With params->persistent = 1 the whole iteration
+ * loop is one cooperative launch per start (see lqcd_solve_params). */
 LQCD_API int lqcd_workspace_bytes_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops,
                                         const lqcd_solve_params* params, size_t* bytes);
 LQCD_API int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,

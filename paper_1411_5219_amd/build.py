@@ -19,6 +19,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "liblqcd.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["dslash64.hip", "dslash32.hip", "dslash16.hip", "stag64.hip", "stag32.hip", "stag16.hip", "dslash.hip",
+           "persist.hip",
            "blas.hip", "force.hip", "abi.cpp"]
 ARCH = "gfx950"
 

@@ -420,6 +420,7 @@ int check_params(const lqcd_solve_params* p, int method)
         if (!(p->tol_inner >= 0.0 && p->tol_inner < 1.0))
             return set_error(LQCD_EINVAL, "tol_inner must be in [0, 1)");
     }
+    if (p->persistent < 0 || p->persistent > 2) return set_error(LQCD_EINVAL, "persistent %d not in {0, 1, 2}", p->persistent);
     return LQCD_OK;
 }
 
@@ -541,7 +542,7 @@ void fill_info(const Ctl* ctl, int nrhs, int method, bool eo, bool mixed, int re
         in.outer_iters = 1 + ctl[i].nouter;
         in.stagnations = ctl[i].nstag;
         in.fallbacks = fallbacks ? ((fallbacks >> i) & 1u) : 0;
-        in.reserved = 0;
+        in.persistent_launches = 0;
         int st = ctl[i].status;
         if (st == LQCD_OK && in.true_resid > prm->tol) st = LQCD_ENOCONV;
         if (st == LQCD_OK && !std::isfinite(in.true_resid)) st = LQCD_ENONFINITE;
@@ -839,6 +840,7 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
     if (rc) return rc;
     if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
     if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
+    if (prm->persistent) return set_error(LQCD_EUNSUPPORTED, "persistent launches are for cg_solve_batch");
     SolverPlan sp;
     plan_solver(g, opi, prm, method, ws, &sp);
     if (ws_bytes < sp.bytes)
@@ -958,11 +960,50 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
 
 constexpr size_t kStepTableBytes = 16 * 1024;  // per recorded step: arguments, offsets, finalizes of <= 16 systems
 constexpr int kMaxSteps = 32;
+static_assert(kMaxSteps <= kMaxPersistSteps, "the persistent program holds every recorded step");
+// Polls of a grid barrier's generation word before the persistent kernel
+// gives up (each poll sleeps ~50 ns and waits one atomic round trip: a few
+// seconds, against phases of well under a millisecond).
+constexpr int kPersistSpinLimit = 1 << 22;
+
+// The persistent kernel's routine for a recorded step of all systems, or
+// PR_NONE when the step is not one it runs (or a block shape it cannot).
+int persist_routine(const std::vector<std::vector<Step>>& steps, size_t k)
+{
+    const Step& st = steps[0][k];
+    for (const auto& sys : steps) {
+        const Step& q = sys[k];
+        if (q.kind == STEP_DSLASH && (q.d.block.x > (unsigned)kPersistThreads || q.d.a.lanes != 1)) return PR_NONE;
+        if (q.kind == STEP_BLAS && q.b.block.x != (unsigned)kPersistThreads) return PR_NONE;
+        if (q.kind == STEP_CONVERT && q.c.block.x != (unsigned)kPersistThreads) return PR_NONE;
+    }
+    if (st.kind == STEP_DSLASH) {
+        const DslashPlan& d = st.d;
+        if (d.kind != PLAN_WILSON || d.nr != 1 || d.lnt || (d.red != RED_NONE && d.red != RED_NORM)) return PR_NONE;
+        const bool norm = d.red == RED_NORM;
+        if (d.prec == 32 && d.recon == 12)
+            return d.dag ? (norm ? PR_HOP32_12_D1_NORM : PR_HOP32_12_D1_NONE)
+                         : (norm ? PR_HOP32_12_D0_NORM : PR_HOP32_12_D0_NONE);
+        if (d.prec == 64 && d.recon == 18 && !d.dag) return norm ? PR_HOP64_18_D0_NORM : PR_HOP64_18_D0_NONE;
+        return PR_NONE;
+    }
+    if (st.kind == STEP_BLAS) {
+        if (st.b.prec != 32 || st.b.a.kind != KIND_SPINOR) return PR_NONE;
+        if (st.b.op == BLAS_CG_XR) return PR_BLAS32_CG_XR;
+        if (st.b.op == BLAS_CG_P) return PR_BLAS32_CG_P;
+        return PR_NONE;
+    }
+    if (st.c.pd == 64 && st.c.ps == 32 && st.c.a.accumulate) return PR_CONV64_32_ACC;
+    if (st.c.pd == 32 && st.c.ps == 64 && !st.c.a.accumulate) return PR_CONV32_64;
+    return PR_NONE;
+}
 
 struct BatchLayout {
     Ctl* ctl = nullptr;               // nsys x kMaxRhs control blocks
     std::vector<SolverPlan> plans;
     char* tables = nullptr;           // kMaxSteps x kStepTableBytes
+    PProgram* prog = nullptr;         // the persistent kernel's program
+    unsigned* words = nullptr;        // its barrier words [0, 2) and flags [2, 4)
     size_t bytes = 0;
 };
 
@@ -971,6 +1012,8 @@ int plan_batch(int nsys, const Geom* g, const lqcd_op* ops, const lqcd_solve_par
     Arena ar{static_cast<char*>(ws), 0, 0};
     L->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs * nsys));
     L->tables = static_cast<char*>(ar.take(kStepTableBytes * kMaxSteps));
+    L->prog = static_cast<PProgram*>(ar.take(sizeof(PProgram)));
+    L->words = static_cast<unsigned*>(ar.take(4 * sizeof(unsigned)));
     L->plans.resize(nsys);
     for (int s = 0; s < nsys; ++s) {
         ar.off = align_up(ar.off, 256);
@@ -1060,6 +1103,38 @@ struct BatchProgram {
         return LQCD_OK;
     }
 
+    // The recorded iteration as the persistent kernel's program (host copy);
+    // false when some step is not one the kernel runs.
+    bool persistent_program(PProgram* P) const
+    {
+        const size_t nst = steps[0].size();
+        *P = PProgram{};
+        P->nsteps = (int)nst;
+        for (size_t k = 0; k < nst; ++k) {
+            const int r = persist_routine(steps, k);
+            if (r == PR_NONE) return false;
+            const Step& st = steps[0][k];
+            PStep& ps = P->step[k];
+            ps.routine = r;
+            ps.total = total[k];
+            unsigned gy = 1;
+            int nfin = 0;
+            for (int i = 0; i < nsys; ++i) {
+                const Step& q = steps[i][k];
+                const unsigned y = q.kind == STEP_DSLASH ? q.d.grid.y : q.kind == STEP_BLAS ? q.b.grid.y : q.c.grid.y;
+                gy = y > gy ? y : gy;
+            }
+            if (st.kind == STEP_DSLASH) nfin = st.d.nfin;
+            else if (st.kind == STEP_BLAS) nfin = st.b.nfin;
+            ps.gy = (int)gy;
+            ps.nfin = nfin;
+            ps.tab = tab[k];
+            ps.offs = reinterpret_cast<const int*>(offs[k]);
+            ps.fin = reinterpret_cast<const FinArgs*>(fin[k]);
+        }
+        return true;
+    }
+
     int run(hipStream_t s) const
     {
         const size_t nst = steps[0].size();
@@ -1127,14 +1202,52 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
     BatchProgram prog;
     if ((rc = prog.build(rec, L.tables, st))) return rc;
 
+    // One persistent cooperative launch per start: the program, the grid
+    // (the blocks the device keeps resident) and the barrier words.
+    int pgrid = 0, launches = 0;
+    PProgram P{};
+    if (prm->persistent) {
+        if (nrhs < 2 || !prog.persistent_program(&P))
+            return set_error(LQCD_EUNSUPPORTED, "the persistent batched solve runs the mixed CGNR with FP32/12 inner "
+                                                "and 18-real FP64 outer hops on nrhs >= 2 right-hand sides");
+        hipError_t e = persistent_grid(&pgrid);
+        if (e != hipSuccess) return set_error(LQCD_EUNSUPPORTED, "no cooperative launch on this device: %s",
+                                              hipGetErrorString(e));
+        P.nsys = nsys;
+        P.nrhs = nrhs;
+        P.ctl_stride = kMaxRhs;
+        P.ctl = L.ctl;
+        P.max_iter = prm->maxiter + 1;
+        P.spin_limit = kPersistSpinLimit;
+        P.bar = L.words;
+        P.flag = reinterpret_cast<int*>(L.words + 2);
+        LQCD_HIP(hipMemcpyAsync(L.prog, &P, sizeof(PProgram), hipMemcpyHostToDevice, st));
+        LQCD_HIP(hipStreamSynchronize(st));
+    }
+
     std::vector<Ctl> ctl;
     int restarts = 0;
     for (;;) {
         for (int s = 0; s < nsys; ++s)
             if ((rc = sys[s].start())) return rc;
-        rc = drive(st, L.ctl, nsys, kMaxRhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0,
-                   [&]() -> int { return prog.run(st); });
-        if (rc) return rc;
+        if (prm->persistent) {
+            // barrier words zero; the give-up word set for persistent = 2
+            const unsigned words[4] = {0u, 0u, prm->persistent == 2 ? 1u : 0u, 0u};
+            LQCD_HIP(hipMemcpyAsync(L.words, words, sizeof(words), hipMemcpyHostToDevice, st));
+            LQCD_HIP(hipStreamSynchronize(st));
+            LQCD_HIP(launch_batch_persistent(L.prog, pgrid, st));
+            ++launches;
+            unsigned back[4] = {0u, 0u, 0u, 0u};
+            LQCD_HIP(hipMemcpyAsync(back, L.words, sizeof(back), hipMemcpyDeviceToHost, st));
+            LQCD_HIP(hipStreamSynchronize(st));
+            if (back[3] != 0u)
+                return set_error(LQCD_EHIP, "persistent batched solve: a grid barrier gave up (%s)",
+                                 prm->persistent == 2 ? "give-up word set at launch" : "wait beyond the spin limit");
+        } else {
+            rc = drive(st, L.ctl, nsys, kMaxRhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0,
+                       [&]() -> int { return prog.run(st); });
+            if (rc) return rc;
+        }
         for (int s = 0; s < nsys; ++s)
             if ((rc = sys[s].finish())) return rc;
         if ((rc = read_ctls(st, L.ctl, nsys * kMaxRhs, ctl))) return rc;
@@ -1151,14 +1264,16 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
     for (int s = 0; s < nsys; ++s)
         fill_info(ctl.data() + s * kMaxRhs, nrhs, M_CG, prm->eo != 0, prm->inner_prec != 64, restarts, secs, prm,
                   info + s * nrhs, &worst);
+    for (int i = 0; i < nsys * nrhs; ++i) info[i].persistent_launches = launches;
     if (worst != LQCD_OK) set_error(worst, "batched solve did not converge for every system (status %d)", worst);
     return worst;
 }
 
 
 // Times the even-odd hop of one kernel family (launch(cfg) enqueues one hop
-// with launch shape cfg) in the 16 shapes {memory order, row tiles} x {XCD
-// remap off, on} x block {64, 128, 192, 256} with HIP events, keeps the
+// with launch shape cfg) in the 32 shapes {memory order, row tiles with y-chunk
+// groups of 1, 2, 3} x {XCD remap off, on} x block {64, 128, 192, 256} with
+// HIP events, keeps the
 // fastest in the process-wide table (the right-hand-side tile and group of
 // the family are kept: they only matter for several right-hand sides) and
 // reports it.  Synchronises the stream.
@@ -1172,10 +1287,12 @@ int autotune_hop(int kernel, int prec, int reps, hipStream_t s, lqcd_launch* bes
     float win_ms = 0.f;
     bool have = false;
     int result = LQCD_OK;
+    const int ygroups[3] = {1, 2, 3};
     for (int order = 0; order < 2 && !result; ++order)
+        for (int yi = 0; yi < (order ? 3 : 1) && !result; ++yi)
         for (int sw = 0; sw < 2 && !result; ++sw)
             for (int blk = 64; blk <= 256 && !result; blk += 64) {
-                const Launch cfg{blk, sw, order, 1, 0};
+                const Launch cfg{blk, sw, order, 1, 0, ygroups[yi]};
                 hipError_t e = hipSuccess;
                 for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch(cfg);
                 if (e == hipSuccess) e = hipEventRecord(e0, s);
@@ -1202,6 +1319,7 @@ int autotune_hop(int kernel, int prec, int reps, hipStream_t s, lqcd_launch* bes
         Launch& slot = g_launch[kernel][prec_slot(prec)];
         win.rhs_tile = slot.rhs_tile;
         win.rhs_group = slot.rhs_group;
+        win.rhs_lanes = slot.rhs_lanes;
         slot = win;
     }
     if (best) {
@@ -1210,6 +1328,8 @@ int autotune_hop(int kernel, int prec, int reps, hipStream_t s, lqcd_launch* bes
         best->order = win.order;
         best->rhs_tile = win.rhs_tile;
         best->rhs_group = win.rhs_group;
+        best->ygroup = win.ygroup;
+        best->rhs_lanes = win.rhs_lanes;
     }
     if (best_us) *best_us = 1e3 * win_ms / reps;
     return LQCD_OK;
@@ -1589,8 +1709,13 @@ int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg)
         return set_error(LQCD_EINVAL, "rhs_tile %d not in {1, 2, 4}", cfg->rhs_tile);
     if (cfg->rhs_group != 0 && (cfg->rhs_group < 2 || cfg->rhs_group > 16))
         return set_error(LQCD_EINVAL, "rhs_group %d not 0 or in [2, 16]", cfg->rhs_group);
+    if (cfg->ygroup < 0 || cfg->ygroup > 64) return set_error(LQCD_EINVAL, "ygroup %d not in [0, 64]", cfg->ygroup);
+    if (cfg->rhs_lanes != 0 && cfg->rhs_lanes != 1 && cfg->rhs_lanes != 2 && cfg->rhs_lanes != 4 &&
+        cfg->rhs_lanes != 8 && cfg->rhs_lanes != 16)
+        return set_error(LQCD_EINVAL, "rhs_lanes %d not in {0, 1, 2, 4, 8, 16}", cfg->rhs_lanes);
     std::lock_guard<std::mutex> lk(g_launch_mu);
-    g_launch[kernel][k] = Launch{cfg->block, cfg->swizzle, cfg->order, cfg->rhs_tile, cfg->rhs_group};
+    g_launch[kernel][k] = Launch{cfg->block, cfg->swizzle, cfg->order, cfg->rhs_tile, cfg->rhs_group,
+                                 cfg->ygroup < 1 ? 1 : cfg->ygroup, cfg->rhs_lanes < 1 ? 1 : cfg->rhs_lanes};
     return LQCD_OK;
 }
 
@@ -1608,6 +1733,8 @@ int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
     cfg->order = l.order;
     cfg->rhs_tile = l.rhs_tile;
     cfg->rhs_group = l.rhs_group;
+    cfg->ygroup = l.ygroup;
+    cfg->rhs_lanes = l.rhs_lanes;
     return LQCD_OK;
 }
 
@@ -1670,14 +1797,20 @@ int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const voi
     const int blocks[3] = {128, 192, 256};
     const int tiles[3] = {1, 2, 4};
     const int groups[5] = {0, 2, 4, 8, 16};
+    const int lanes[4] = {2, 4, 8, 16};
     for (int bi = 0; bi < 3 && !result; ++bi) {
-        for (int ti = 0; ti < 3 && !result; ++ti) {
-            if (dslash_rhs_tile(op->prec, tiles[ti], nrhs) != tiles[ti]) continue;  // not compiled / larger than nrhs
-            for (int gi = 0; gi < 5 && !result; ++gi) {
+        // tiles 1, 2, 4 in registers with groups, then tile 1 across 2..16 lanes
+        for (int ti = 0; ti < 3 + 4 && !result; ++ti) {
+            const bool across = ti >= 3;
+            const int tile = across ? 1 : tiles[ti];
+            if (!across && dslash_rhs_tile(op->prec, tile, nrhs) != tile) continue;  // not compiled / larger than nrhs
+            if (across && (shape.order < 1 || lanes[ti - 3] > 2 * nrhs)) continue;
+            for (int gi = 0; gi < (across ? 1 : 5) && !result; ++gi) {
                 Launch cfg = shape;
                 cfg.block = blocks[bi];
-                cfg.rhs_tile = tiles[ti];
-                cfg.rhs_group = groups[gi];
+                cfg.rhs_tile = tile;
+                cfg.rhs_group = across ? 0 : groups[gi];
+                cfg.rhs_lanes = across ? lanes[ti - 3] : 1;
                 o.dcfg = cfg;
                 auto hop = [&]() {
                     return o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
@@ -1716,6 +1849,8 @@ int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const voi
         best->order = win.order;
         best->rhs_tile = win.rhs_tile;
         best->rhs_group = win.rhs_group;
+        best->ygroup = win.ygroup;
+        best->rhs_lanes = win.rhs_lanes;
     }
     if (best_us) *best_us = 1e3 * win_ms / reps;
     return LQCD_OK;

@@ -57,16 +57,17 @@ struct SitePos {
     bool valid;       // false for work-items past the lattice (padding lanes)
 };
 
-// Output site of this work-item in spatial block bid of parity p (memory
-// order, t-fastest row tiles or z-slabs of row tiles; see DslashArgs).
-__device__ __forceinline__ SitePos site_pos(const DslashArgs& a, int bid, int p)
+// Output site of site work-item tid (threadIdx.x, or threadIdx.x >> lanes_log2
+// with right-hand sides across lanes) in spatial block bid of parity p
+// (memory order, t-fastest row tiles or z-slabs of row tiles; see DslashArgs).
+__device__ __forceinline__ SitePos site_pos(const DslashArgs& a, int bid, int p, int tid)
 {
     const int Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
     const int Lxh = a.g.Lxh;
     SitePos s;
     if (a.rows == 0) {
-        s.h = bid * a.bdim + threadIdx.x;
-        s.valid = (int)threadIdx.x < a.bdim && s.h < a.g.Vh;
+        s.h = bid * a.bdim + tid;
+        s.valid = tid < a.bdim && s.h < a.g.Vh;
         s.xh = s.h % Lxh;
         int r = s.h / Lxh;
         s.y = r % Ly;
@@ -75,7 +76,15 @@ __device__ __forceinline__ SitePos site_pos(const DslashArgs& a, int bid, int p)
         s.t = r / Lz;
     } else {
         int yc;
-        if (a.ztile <= 1) {
+        if (a.ztile <= 1 && a.ygroup > 1) {
+            const int G = a.ygroup;
+            s.t = bid % Lt;
+            int r = bid / Lt;
+            const int yi = r % G;
+            r /= G;
+            s.z = r % Lz;
+            yc = (r / Lz) * G + yi;
+        } else if (a.ztile <= 1) {
             s.t = bid % Lt;
             const int r = bid / Lt;
             s.z = r % Lz;
@@ -89,8 +98,8 @@ __device__ __forceinline__ SitePos site_pos(const DslashArgs& a, int bid, int p)
             s.z = (r % nzs) * T + zl;
             yc = r / nzs;
         }
-        const int yr = threadIdx.x / Lxh;
-        s.xh = threadIdx.x - yr * Lxh;
+        const int yr = tid / Lxh;
+        s.xh = tid - yr * Lxh;
         s.y = yc * a.rows + yr;
         s.valid = yr < a.rows && s.y < Ly;
         s.h = s.xh + Lxh * (s.y + Ly * (s.z + Lz * s.t));

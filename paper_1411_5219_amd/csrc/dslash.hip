@@ -57,13 +57,53 @@ hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashAr
     a = args;
     a.swizzle = cfg.swizzle;
     a.nrhs = nrhs;
+    // right-hand sides across lanes: L = the next power of two of nrhs, at
+    // most the request and 16; every field's lane offsets must fit 31 bits
+    int L = 1;
+    if (nrhs > 1 && cfg.rhs_lanes > 1 && cfg.rhs_tile == 1) {
+        while (L < nrhs && 2 * L <= cfg.rhs_lanes && L < 16) L *= 2;
+        int64_t st = a.st_in;
+        for (int64_t v : {a.st_out, a.st_site, a.st_add, a.st_aux}) st = v > st ? v : st;
+        if ((int64_t)L * st >= ((int64_t)1 << 31)) L = 1;
+    }
     int blk = cfg.block;
     unsigned nbh = (unsigned)((a.g.Vh + blk - 1) / blk);
     a.rows = 0;
     a.nyc = 0;
     a.ztile = 1;
+    a.ygroup = 1;
     const int Lxh = a.g.Lxh, Ly = a.g.L[1];
-    if (cfg.order >= 1 && Lxh <= 256) {
+    if (L > 1) {
+        // whole x-rows per block only (the block order and the partials
+        // count of the row tiles): the largest divisor R of Ly with R rows
+        // within the site budget cfg.block / L (at least one row) and
+        // R * Lxh * L lanes within the block limit, where 3/4 of the lanes
+        // are busy; otherwise tiles in registers (L = 1)
+        const int tmax = hop_lane_block_limit(prec);
+        const int sites = cfg.block / L;
+        int R = 0;
+        if (cfg.order >= 1)
+            for (int d = 1; d <= Ly; ++d)
+                if (Ly % d == 0 && (d * Lxh <= sites || d == 1) && d * Lxh * L <= tmax) R = d;
+        const int B = (R * Lxh * L + 63) / 64 * 64;
+        if (R > 0 && B <= tmax && 4 * R * Lxh * L >= 3 * B) {
+            a.rows = R;
+            a.nyc = (Ly + R - 1) / R;
+            for (int d = 1; d <= a.g.L[2] && d <= cfg.order; ++d)
+                if (a.g.L[2] % d == 0) a.ztile = d;
+            if (a.ztile == 1)
+                for (int d = 1; d <= a.nyc && d <= cfg.ygroup; ++d)
+                    if (a.nyc % d == 0) a.ygroup = d;
+            blk = R * Lxh;
+            nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
+        } else {
+            L = 1;
+        }
+    }
+    a.lanes = L;
+    a.lanes_log2 = 0;
+    while ((1 << a.lanes_log2) < L) ++a.lanes_log2;
+    if (L == 1 && cfg.order >= 1 && Lxh <= 256) {
         // R whole x-rows per block: the largest divisor of Ly with R*Lxh at
         // most the requested block size (at least one row); the block is
         // rounded up to whole wavefronts.
@@ -82,19 +122,27 @@ hipError_t plan_dslash(int prec, int recon, bool dagger, int red, const DslashAr
             // z-slabs: the largest divisor of Lz not above the requested depth
             for (int d = 1; d <= a.g.L[2] && d <= cfg.order; ++d)
                 if (a.g.L[2] % d == 0) a.ztile = d;
+            // y-chunk groups (t-fastest order only): the largest divisor of
+            // the chunk count not above the request
+            if (a.ztile == 1)
+                for (int d = 1; d <= a.nyc && d <= cfg.ygroup; ++d)
+                    if (a.nyc % d == 0) a.ygroup = d;
             blk = B;
             nbh = (unsigned)a.nyc * a.g.L[2] * a.g.L[3];
         }
     }
     a.bdim = blk;
-    p.nr = dslash_rhs_tile(prec, cfg.rhs_tile, nrhs);
-    a.ntiles = (nrhs + p.nr - 1) / p.nr;
-    // links are streamed past the caches when no other block of the launch reads them
-    p.lnt = p.nr == 1 && a.ntiles == 1;
+    p.nr = L > 1 ? 1 : dslash_rhs_tile(prec, cfg.rhs_tile, nrhs);
+    a.ntiles = (nrhs + p.nr * L - 1) / (p.nr * L);
+    // links are streamed past the caches when no other block of the launch
+    // reads them (one right-hand side per site); with right-hand sides across
+    // lanes the L lanes of a site share one cached load
+    p.lnt = p.nr == 1 && a.ntiles == 1 && L == 1;
     a.nsp = (int)nbh;
     // interleave right-hand-side tiles into the block order when there are several
-    a.rhs_group = (cfg.rhs_group > 1 && a.ntiles > 1) ? (cfg.rhs_group < a.ntiles ? cfg.rhs_group : a.ntiles) : 0;
-    p.block = dim3(blk);
+    a.rhs_group = (L == 1 && cfg.rhs_group > 1 && a.ntiles > 1) ? (cfg.rhs_group < a.ntiles ? cfg.rhs_group : a.ntiles)
+                                                                 : 0;
+    p.block = dim3(L > 1 ? (unsigned)((blk * L + 63) / 64 * 64) : (unsigned)blk);
     if (a.rhs_group > 0) {
         const unsigned groups = (unsigned)((a.ntiles + a.rhs_group - 1) / a.rhs_group);
         p.grid = dim3(nbh * (unsigned)a.rhs_group * groups * (a.full ? 2u : 1u), 1);
@@ -157,6 +205,7 @@ hipError_t launch_stag(int prec, int recon, int red, const DslashArgs& args, int
     Launch c = cfg;
     c.rhs_tile = 1;   // one right-hand side per work-item, tiles along grid.y
     c.rhs_group = 0;
+    c.rhs_lanes = 1;
     DslashPlan p;
     hipError_t e = plan_dslash(prec, recon, false, red, args, nrhs, c, &p);
     if (e != hipSuccess) return e;

@@ -93,14 +93,14 @@ struct HopBuf {
 // per-hop branch that would keep the loads of consecutive hops apart.
 template <int PREC, int RECON, int NR, bool LNT>
 __device__ __forceinline__ void hop_load(const char* const (&in)[NR], const bool (&act)[NR], const void* U,
-                                         int64_t S, const Nbr& n, HopBuf<PREC, NR>& b)
+                                         int64_t S, const Nbr& n, HopBuf<PREC, NR>& b, uint32_t xo, int64_t span)
 {
     if constexpr (LNT) LinkIO<PREC, RECON>::template load<>(U, S, n.lblk, n.lsite, b.L);
     else LinkIO<PREC, RECON>::template load<0>(U, S, n.lblk, n.lsite, b.L);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (NR > 1 && !act[r]) continue;
-        SpinorIO<PREC>::load(in[r], S, n.nb, b.p[r]);
+        SpinorIO<PREC>::load(in[r], S, n.nb, b.p[r], xo, span);
     }
 }
 
@@ -130,12 +130,12 @@ __device__ __forceinline__ void hop_apply(const HopBuf<PREC, NR>& b, const bool 
 template <int PREC, int RECON, int MU, bool FWD, int SIG, int NR, bool LNT>
 __device__ __forceinline__ void hop_fused(const char* const (&in)[NR], const bool (&act)[NR], const void* U,
                                           int64_t S, const Nbr& n, cplx<typename SpinorIO<PREC>::R> ph,
-                                          Spinor<typename SpinorIO<PREC>::R> (&acc)[NR])
+                                          Spinor<typename SpinorIO<PREC>::R> (&acc)[NR], uint32_t xo, int64_t span)
 {
     using R = typename SpinorIO<PREC>::R;
     if constexpr (NR == 1) {
         Spinor<R> p;
-        SpinorIO<PREC>::load(in[0], S, n.nb, p);
+        SpinorIO<PREC>::load(in[0], S, n.nb, p, xo, span);
         cplx<R> h[2][3];
         project<R, MU, SIG>(p, h);
         Link<R> L;
@@ -154,7 +154,7 @@ __device__ __forceinline__ void hop_fused(const char* const (&in)[NR], const boo
     for (int r = 0; r < NR; ++r) {
         if (NR > 1 && !act[r]) continue;
         Spinor<R> p;
-        SpinorIO<PREC>::load(in[r], S, n.nb, p);
+        SpinorIO<PREC>::load(in[r], S, n.nb, p, xo, span);
         cplx<R> h[2][3];
         project<R, MU, SIG>(p, h);
         cplx<R> w[2][3];
@@ -171,20 +171,11 @@ __device__ __forceinline__ void hop_fused(const char* const (&in)[NR], const boo
 // registers of operands per hop and already needs about 250 registers for
 // two waves per SIMD with one hop in flight; FP32 and FP16 keep three waves
 // with two hops in flight.
-#ifndef LQCD_WAVES_64
-#define LQCD_WAVES_64 2
-#endif
 #ifndef LQCD_DEPTH_64
 #define LQCD_DEPTH_64 1
 #endif
-#ifndef LQCD_WAVES_32
-#define LQCD_WAVES_32 3
-#endif
 #ifndef LQCD_DEPTH_32
 #define LQCD_DEPTH_32 2
-#endif
-#ifndef LQCD_WAVES_16
-#define LQCD_WAVES_16 3
 #endif
 #ifndef LQCD_DEPTH_16
 #define LQCD_DEPTH_16 2
@@ -194,10 +185,19 @@ __device__ __forceinline__ void hop_fused(const char* const (&in)[NR], const boo
 // with the register count the compiler chooses.
 template <int PREC, int NR>
 struct HopTune {
-    static constexpr int waves = NR > 1 ? 1 : PREC == 64 ? LQCD_WAVES_64 : PREC == 32 ? LQCD_WAVES_32 : LQCD_WAVES_16;
+    static constexpr int waves = NR > 1 ? 1 : hop_waves(PREC);
     static constexpr int depth = NR > 1 ? 1 : PREC == 64 ? LQCD_DEPTH_64 : PREC == 32 ? LQCD_DEPTH_32 : LQCD_DEPTH_16;
     static_assert(depth >= 1 && depth <= 4, "hop pipeline depth 1..4");
     static_assert(waves >= 1 && waves <= 8, "waves per SIMD 1..8");
+};
+
+// Largest block of a hop launch: 256 work-items, or for the tile-1 launches
+// with cached links (right-hand sides across lanes: up to 16 lanes per site
+// and whole x-rows per block) one block per compute unit at the kernel's
+// waves per SIMD: 8 waves in FP64, 12 in FP32 and FP16.
+template <int PREC, int NR, bool LNT>
+struct HopBlock {
+    static constexpr int max_threads = (NR == 1 && !LNT) ? hop_lane_block_limit(PREC) : 256;
 };
 
 template <int PREC, int RECON, int NR, bool LNT, int SF, int D>
@@ -210,12 +210,14 @@ struct HopPipe {
     const SiteGeo& g;
     const cplx<R> (&ph)[4];
     Spinor<R> (&acc)[NR];
+    uint32_t xo;      // per-lane byte offset of the input field (right-hand sides across lanes)
+    int64_t span;     // bytes the input buffer resource covers (0: one field)
     HopBuf<PREC, NR> buf[D > 1 ? D : 1];
 
     template <int K>
     __device__ __forceinline__ void load()
     {
-        hop_load<PREC, RECON, NR, LNT>(in, act, U, S, g.template get<K>(), buf[K % D]);
+        hop_load<PREC, RECON, NR, LNT>(in, act, U, S, g.template get<K>(), buf[K % D], xo, span);
     }
     template <int K>
     __device__ __forceinline__ void step()
@@ -230,7 +232,8 @@ struct HopPipe {
     {
         constexpr int MU = K >> 1;
         constexpr bool FWD = (K & 1) == 0;
-        hop_fused<PREC, RECON, MU, FWD, FWD ? SF : -SF, NR, LNT>(in, act, U, S, g.template get<K>(), ph[MU], acc);
+        hop_fused<PREC, RECON, MU, FWD, FWD ? SF : -SF, NR, LNT>(in, act, U, S, g.template get<K>(), ph[MU], acc,
+                                                                 xo, span);
     }
     __device__ __forceinline__ void run()
     {
@@ -300,6 +303,36 @@ __device__ void block_reduce_tile(double (&v)[NR][N], double* partials, int nb, 
     }
 }
 
+// Block part of the reductions with right-hand sides across L lanes (L a
+// power of two up to 64; L = 1 is one right-hand side per block): lanes with
+// the same right-hand side (equal lane index mod L) fold their N sums per
+// wavefront, the waves are combined in LDS in wave order, and work-item r < L
+// writes partials[rhs0 + r][bid][j].  Blocks of up to 16 waves.
+template <int N>
+__device__ void block_reduce_lanes(double (&v)[N], double* partials, int nb, int rhs0, int L, int nrhs, int bid)
+{
+    __shared__ double sm[N][16][16];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    for (int off = 32; off >= L; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] += __shfl_xor(v[j], off, 64);
+    if (lane < L)
+#pragma unroll
+        for (int j = 0; j < N; ++j) sm[j][wave][lane] = v[j];
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r < L && rhs0 + r < nrhs) {
+        double* out = partials + ((int64_t)(rhs0 + r) * nb + bid) * N;
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int w = 0; w < nwaves; ++w) s += sm[j][w][r];
+            out[j] = s;
+        }
+    }
+}
+
 // The work of one block: block bx of nbx along x and by along y of the
 // launch that serves this set of arguments.
 template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
@@ -307,22 +340,35 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
 {
     using R = typename SpinorIO<PREC>::R;
     constexpr int N = RedN<RED>::N;
+    // right-hand sides across lanes: the tile-1 launches with cached links
+    constexpr bool kLanes = NR == 1 && !LNT;
+    const int L = kLanes ? a.lanes : 1;
+    const int lr = kLanes ? (int)(threadIdx.x & (unsigned)(L - 1)) : 0;
+    const int tid = kLanes ? (int)(threadIdx.x >> a.lanes_log2) : (int)threadIdx.x;
     const BlockPos bp = block_pos(a, bx, nbx, by);
     const int p = bp.p, tile = bp.tile;
-    const int rhs0 = tile * NR;
+    const int rhs0 = tile * NR * L;  // first right-hand side of the block's tile (uniform)
     bool act[NR];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int rr = rhs0 + r;
+        const int rr = rhs0 + lr + r;
         act[r] = tile < a.ntiles && rr < a.nrhs && !pred_skip(a.pred, a.ctl ? a.ctl + rr : nullptr);
         any = any || act[r];
     }
-    if (!any) return;
-    const SitePos sp = site_pos(a, bp.bid, p);
+    if (L == 1 && !any) return;  // uniform over the block unless the right-hand sides are across lanes
+    const SitePos sp = site_pos(a, bp.bid, p, tid);
     const int h = sp.h;
     const int64_t poff = bp.poff, ioff = bp.ioff;
     const int64_t S = a.g.S;
+    // per-lane offsets and buffer spans of the fields (right-hand side rhs0 + lr)
+    const bool wide = L > 1;
+    const uint32_t xo_in = (uint32_t)(lr * a.st_in), xo_out = (uint32_t)(lr * a.st_out);
+    const uint32_t xo_site = (uint32_t)(lr * a.st_site), xo_add = (uint32_t)(lr * a.st_add);
+    const uint32_t xo_aux = (uint32_t)(lr * a.st_aux);
+    const int64_t sp_in = wide ? L * a.st_in : 0, sp_out = wide ? L * a.st_out : 0;
+    const int64_t sp_site = wide ? L * a.st_site : 0, sp_add = wide ? L * a.st_add : 0;
+    const int64_t sp_aux = wide ? L * a.st_aux : 0;
 
     double tot[NR][N];
 #pragma unroll
@@ -330,7 +376,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
 #pragma unroll
         for (int j = 0; j < N; ++j) tot[r][j] = 0.0;
 
-    if (sp.valid) {
+    if (sp.valid && any) {
         const char* in[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) in[r] = static_cast<const char*>(a.in) + (int64_t)(rhs0 + r) * a.st_in + ioff;
@@ -348,7 +394,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
                                {R(a.g.ph[2][0]), R(a.g.ph[2][1])},
                                {R(a.g.ph[3][0]), R(a.g.ph[3][1])}};
         const SiteGeo geo = site_geo(a.g, sp, p);
-        HopPipe<PREC, RECON, NR, LNT, SF, HopTune<PREC, NR>::depth> pipe{in, act, a.U, S, geo, ph, acc};
+        HopPipe<PREC, RECON, NR, LNT, SF, HopTune<PREC, NR>::depth> pipe{in, act, a.U, S, geo, ph, acc, xo_in, sp_in};
         pipe.run();
 
         // epilogue per right-hand side: out = add + a * site + c * acc
@@ -365,7 +411,8 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
             Spinor<R> st;
             if (a.site) {
                 const cplx<R> au = {R(a.a.up[0]), R(a.a.up[1])}, al = {R(a.a.lo[0]), R(a.a.lo[1])};
-                SpinorIO<PREC>::load(static_cast<const char*>(a.site) + rr * a.st_site + poff, S, h, st);
+                SpinorIO<PREC>::load(static_cast<const char*>(a.site) + rr * a.st_site + poff, S, h, st, xo_site,
+                                     sp_site);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -373,14 +420,15 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
             }
             if (a.add) {
                 Spinor<R> ad;
-                SpinorIO<PREC>::load(static_cast<const char*>(a.add) + rr * a.st_add + poff, S, h, ad);
+                SpinorIO<PREC>::load(static_cast<const char*>(a.add) + rr * a.st_add + poff, S, h, ad, xo_add, sp_add);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) o.s[s][c] = o.s[s][c] + ad.s[s][c];
             }
             if (a.out)
-                SpinorIO<PREC>::template store<LQCD_OUT_AUX>(static_cast<char*>(a.out) + rr * a.st_out + poff, S, h, o);
+                SpinorIO<PREC>::template store<LQCD_OUT_AUX>(static_cast<char*>(a.out) + rr * a.st_out + poff, S, h, o,
+                                                             xo_out, sp_out);
 
             if (RED == RED_NORM || RED == RED_NORM_DS) {
                 double n2 = 0.0;
@@ -405,7 +453,7 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
             }
             if (RED == RED_DOT_AUX) {  // <aux, out>
                 Spinor<R> ax;
-                SpinorIO<PREC>::load(static_cast<const char*>(a.aux) + rr * a.st_aux + poff, S, h, ax);
+                SpinorIO<PREC>::load(static_cast<const char*>(a.aux) + rr * a.st_aux + poff, S, h, ax, xo_aux, sp_aux);
                 double re = 0.0, im = 0.0;
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -421,12 +469,15 @@ __device__ __forceinline__ void dslash_block(const DslashArgs& a, int bx, int nb
         }
     }
 
-    if (RED != RED_NONE) block_reduce_tile<NR, N>(tot, a.r.partials, bp.nslots, rhs0, a.nrhs, bp.pslot);
+    if constexpr (RED != RED_NONE) {
+        if constexpr (kLanes) block_reduce_lanes<N>(tot[0], a.r.partials, bp.nslots, rhs0, L, a.nrhs, bp.pslot);
+        else block_reduce_tile<NR, N>(tot, a.r.partials, bp.nslots, rhs0, a.nrhs, bp.pslot);
+    }
 }
 
 template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopTune<PREC, NR>::waves)))
-k_dslash_eo(const DslashArgs a)
+__global__ void __launch_bounds__((HopBlock<PREC, NR, LNT>::max_threads))
+    __attribute__((amdgpu_waves_per_eu(HopTune<PREC, NR>::waves))) k_dslash_eo(const DslashArgs a)
 {
     dslash_block<PREC, RECON, DAG, RED, NR, LNT>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
@@ -435,8 +486,8 @@ k_dslash_eo(const DslashArgs a)
 // flattened grid belongs to system s with offs[s] <= x < offs[s + 1]; each
 // system's arguments come from the device table tab.
 template <int PREC, int RECON, bool DAG, int RED, int NR, bool LNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopTune<PREC, NR>::waves)))
-k_dslash_eo_batch(const DslashArgs* __restrict__ tab,
+__global__ void __launch_bounds__((HopBlock<PREC, NR, LNT>::max_threads))
+    __attribute__((amdgpu_waves_per_eu(HopTune<PREC, NR>::waves))) k_dslash_eo_batch(const DslashArgs* __restrict__ tab,
                                                         const int* __restrict__ offs, int nsys)
 {
     const int x = blockIdx.x;

@@ -182,14 +182,18 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, c
 template <int PREC>
 struct SpinorIO;
 
+// Every spinor access takes an optional per-lane byte offset xo (added to the
+// site offset; the field of another right-hand side) and the bytes span the
+// buffer resource covers from base (0: one field).
 template <>
 struct SpinorIO<64> {
     using R = double;
     static constexpr int kBytesPerSite = 192;
-    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v)
+    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v,
+                                                uint32_t xo = 0, int64_t span = 0)
     {
-        const rsrc_t r = make_rsrc(base, 192 * S);
-        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+        const rsrc_t r = make_rsrc(base, span > 0 ? span : 192 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u + xo;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const double2 d = bload<double2>(r, o, (uint32_t)(k * S * 16));
@@ -197,10 +201,11 @@ struct SpinorIO<64> {
         }
     }
     template <int AUX = 0>
-    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v)
+    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v,
+                                                 uint32_t xo = 0, int64_t span = 0)
     {
-        const rsrc_t r = make_rsrc(base, 192 * S);
-        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+        const rsrc_t r = make_rsrc(base, span > 0 ? span : 192 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u + xo;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const cplx<R> c = v.s[k / 3][k % 3];
@@ -213,10 +218,11 @@ template <>
 struct SpinorIO<32> {
     using R = float;
     static constexpr int kBytesPerSite = 96;
-    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v)
+    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v,
+                                                uint32_t xo = 0, int64_t span = 0)
     {
-        const rsrc_t r = make_rsrc(base, 96 * S);
-        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+        const rsrc_t r = make_rsrc(base, span > 0 ? span : 96 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u + xo;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const float4 d = bload<float4>(r, o, (uint32_t)(k * S * 16));
@@ -225,10 +231,11 @@ struct SpinorIO<32> {
         }
     }
     template <int AUX = 0>
-    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v)
+    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v,
+                                                 uint32_t xo = 0, int64_t span = 0)
     {
-        const rsrc_t r = make_rsrc(base, 96 * S);
-        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+        const rsrc_t r = make_rsrc(base, span > 0 ? span : 96 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u + xo;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const cplx<R> a = v.s[(2 * k) / 3][(2 * k) % 3];
@@ -265,11 +272,12 @@ struct SpinorIO<16> {
         __half_raw rb = __half(__float2half_rn(b));
         return (uint32_t)ra.x | ((uint32_t)rb.x << 16);
     }
-    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v)
+    __device__ static __forceinline__ void load(const void* base, int64_t S, int64_t site, Spinor<R>& v,
+                                                uint32_t xo = 0, int64_t span = 0)
     {
-        const rsrc_t r = make_rsrc(base, 52 * S);
-        const uint32_t o = static_cast<uint32_t>(site) * 16u;
-        const float scale = bload<float>(r, static_cast<uint32_t>(site) * 4u, (uint32_t)(3 * S * 16));
+        const rsrc_t r = make_rsrc(base, span > 0 ? span : 52 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u + xo;
+        const float scale = bload<float>(r, static_cast<uint32_t>(site) * 4u + xo, (uint32_t)(3 * S * 16));
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const uint4 d = bload<uint4>(r, o, (uint32_t)(k * S * 16));
@@ -282,7 +290,8 @@ struct SpinorIO<16> {
         }
     }
     template <int AUX = 0>
-    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v)
+    __device__ static __forceinline__ void store(void* base, int64_t S, int64_t site, const Spinor<R>& v,
+                                                 uint32_t xo = 0, int64_t span = 0)
     {
         float m = 0.f;
 #pragma unroll
@@ -291,8 +300,8 @@ struct SpinorIO<16> {
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.s[a][c].x), fabsf(v.s[a][c].y)));
         m = fp16_site_scale(m);
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        const rsrc_t r = make_rsrc(base, 52 * S);
-        const uint32_t o = static_cast<uint32_t>(site) * 16u;
+        const rsrc_t r = make_rsrc(base, span > 0 ? span : 52 * S);
+        const uint32_t o = static_cast<uint32_t>(site) * 16u + xo;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             uint32_t w[4];
@@ -303,7 +312,7 @@ struct SpinorIO<16> {
             }
             bstore<AUX>(r, o, (uint32_t)(k * S * 16), make_uint4(w[0], w[1], w[2], w[3]));
         }
-        bstore<AUX>(r, static_cast<uint32_t>(site) * 4u, (uint32_t)(3 * S * 16), m);
+        bstore<AUX>(r, static_cast<uint32_t>(site) * 4u + xo, (uint32_t)(3 * S * 16), m);
     }
 };
 

@@ -76,9 +76,14 @@ struct DslashArgs {
     // (T divides Lz): z-slabs of T planes, z fastest within a slab, then t,
     // then the slab, then the y-chunk; a spinor's z and t neighbours are then
     // at most T blocks away except on slab faces.
+    // ygroup = G > 1 (ztile 1; G divides nyc): G neighbouring y-chunks run
+    // after t and before z (t fastest, then the G chunks, then z, then the
+    // group), so the rows just outside a chunk, which its y-hops read, were
+    // loaded by blocks a few places before it on the same XCD.
     int rows;
     int nyc;                // y-chunks of R rows (rows > 0)
     int ztile;              // z-planes per slab (rows > 0; 1: t fastest)
+    int ygroup;             // y-chunks interleaved after t (rows > 0, ztile 1)
     int nrhs;               // right-hand sides (set by the launcher)
     // Right-hand-side tiles in the block order.  rhs_group = 0: tile index
     // is blockIdx.y.  rhs_group = G > 0: grid.y = 1 and the tiles are
@@ -88,9 +93,37 @@ struct DslashArgs {
     int rhs_group;
     int ntiles;             // right-hand-side tiles (ceil(nrhs / tile))
     int nsp;                // spatial blocks per parity (rhs_group > 0)
-    int bdim;               // work-items of a block that this argument set uses
+    // Right-hand sides across lanes: lanes = L > 1 (a power of two, tile 1):
+    // work-item t of a block serves site t >> lanes_log2 of the block and
+    // right-hand side (tile L + (t & (L - 1))), so the L right-hand sides of
+    // a site sit in adjacent lanes of one wave, their link loads are one
+    // coalesced request, and the link comes from memory once per hop for all
+    // of them.  The right-hand-side offset travels in the per-lane buffer
+    // offset (the buffer base stays uniform).
+    int lanes;
+    int lanes_log2;
+    int bdim;               // site work-items of a block that this argument set uses
     int gx;                 // planned grid.x (batched launches pad each system's range)
 };
+
+// Waves per SIMD the one-right-hand-side hop kernels are compiled for (their
+// register budget): FP64 holds about 250 registers at two waves, FP32 and FP16
+// keep three.  The tile-1 launches with right-hand sides across lanes take
+// blocks of up to one compute unit's worth of those waves.
+#ifndef LQCD_WAVES_64
+#define LQCD_WAVES_64 2
+#endif
+#ifndef LQCD_WAVES_32
+#define LQCD_WAVES_32 3
+#endif
+#ifndef LQCD_WAVES_16
+#define LQCD_WAVES_16 3
+#endif
+__host__ __device__ constexpr int hop_waves(int prec)
+{
+    return prec == 64 ? LQCD_WAVES_64 : prec == 32 ? LQCD_WAVES_32 : LQCD_WAVES_16;
+}
+__host__ __device__ constexpr int hop_lane_block_limit(int prec) { return 256 * hop_waves(prec); }
 
 // Launch configuration picked per kernel (autotuned).
 struct Launch {
@@ -99,6 +132,8 @@ struct Launch {
     int order = 0;     // 0: memory order, 1: t-fastest tiles of whole x-rows, k > 1: z-slabs of k planes (Dslash)
     int rhs_tile = 4;  // right-hand sides one Dslash work-item handles (links loaded once)
     int rhs_group = 4; // right-hand-side tiles interleaved per spatial block (0: grid.y)
+    int ygroup = 1;    // y-chunks interleaved after t in the row-tile order (1: none)
+    int rhs_lanes = 1; // right-hand sides across adjacent lanes of a site (1: none; 2..16, tile 1)
 };
 
 // Right-hand-side tile the Dslash uses for a request (clamped to the tiles
@@ -274,6 +309,58 @@ hipError_t launch_convert_gauge(int prec, int recon, const Geom& g, const void* 
 
 // Fill memory with zero bytes through a kernel (graph-capture safe).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// ---- persistent batched solver (persist.hip)
+// Block routines a phase of the persistent kernel runs: the steps of the
+// mixed-precision CGNR iteration with FP32/12 inner and FP64/18 outer hops on
+// several right-hand sides (tile 1, cached links).
+enum PRoutine {
+    PR_HOP32_12_D0_NONE = 0,
+    PR_HOP32_12_D0_NORM,
+    PR_HOP32_12_D1_NONE,
+    PR_HOP32_12_D1_NORM,
+    PR_HOP64_18_D0_NONE,
+    PR_HOP64_18_D0_NORM,
+    PR_BLAS32_CG_XR,
+    PR_BLAS32_CG_P,
+    PR_CONV64_32_ACC,
+    PR_CONV32_64,
+    PR_NONE = -1,
+};
+constexpr int kPersistThreads = 256;   // block size of the persistent kernel
+constexpr int kMaxPersistSteps = 32;
+
+// One step of the batched iteration as a phase: its routine, the blocks of
+// all systems (total along x, each system's range starting at offs[s]; gy
+// along y), the per-system argument table, and the finalize of its
+// reduction (nfin values, per-system FinArgs; 0: none).
+struct PStep {
+    int routine;
+    int total;
+    int gy;
+    int nfin;
+    const void* tab;
+    const int* offs;
+    const FinArgs* fin;
+};
+
+struct PProgram {
+    PStep step[kMaxPersistSteps];
+    int nsteps;
+    int nsys, nrhs;
+    int ctl_stride;        // control block of system s, right-hand side r: ctl[s * ctl_stride + r]
+    Ctl* ctl;
+    int max_iter;          // iterations this launch may run
+    int spin_limit;        // polls of a barrier's generation word before it gives up
+    unsigned* bar;         // [0] arrivals, [1] generation (zero before the launch)
+    int* flag;             // [0] give-up request from the host, [1] a barrier gave up (zero before the launch)
+};
+
+// Blocks the device keeps resident at once for the persistent kernel
+// (hipErrorNotSupported without cooperative launch).
+hipError_t persistent_grid(int* blocks);
+// Cooperative launch of the persistent kernel on prog_dev (device memory).
+hipError_t launch_batch_persistent(const PProgram* prog_dev, int blocks, hipStream_t s);
 
 // Initialise control blocks on the device (every right-hand side from in;
 // the short form: a plain or reliable-update solve without stagnation

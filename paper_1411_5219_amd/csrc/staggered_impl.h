@@ -71,7 +71,7 @@ __device__ __forceinline__ void stag_block(const DslashArgs& a, int bx, int nbx,
     const BlockPos bp = block_pos(a, bx, nbx, by);
     const int p = bp.p, rhs = bp.tile;
     if (rhs >= a.nrhs || pred_skip(a.pred, a.ctl ? a.ctl + rhs : nullptr)) return;
-    const SitePos sp = site_pos(a, bp.bid, p);
+    const SitePos sp = site_pos(a, bp.bid, p, (int)threadIdx.x);
     const int64_t S = a.g.S;
     double tot[N];
 #pragma unroll

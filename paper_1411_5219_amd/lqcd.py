@@ -53,12 +53,16 @@ class SolveParams(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("inner_recon", ctypes.c_int32), ("nrhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("stag_window", ctypes.c_int32), ("tol_inner", ctypes.c_double),
-                ("max_stagnations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_stagnations", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("swizzle", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("rhs_tile", ctypes.c_int32), ("rhs_group", ctypes.c_int32)]
+                ("rhs_tile", ctypes.c_int32), ("rhs_group", ctypes.c_int32), ("ygroup", ctypes.c_int32),
+                ("rhs_lanes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 KERNEL_DSLASH, KERNEL_BLAS, KERNEL_STAG, KERNEL_DSLASH_RHS = 0, 1, 2, 3
@@ -69,7 +73,7 @@ class SolveInfo(ctypes.Structure):
                 ("restarts", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("hops_outer", ctypes.c_double), ("hops_inner", ctypes.c_double),
                 ("outer_iters", ctypes.c_int32), ("stagnations", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("persistent_launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -171,10 +175,11 @@ def op(kappa, mu=0.0, prec=64, recon=18) -> Op:
 
 
 def solve_params(tol=1e-10, maxiter=10000, eo=1, inner_prec=64, inner_recon=12, nrhs=1, use_graph=0,
-                 delta_reliable=0.1, check_every=8, stag_window=0, tol_inner=0.0, max_stagnations=0) -> SolveParams:
+                 delta_reliable=0.1, check_every=8, stag_window=0, tol_inner=0.0, max_stagnations=0,
+                 persistent=0) -> SolveParams:
     return SolveParams(float(tol), int(maxiter), int(eo), int(inner_prec), int(inner_recon), int(nrhs),
                        int(use_graph), float(delta_reliable), int(check_every), int(stag_window), float(tol_inner),
-                       int(max_stagnations), 0)
+                       int(max_stagnations), int(persistent))
 
 
 def lqcd_last_error() -> str:
@@ -198,16 +203,15 @@ def lqcd_workspace_bytes(g, o, params=None) -> int:
     return n.value
 
 
-def lqcd_set_launch(kernel, prec, block, swizzle=1, order=0, rhs_tile=1, rhs_group=0):
-    cfg = Launch(int(block), int(swizzle), int(order), int(rhs_tile), int(rhs_group))
+def lqcd_set_launch(kernel, prec, block, swizzle=1, order=0, rhs_tile=1, rhs_group=0, ygroup=1, rhs_lanes=1):
+    cfg = Launch(int(block), int(swizzle), int(order), int(rhs_tile), int(rhs_group), int(ygroup), int(rhs_lanes))
     return _check(_lib.lqcd_set_launch(int(kernel), int(prec), ctypes.byref(cfg)))
 
 
 def lqcd_get_launch(kernel, prec):
     l = Launch()
     _check(_lib.lqcd_get_launch(int(kernel), int(prec), ctypes.byref(l)))
-    return {"block": l.block, "swizzle": l.swizzle, "order": l.order, "rhs_tile": l.rhs_tile,
-            "rhs_group": l.rhs_group}
+    return l.as_dict()
 
 
 def lqcd_autotune_dslash(g, o, U, inp, out, reps=10, stream=None):
@@ -216,8 +220,7 @@ def lqcd_autotune_dslash(g, o, U, inp, out, reps=10, stream=None):
     us = ctypes.c_double()
     _check(_lib.lqcd_autotune_dslash(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(reps),
                                      _stream(stream), ctypes.byref(best), ctypes.byref(us)))
-    return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
-             "rhs_group": best.rhs_group}, us.value)
+    return (best.as_dict(), us.value)
 
 
 def lqcd_pack_gauge(g, prec, recon, U_canonical, U_out, stream=None):
@@ -362,8 +365,7 @@ def lqcd_autotune_stag(g, o, U, inp, out, reps=10, stream=None):
     us = ctypes.c_double()
     _check(_lib.lqcd_autotune_stag(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(reps),
                                    _stream(stream), ctypes.byref(best), ctypes.byref(us)))
-    return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
-             "rhs_group": best.rhs_group}, us.value)
+    return (best.as_dict(), us.value)
 
 
 def lqcd_autotune_dslash_rhs(g, o, U, inp, out, nrhs, reps=10, stream=None):
@@ -373,8 +375,7 @@ def lqcd_autotune_dslash_rhs(g, o, U, inp, out, nrhs, reps=10, stream=None):
     us = ctypes.c_double()
     _check(_lib.lqcd_autotune_dslash_rhs(ctypes.byref(g), ctypes.byref(o), _ptr(U), _ptr(inp), _ptr(out), int(nrhs),
                                          int(reps), _stream(stream), ctypes.byref(best), ctypes.byref(us)))
-    return ({"block": best.block, "swizzle": best.swizzle, "order": best.order, "rhs_tile": best.rhs_tile,
-             "rhs_group": best.rhs_group}, us.value)
+    return (best.as_dict(), us.value)
 
 
 # ---------------------------------------------------------------------------

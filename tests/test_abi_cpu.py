@@ -119,7 +119,9 @@ def test_launch_validation():
                               (L.KERNEL_DSLASH, 64, dict(block=256, order=-1)),
                               (L.KERNEL_BLAS, 64, dict(block=256, order=2)),
                               (L.KERNEL_DSLASH, 64, dict(block=256, rhs_tile=3)),
-                              (L.KERNEL_DSLASH, 64, dict(block=256, rhs_group=17))]:
+                              (L.KERNEL_DSLASH, 64, dict(block=256, rhs_group=17)),
+                              (L.KERNEL_DSLASH, 64, dict(block=256, order=1, ygroup=65)),
+                              (L.KERNEL_DSLASH, 64, dict(block=256, order=1, ygroup=-1))]:
         with pytest.raises(L.LqcdError) as e:
             L.lqcd_set_launch(kernel, prec, **cfg)
         assert e.value.code == L.EINVAL, cfg
@@ -134,7 +136,11 @@ def test_launch_validation():
         assert L.lqcd_get_launch(L.KERNEL_DSLASH_RHS, 32) == saved_rhs  # separate slots
         L.lqcd_set_launch(L.KERNEL_DSLASH_RHS, 32, 128, 1, 1, 2, 8)
         assert L.lqcd_get_launch(L.KERNEL_DSLASH_RHS, 32) == dict(block=128, swizzle=1, order=1, rhs_tile=2,
-                                                                   rhs_group=8)
+                                                                   rhs_group=8, ygroup=1, rhs_lanes=1)
+        L.lqcd_set_launch(L.KERNEL_DSLASH, 32, 256, 1, 1, 1, 0, 3)
+        assert L.lqcd_get_launch(L.KERNEL_DSLASH, 32)["ygroup"] == 3
+        L.lqcd_set_launch(L.KERNEL_DSLASH, 32, 256, 1, 1, 1, 0, 0)   # 0 means none
+        assert L.lqcd_get_launch(L.KERNEL_DSLASH, 32)["ygroup"] == 1
     finally:
         L.lqcd_set_launch(L.KERNEL_DSLASH, 32, **saved)
         L.lqcd_set_launch(L.KERNEL_DSLASH_RHS, 32, **saved_rhs)

@@ -25,6 +25,8 @@ LATTICES = [
     ((4, 6, 8, 2), (0.0, 0.0, 0.0, math.pi)),
     ((6, 4, 6, 10), (0.3, -0.7, 1.1, math.pi + 0.2)),
     ((8, 8, 6, 6), (0.0, 0.0, 0.0, math.pi)),
+    # rows of 16 sites: row tiles of 4 or 6 x-rows, 2 or 3 y-chunks (y-chunk groups)
+    ((32, 12, 4, 6), (0.0, 0.4, 0.0, math.pi)),
 ]
 
 
@@ -32,7 +34,8 @@ LATTICES = [
 # and without the XCD remap, and row tiles in t-fastest order
 LAUNCHES = [dict(block=128, swizzle=1, order=0), dict(block=64, swizzle=0, order=0),
             dict(block=192, swizzle=1, order=1), dict(block=64, swizzle=0, order=1),
-            dict(block=256, swizzle=1, order=4), dict(block=128, swizzle=0, order=3)]
+            dict(block=256, swizzle=1, order=4), dict(block=128, swizzle=0, order=3),
+            dict(block=64, swizzle=1, order=1, ygroup=3), dict(block=128, swizzle=0, order=1, ygroup=2)]
 
 
 @pytest.fixture(scope="module")
@@ -121,24 +124,29 @@ def test_schur(mods, L4, theta, dagger, prec, recon):
 
 
 @pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
-@pytest.mark.parametrize("tile,group", [(1, 0), (2, 0), (4, 0), (1, 4), (2, 2), (4, 2), (1, 16)])
-def test_multi_rhs_equals_single(mods, prec, recon, tile, group):
+@pytest.mark.parametrize("tile,group,lanes", [(1, 0, 1), (2, 0, 1), (4, 0, 1), (1, 4, 1), (2, 2, 1), (4, 2, 1),
+                                              (1, 16, 1), (1, 0, 4), (1, 0, 8), (1, 0, 16)])
+def test_multi_rhs_equals_single(mods, prec, recon, tile, group, lanes):
     """A right-hand-side tile applies each link to several right-hand sides
     with the same per-RHS operations, so every RHS of a batch (5 RHS: full
     tiles plus a ragged one) equals its single-RHS application to rounding:
     different template instances may contract multiply-adds differently, which
-    can flip the last bit of an FP32 result or the rounding of a stored half."""
+    can flip the last bit of an FP32 result or the rounding of a stored half.
+    With the right-hand sides across lanes (4 lanes: two tiles, the second
+    ragged; 8 or 16 requested: one tile of 8 lanes, 3 of them idle) each lane
+    runs the one-right-hand-side code on its own field."""
     torch, fields, lqcd = mods
     L4, theta = (6, 4, 6, 10), (0.0, 0.0, 0.0, math.pi)
     U, psi = _setup(L4, theta, seed=3, kind="exp", nrhs=5)
-    print(f"\n[case] multi-rhs full M nrhs=5 prec={prec} tile={tile} group={group}", flush=True)
+    print(f"\n[case] multi-rhs full M nrhs=5 prec={prec} tile={tile} group={group} lanes={lanes}", flush=True)
     lat = fields.Lattice(L4, theta)
     o = lqcd.op(0.16, 0.005, prec, recon)
     Ud = lat.gauge(U, prec, recon)
     inp = lat.spinor(psi, prec)
     saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, prec)
     try:
-        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **dict(saved, rhs_tile=tile, rhs_group=group))
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec,
+                             **dict(saved, order=1, rhs_tile=tile, rhs_group=group, rhs_lanes=lanes))
         out = lat.empty(lqcd.FIELD_SPINOR_FULL, prec, nrhs=5)
         lqcd.dslash_apply(lat.g, o, Ud, inp, out, nrhs=5)
         got = lat.unpack(out, prec, nrhs=5)
@@ -148,6 +156,46 @@ def test_multi_rhs_equals_single(mods, prec, recon, tile, group):
             lqcd.dslash_apply(lat.g, o, Ud, one, o1)
             err = site_rel_err(got[k], lat.unpack(o1, prec))
             assert err <= {64: 1e-15, 32: 1e-6, 16: 2e-3}[prec], (k, err)
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **saved)
+
+
+@pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_rhs_lanes_16_against_oracle(mods, prec, recon, dagger):
+    """16 right-hand sides across 16 lanes (blocks of two x-rows of 8 sites:
+    256 lanes, every wave full) on the even-odd hop and the Schur complement,
+    each right-hand side against the oracle."""
+    torch, fields, lqcd = mods
+    L4, theta = (16, 8, 4, 6), (0.2, 0.0, 0.0, math.pi)
+    U, psi = _setup(L4, theta, seed=8, kind="exp", nrhs=16)
+    print(f"\n[case] 16 rhs across lanes prec={prec} dagger={dagger}", flush=True)
+    lat = fields.Lattice(L4, theta)
+    kappa, mu = 0.16, 0.005
+    o = lqcd.op(kappa, mu, prec, recon)
+    Ud = lat.gauge(U, prec, recon)
+    full = lat.spinor(psi, prec)
+    even = lat.parity_view(full, 0, prec, nrhs=16)
+    odd = lat.parity_view(full, 1, prec, nrhs=16)
+    pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, prec)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, prec)
+    try:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, 256, 1, 1, 1, 0, 1, 16)
+        hop = lat.zeros(lqcd.FIELD_SPINOR_PARITY, prec, nrhs=16)
+        lqcd.dslash_eo_apply(lat.g, o, Ud, odd, hop, 0, lqcd.OP_HOP, dagger, nrhs=16)
+        sch = lat.zeros(lqcd.FIELD_SPINOR_PARITY, prec, nrhs=16)
+        lqcd.dslash_eo_apply(lat.g, o, Ud, even, sch, 0, lqcd.OP_SCHUR, dagger, nrhs=16, ws=lat.workspace(o))
+        ev = W.parity(L4) == 0
+        for name, buf in (("hop", hop), ("schur", sch)):
+            f = lat.zeros(lqcd.FIELD_SPINOR_FULL, prec, nrhs=16)
+            f.view(16, 2, pb)[:, 0, :] = buf.view(16, pb)
+            got = lat.unpack(f, prec, nrhs=16)
+            for k in range(16):
+                if name == "hop":
+                    ref = W.hop_eo(U, psi[k], L4, theta, 0, dagger=bool(dagger))
+                else:
+                    ref = W.schur(U, W.mask(psi[k], L4, 0), L4, theta, kappa, mu, dagger=bool(dagger))
+                assert site_rel_err(got[k][ev], ref[ev]) <= TOL[prec], (name, k)
     finally:
         lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **saved)
 
@@ -178,6 +226,7 @@ def test_rhs_autotune(mods, prec, recon):
         assert {k: now[k] for k in ("swizzle", "order")} == {k: saved[k] for k in ("swizzle", "order")}
         assert now["block"] in (128, 192, 256)
         assert now["rhs_tile"] in ((1, 2) if prec == 64 else (1, 2, 4)) and now["rhs_group"] in (0, 2, 4, 8, 16)
+        assert now["rhs_lanes"] in (1, 2, 4, 8, 16)
         out = lat.zeros(lqcd.FIELD_SPINOR_FULL, prec, nrhs=6)
         pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, prec)
         even = lat.zeros(lqcd.FIELD_SPINOR_PARITY, prec, nrhs=6)
@@ -248,28 +297,29 @@ def test_autotune_configs_agree(mods):
     the FP64 results of all 16 configurations are bitwise identical; the
     autotuner installs one of them."""
     torch, fields, lqcd = mods
-    L4, theta = (8, 6, 10, 4), (0.0, 0.0, 0.0, math.pi)
-    U, psi = _setup(L4, theta, seed=9, kind="exp")
-    lat = fields.Lattice(L4, theta)
-    o = lqcd.op(0.16, 0.005)
-    Ud = lat.gauge(U)
-    src = lat.parity_view(lat.spinor(psi), 1)
     saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64)
     try:
-        outs = []
-        for order in (0, 1, 2, 5):
-            for sw in (0, 1):
-                for blk in (64, 128, 192, 256):
-                    lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, blk, sw, order)
-                    out = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
-                    lqcd.dslash_eo_apply(lat.g, o, Ud, src, out, 0)
-                    outs.append(out)
-        torch.cuda.synchronize()
-        for out in outs[1:]:
-            assert torch.equal(out, outs[0])
-        scratch = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
-        best, us = lqcd.lqcd_autotune_dslash(lat.g, o, Ud, src, scratch, reps=3)
-        assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64) == best and us > 0
+        for L4 in ((8, 6, 10, 4), (32, 12, 4, 6)):
+            theta = (0.0, 0.0, 0.0, math.pi)
+            U, psi = _setup(L4, theta, seed=9, kind="exp")
+            lat = fields.Lattice(L4, theta)
+            o = lqcd.op(0.16, 0.005)
+            Ud = lat.gauge(U)
+            src = lat.parity_view(lat.spinor(psi), 1)
+            outs = []
+            for order, yg in ((0, 1), (1, 1), (1, 2), (1, 3), (2, 1), (5, 1)):
+                for sw in (0, 1):
+                    for blk in (64, 128, 192, 256):
+                        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, blk, sw, order, ygroup=yg)
+                        out = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
+                        lqcd.dslash_eo_apply(lat.g, o, Ud, src, out, 0)
+                        outs.append(out)
+            torch.cuda.synchronize()
+            for out in outs[1:]:
+                assert torch.equal(out, outs[0]), L4
+            scratch = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
+            best, us = lqcd.lqcd_autotune_dslash(lat.g, o, Ud, src, scratch, reps=3)
+            assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64) == best and us > 0
     finally:
         lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, **saved)
 

@@ -324,3 +324,28 @@ def test_fp16_no_fall_back_when_disabled(mods):
     assert rc == 0, info
     assert info[0]["fallbacks"] == 0 and info[0]["stagnations"] >= 1
     assert true_res(U, x, b, L4, theta, kappa, mu) <= 1e-10
+
+
+@pytest.mark.parametrize("inner", [(64, 18), (32, 12), (16, 12)])
+def test_multi_rhs_lanes_solve(mods, inner):
+    """The 16-source solve (12 point + 4 Gaussian) with the right-hand sides
+    across 16 lanes in every hop (per-right-hand-side reductions inside the
+    blocks): each solution certified by the oracle's M."""
+    torch, fields, lqcd = mods
+    L4, theta, kappa, mu = (8, 8, 8, 4), (0, 0, 0, math.pi), 0.16, 0.005
+    U = gauge_field(L4, "exp", eps=0.4, seed=1003)
+    b = np.concatenate([np.stack([point_source(L4, s, c) for s in range(4) for c in range(3)]),
+                        gaussian_spinor(L4, seed=2003, nrhs=4)])
+    saved = {p: lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, p) for p in (64, 32, 16)}
+    print(f"\n[case] 16 rhs across lanes, inner={inner}", flush=True)
+    try:
+        for p in (64, 32, 16):
+            lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, p, 256, 1, 1, 1, 0, 1, 16)
+        rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "cg", nrhs=16, tol=1e-10, maxiter=20000,
+                                inner_prec=inner[0], inner_recon=inner[1])
+    finally:
+        for p, cfg in saved.items():
+            lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, p, **cfg)
+    assert rc == 0, info
+    for k in range(16):
+        assert true_res(U, x[k], b[k], L4, theta, kappa, mu) <= 1e-10, k
