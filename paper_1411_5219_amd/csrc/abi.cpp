@@ -1179,6 +1179,13 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
         if ((rc = validate_solve(&geoms[s], &ops[s], U[s], b[s], x[s], prm, info, M_CG, &g[s]))) return rc;
     if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
     if (prm->use_graph && !stream) return set_error(LQCD_EINVAL, "graph replay needs a non-default stream");
+    if (prm->persistent) {
+        bool ok = prm->nrhs >= 2 && prm->inner_prec == 32 && prm->inner_recon == 12 && prm->eo;
+        for (int s = 0; s < nsys; ++s) ok = ok && ops[s].recon == 18;
+        if (!ok)
+            return set_error(LQCD_EUNSUPPORTED, "the persistent batched solve runs the even-odd mixed CGNR with FP32/12 "
+                                                "inner and 18-real FP64 outer hops on nrhs >= 2 right-hand sides");
+    }
     BatchLayout L;
     plan_batch(nsys, g.data(), ops, prm, ws, &L);
     if (ws_bytes < L.bytes) return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);

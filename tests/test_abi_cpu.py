@@ -227,3 +227,20 @@ def test_rhs_launch_slot_validation():
         with pytest.raises(L.LqcdError) as e:
             L.lqcd_autotune_dslash_rhs(g, o, 48, inp, out, nrhs, reps=reps, stream=0)
         assert e.value.code == L.EINVAL, (nrhs, reps, inp, out)
+
+
+def test_persistent_parameter_checks():
+    """params.persistent: 0, 1 or 2 (anything else EINVAL before any device
+    work); the single-system solvers refuse it (EUNSUPPORTED): the persistent
+    launch runs batched solves."""
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((4, 4, 4, 4))
+    o = L.op(0.13, 0.1)
+    for bad in (-1, 3):
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_workspace_bytes(g, o, L.solve_params(persistent=bad))
+        assert e.value.code == L.EINVAL
+    for fn in (L.cg_solve, L.bicgstab_solve):
+        with pytest.raises(L.LqcdError) as e:
+            fn(g, o, 16, 32, 48, L.solve_params(persistent=1), 64, stream=0)
+        assert e.value.code == L.EUNSUPPORTED

@@ -349,3 +349,93 @@ def test_multi_rhs_lanes_solve(mods, inner):
     assert rc == 0, info
     for k in range(16):
         assert true_res(U, x[k], b[k], L4, theta, kappa, mu) <= 1e-10, k
+
+
+def _uneven_batch(mods, nrhs=2):
+    torch, fields, lqcd = mods
+    systems = [((6, 6, 6, 4), 0.3, 0.15), ((8, 8, 8, 4), 0.4, 0.16), ((4, 6, 8, 4), 0.5, 0.155)]
+    theta, mu = (0, 0, 0, math.pi), 0.005
+    geoms, ops, Us, bs, xs, host = [], [], [], [], [], []
+    for i, (L4, eps, kappa) in enumerate(systems):
+        U = gauge_field(L4, "exp", eps=eps, seed=1004 + 10 * i)
+        b = gaussian_spinor(L4, seed=2004 + 10 * i, nrhs=nrhs)
+        lat = fields.Lattice(L4, theta)
+        geoms.append(lat.g)
+        ops.append(lqcd.op(kappa, mu))
+        Us.append(lat.gauge(U))
+        bs.append(lat.spinor(b))
+        xs.append(lat.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=nrhs))
+        host.append((L4, kappa, U, b, lat))
+    return geoms, ops, Us, bs, xs, host, theta, mu
+
+
+def test_uneven_batch_persistent(mods):
+    """The uneven batch in one persistent cooperative launch per start (grid
+    barriers between the steps of the iteration): every solution certified
+    by the oracle's M and equal, within cond(M) tol, to the batched-launch
+    solve of the same systems."""
+    torch, fields, lqcd = mods
+    nrhs = 2
+    geoms, ops, Us, bs, xs, host, theta, mu = _uneven_batch(mods, nrhs)
+    p = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=1)
+    ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    print("\n[case] uneven batch, persistent launch", flush=True)
+    with torch.cuda.stream(s):
+        rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p, ws, stream=s)
+    torch.cuda.synchronize()
+    print(f"  rc={rc} iters={[i[0]['iters'] for i in infos]} launches={infos[0][0]['persistent_launches']}",
+          flush=True)
+    assert rc == 0, infos
+    assert infos[0][0]["persistent_launches"] >= 1
+    xs_p = [lat.unpack(xs[i], 64, nrhs=nrhs) for i, (_, _, _, _, lat) in enumerate(host)]
+    p0 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12)
+    xs0 = [lat.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=nrhs) for (_, _, _, _, lat) in host]
+    ws0 = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p0), dtype=torch.uint8, device="cuda")
+    rc0, infos0 = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs0, p0, ws0)
+    assert rc0 == 0
+    for i, (L4, kappa, U, b, lat) in enumerate(host):
+        x0 = lat.unpack(xs0[i], 64, nrhs=nrhs)
+        for k in range(nrhs):
+            tr = true_res(U, xs_p[i][k], b[k], L4, theta, kappa, mu)
+            assert tr <= 1e-10, (i, k, tr)
+            assert abs(tr - infos[i][k]["true_resid"]) < 1e-12
+            err = np.linalg.norm((xs_p[i][k] - x0[k]).ravel()) / np.linalg.norm(x0[k].ravel())
+            assert err < 1e-8, (i, k, err)
+
+
+def test_uneven_batch_persistent_give_up(mods):
+    """The persistent kernel's failure path, forced from the host: with the
+    give-up word set at launch (persistent = 2) every block leaves at its
+    first grid barrier, the kernel ends and the call fails with EHIP; the
+    device then runs the same batch normally."""
+    torch, fields, lqcd = mods
+    nrhs = 2
+    geoms, ops, Us, bs, xs, host, theta, mu = _uneven_batch(mods, nrhs)
+    p2 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=2)
+    ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p2), dtype=torch.uint8, device="cuda")
+    print("\n[case] uneven batch, persistent give-up", flush=True)
+    with pytest.raises(lqcd.LqcdError) as e:
+        lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p2, ws)
+    assert e.value.code == lqcd.EHIP and "gave up" in str(e.value)
+    torch.cuda.synchronize()
+    p1 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=1)
+    rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p1, ws)
+    assert rc == 0, infos
+    for i, (L4, kappa, U, b, lat) in enumerate(host):
+        x = lat.unpack(xs[i], 64, nrhs=nrhs)
+        for k in range(nrhs):
+            assert true_res(U, x[k], b[k], L4, theta, kappa, mu) <= 1e-10, (i, k)
+
+
+def test_persistent_refuses_unsupported(mods):
+    """The persistent launch runs the FP32/12-inner batched CGNR on several
+    right-hand sides; anything else is refused with EUNSUPPORTED."""
+    torch, fields, lqcd = mods
+    geoms, ops, Us, bs, xs, host, theta, mu = _uneven_batch(mods, 1)
+    for prm in (lqcd.solve_params(nrhs=1, inner_prec=32, inner_recon=12, persistent=1),
+                lqcd.solve_params(nrhs=1, inner_prec=64, persistent=1)):
+        ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, prm), dtype=torch.uint8, device="cuda")
+        with pytest.raises(lqcd.LqcdError) as e:
+            lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, prm, ws)
+        assert e.value.code == lqcd.EUNSUPPORTED
