@@ -274,7 +274,9 @@ LQCD_API int lqcd_unpack_spinor(const lqcd_geom* geom, int32_t prec, int32_t nrh
 
 /* out = M in (dagger = 0) or M^+ in (dagger = 1) on the full lattice; in and
  * out are nrhs stacked full-lattice fields at op->prec, U at op->prec /
- * op->recon.  in and out must not overlap. */
+ * op->recon.  in and out must not overlap.
+ * Paper: section 1 (the Dslash is the kernel the inversion repeats), section 3
+ * (twisted-mass Wilson fermions), section 6 (Dslash bandwidth). */
 LQCD_API int dslash_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                  int32_t dagger, int32_t nrhs, void* ws, void* stream);
 
@@ -283,7 +285,9 @@ LQCD_API int dslash_apply(const lqcd_geom* geom, const lqcd_op* op, const void* 
  *                       parity p = out_parity (in holds parity 1 - p);
  *   op = LQCD_OP_SCHUR: out = Mhat in (dagger: Mhat^+ in) on even sites;
  *                       out_parity must be 0; needs ws.
- * in and out must not overlap. */
+ * in and out must not overlap.
+ * Paper: section 1 and section 6 (the Dslash and its bandwidth; the hop is the
+ * kernel the section 6 measurement times), section 3 (twisted mass). */
 LQCD_API int dslash_eo_apply(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                     int32_t out_parity, int32_t op_kind, int32_t dagger, int32_t nrhs, void* ws, void* stream);
 
@@ -306,11 +310,14 @@ LQCD_API int dslash_eo_apply_noalloc(const lqcd_geom* geom, const lqcd_op* op, c
 /* Solve M x = b (nrhs stacked full-lattice FP64 fields, U internal FP64 at
  * op->recon; op->prec must be 64) by CG on the normal equations (CGNR),
  * tracking r = b - M x; stops on the FP64 true residual.  x is overwritten
- * (initial guess ignored).  info: nrhs entries. */
+ * (initial guess ignored).  info: nrhs entries.
+ * Paper: section 1 (inversion of the fermion matrix by Krylov methods such as
+ * CG dominates the cost), section 3 (standard inversion algorithms). */
 LQCD_API int cg_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
              const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
-/* Same contract, BiCGStab on M (or on Mhat with eo = 1). */
+/* Same contract, BiCGStab on M (or on Mhat with eo = 1).
+ * Paper: section 3 (standard inversion algorithms). */
 LQCD_API int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
                    const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes,
                    void* stream);
@@ -324,7 +331,9 @@ LQCD_API int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void
  * a captured HIP graph; each system stops on its own FP64 true residual.
  * info: nsys * nrhs entries, system-major.  ws: lqcd_workspace_bytes_batch
  * bytes of device memory.  With params->persistent = 1 the whole iteration
- * loop is one cooperative launch per start (see lqcd_solve_params). */
+ * loop is one cooperative launch per start (see lqcd_solve_params).
+ * Paper: section 1 (finite-temperature studies scan many parameter sets and
+ * volumes in parallel), section 4 (kernels specialised at run time). */
 LQCD_API int lqcd_workspace_bytes_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops,
                                         const lqcd_solve_params* params, size_t* bytes);
 LQCD_API int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,
@@ -388,7 +397,9 @@ LQCD_API int lqcd_autotune_stag(const lqcd_geom* geom, const lqcd_stag_op* op, c
  * stag_multishift_solve with nshift shifts (1..32). */
 LQCD_API int lqcd_workspace_bytes_stag(const lqcd_geom* geom, const lqcd_stag_op* op, int32_t nshift, size_t* bytes);
 
-/* Solve M x = b for one full-lattice FP64 colour field b (U FP64 at
+/* Staggered D_KS (paper: section 3, staggered fermions; section 6, the
+ * D_KS kernel's bandwidth).
+ * Solve M x = b for one full-lattice FP64 colour field b (U FP64 at
  * op->recon, op->prec = 64, op->mass > 0): CG on the even-site normal
  * operator N = m^2 - D_eo D_oe with right-hand side m b_e - D_eo b_o, then
  * x_o = (b_o - D_oe x_e) / m.  The CG residual r_e of N gives the full one,
@@ -405,10 +416,17 @@ LQCD_API int stag_cg_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const 
  * colour field, x nshift even-parity fields stacked (x_i at byte offset
  * i * lqcd_field_bytes(COLOUR_PARITY, 64)), shifts >= 0 in any order (1..32
  * of them).  One Krylov space, the smallest shift as the base system; each
- * system stops on its own when ||b - (N + shift_i) x_i|| <= tol ||b|| by the
- * recursion, and info[i].true_resid reports the FP64 true residual
- * recomputed at the end.  params: tol, maxiter, use_graph, check_every as
- * for cg_solve; eo = 1, inner_prec = 64, nrhs = 1. */
+ * system leaves the shared recursion when its recursive residual
+ * ||b - (N + shift_i) x_i|| falls to tol ||b||.  Its FP64 true residual is
+ * then recomputed; a shift that misses tol (rounding of the shifted
+ * recurrences) is refined by single-shift CG on N + shift_i started from x_i
+ * (up to 4 passes, counted in info[i].restarts, its iterations added to
+ * info[i].iters).  info[i].status is LQCD_OK only when info[i].true_resid <=
+ * tol, else LQCD_ENOCONV (the call returns the first failing status).
+ * params: tol, maxiter, use_graph, check_every as for cg_solve; eo = 1,
+ * inner_prec = 64, nrhs = 1.
+ * Paper: section 3 (RHMC for staggered fermions, whose rational
+ * approximation needs these shifted inversions). */
 LQCD_API int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, const void* b,
                                    void* x, const double* shifts, int32_t nshift, const lqcd_solve_params* params,
                                    lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);

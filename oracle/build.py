@@ -21,7 +21,7 @@ def build_oracle(force: bool = False, src: str = SRC, out: str = LIB) -> str:
     stale = (not os.path.exists(out)) or os.path.getmtime(out) < os.path.getmtime(src)
     if force or stale:
         tmp = out + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", src, "-o", tmp, "-lm"]
+        cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", src, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, out)
     return out

@@ -129,8 +129,8 @@ std::mutex g_launch_mu;
 // Defaults measured on MI355X at 24^3x8 .. 64^3x16: whole x-rows per block
 // in t-fastest order with the XCD remap for the Dslash; plain 256-wide
 // blocks for the site-local kernels.
-// Several right-hand sides: FP64 tiles of 2 in groups of 2, FP32 single
-// right-hand sides in groups of 4, FP16 tiles of 2 in groups of 4.
+// Several right-hand sides: FP64 and FP32 single right-hand sides per
+// work-item in groups of 4, FP16 tiles of 2 in groups of 4.
 // The staggered hop (colour vectors of 48 / 24 / 16 bytes) gains less from
 // neighbour reuse: memory order in FP64, row tiles of 192 in FP32 and FP16.
 Launch g_launch[4][3] = {{{256, 1, 1, 1, 4}, {256, 1, 1, 1, 4}, {256, 1, 1, 2, 4}},

@@ -11,6 +11,12 @@ kinetic energy is sum tr P^2 (= 1/2 sum_a p_a^2 for P = sum_a p_a T^a,
 T^a = lambda_a / 2), the force of an action S is F = sum_a (dS / dw^a) T^a
 for the link rotation U -> exp(i w T^a) U, and the equations of motion are
 dU/dt = i P U, dP/dt = -F, which conserve H = sum tr P^2 + S_g + S_f.
+
+Scope: this module exists to check the GPU force end to end (the leapfrog
+energy violation must fall as dt^2, which fails for any wrong term of the
+force).  The host-side gauge action, momenta and the Metropolis step are the
+minimum that check needs; a production HMC (integrator hierarchies,
+observables, gauge updates on the device) is not part of this library.
 """
 
 from __future__ import annotations
