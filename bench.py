@@ -213,7 +213,39 @@ def uneven_small(stream, mu, tol, delta):
            "graph_replay": True, "seconds_median": float(np.median(tb)), "iters_max": iters,
            "per_system_solves_seconds": float(np.median(ts))}
     out["speedup_vs_per_system"] = out["per_system_solves_seconds"] / out["seconds_median"]
+    per = persistent_batch(gs, os_, Us, bs, xs, 4, tol, delta, stream)
+    per["speedup_vs_per_system"] = out["per_system_solves_seconds"] / per["seconds_median"]
+    per["speedup_vs_batched_launches"] = out["seconds_median"] / per["seconds_median"]
+    out["persistent"] = per
     return out
+
+
+def persistent_batch(gs, os_, Us, bs, xs, nrhs, tol, delta, stream, reps=3):
+    """The uneven batch as one cooperative persistent launch (every CGNR
+    iteration of every system inside one kernel, grid barriers between the
+    phases): median wall time of `reps` solves, iterations, worst true
+    residual and the number of launches."""
+    import numpy as np
+    import torch
+
+    from paper_1411_5219_amd import lqcd
+
+    p = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=nrhs,
+                          delta_reliable=delta, persistent=1)
+    with torch.cuda.stream(stream):
+        ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(gs, os_, p), dtype=torch.uint8, device="cuda")
+    t, infos = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = lqcd.cg_solve_batch(gs, os_, Us, bs, xs, p, ws, stream=stream)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+        if rc != 0:
+            raise RuntimeError(f"persistent batch failed: rc={rc} {infos}")
+    return {"seconds_median": float(np.median(t)), "iters_max": [max(i["iters"] for i in inf) for inf in infos],
+            "true_resid_max": max(i["true_resid"] for inf in infos for i in inf),
+            "launches": max(i["persistent_launches"] for inf in infos for i in inf)}
 
 
 def recorded_traffic(workload, name="dslash_fp64", sources=None):
@@ -877,6 +909,8 @@ def main():
     extra = config_solves(stream, log, kappa, mu, tol, (latm, Umd, b1))
     log("stream probe")
     probe = stream_probe(stream)
+    log("persistent uneven batch")
+    persist = persistent_batch(gb, ob, Ub, bb, xb, 4, tol, DELTA[32], stream)
     log("small uneven batch")
     small = uneven_small(stream, mu, tol, DELTA[32])
 
@@ -917,6 +951,9 @@ def main():
               "true_resid_max": max(i["true_resid"] for inf in un[-1] for i in inf),
               "per_system_solves_seconds": t_per_system}
     uneven["speedup_vs_per_system"] = t_per_system / uneven["seconds_median"]
+    persist["speedup_vs_per_system"] = t_per_system / persist["seconds_median"]
+    persist["speedup_vs_batched_launches"] = uneven["seconds_median"] / persist["seconds_median"]
+    uneven["persistent"] = persist
 
     result = {
         "metric": METRIC,

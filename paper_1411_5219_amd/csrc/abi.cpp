@@ -961,9 +961,9 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
 constexpr size_t kStepTableBytes = 16 * 1024;  // per recorded step: arguments, offsets, finalizes of <= 16 systems
 constexpr int kMaxSteps = 32;
 static_assert(kMaxSteps <= kMaxPersistSteps, "the persistent program holds every recorded step");
-// Polls of a grid barrier's generation word before the persistent kernel
-// gives up (each poll sleeps ~50 ns and waits one atomic round trip: a few
-// seconds, against phases of well under a millisecond).
+// Polls of a grid barrier slot before the persistent kernel gives up (each
+// poll sleeps ~30 ns and waits one device-coherent load: a few seconds,
+// against phases of well under a millisecond).
 constexpr int kPersistSpinLimit = 1 << 22;
 
 // The persistent kernel's routine for a recorded step of all systems, or
@@ -1003,7 +1003,7 @@ struct BatchLayout {
     std::vector<SolverPlan> plans;
     char* tables = nullptr;           // kMaxSteps x kStepTableBytes
     PProgram* prog = nullptr;         // the persistent kernel's program
-    unsigned* words = nullptr;        // its barrier words [0, 2) and flags [2, 4)
+    unsigned* words = nullptr;        // its barrier slots [0, 2 kMaxPersistBlocks), then two flags
     size_t bytes = 0;
 };
 
@@ -1013,7 +1013,7 @@ int plan_batch(int nsys, const Geom* g, const lqcd_op* ops, const lqcd_solve_par
     L->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs * nsys));
     L->tables = static_cast<char*>(ar.take(kStepTableBytes * kMaxSteps));
     L->prog = static_cast<PProgram*>(ar.take(sizeof(PProgram)));
-    L->words = static_cast<unsigned*>(ar.take(4 * sizeof(unsigned)));
+    L->words = static_cast<unsigned*>(ar.take((2 * kMaxPersistBlocks + 2) * sizeof(unsigned)));
     L->plans.resize(nsys);
     for (int s = 0; s < nsys; ++s) {
         ar.off = align_up(ar.off, 256);
@@ -1128,6 +1128,12 @@ struct BatchProgram {
             else if (st.kind == STEP_BLAS) nfin = st.b.nfin;
             ps.gy = (int)gy;
             ps.nfin = nfin;
+            ps.pred = st.kind == STEP_DSLASH ? st.d.a.pred : st.kind == STEP_BLAS ? st.b.a.pred : st.c.a.pred;
+            for (int i = 1; i < nsys; ++i) {
+                const Step& q = steps[i][k];
+                const int pi = q.kind == STEP_DSLASH ? q.d.a.pred : q.kind == STEP_BLAS ? q.b.a.pred : q.c.a.pred;
+                if (pi != ps.pred) return false;
+            }
             ps.tab = tab[k];
             ps.offs = reinterpret_cast<const int*>(offs[k]);
             ps.fin = reinterpret_cast<const FinArgs*>(fin[k]);
@@ -1220,6 +1226,11 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
         hipError_t e = persistent_grid(&pgrid);
         if (e != hipSuccess) return set_error(LQCD_EUNSUPPORTED, "no cooperative launch on this device: %s",
                                               hipGetErrorString(e));
+        // no more blocks than the largest phase has (the others would only
+        // wait at every barrier) nor than the barrier has slots for
+        int64_t widest = 1;
+        for (int k = 0; k < P.nsteps; ++k) widest = std::max<int64_t>(widest, (int64_t)P.step[k].total * P.step[k].gy);
+        pgrid = (int)std::min<int64_t>({(int64_t)pgrid, widest, (int64_t)kMaxPersistBlocks});
         P.nsys = nsys;
         P.nrhs = nrhs;
         P.ctl_stride = kMaxRhs;
@@ -1227,7 +1238,7 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
         P.max_iter = prm->maxiter + 1;
         P.spin_limit = kPersistSpinLimit;
         P.bar = L.words;
-        P.flag = reinterpret_cast<int*>(L.words + 2);
+        P.flag = reinterpret_cast<int*>(L.words + 2 * kMaxPersistBlocks);
         LQCD_HIP(hipMemcpyAsync(L.prog, &P, sizeof(PProgram), hipMemcpyHostToDevice, st));
         LQCD_HIP(hipStreamSynchronize(st));
     }
@@ -1238,16 +1249,17 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
         for (int s = 0; s < nsys; ++s)
             if ((rc = sys[s].start())) return rc;
         if (prm->persistent) {
-            // barrier words zero; the give-up word set for persistent = 2
-            const unsigned words[4] = {0u, 0u, prm->persistent == 2 ? 1u : 0u, 0u};
-            LQCD_HIP(hipMemcpyAsync(L.words, words, sizeof(words), hipMemcpyHostToDevice, st));
+            // barrier slots zero; the give-up word set for persistent = 2
+            const unsigned flags[2] = {prm->persistent == 2 ? 1u : 0u, 0u};
+            LQCD_HIP(hipMemsetAsync(L.words, 0, 2 * kMaxPersistBlocks * sizeof(unsigned), st));
+            LQCD_HIP(hipMemcpyAsync(L.words + 2 * kMaxPersistBlocks, flags, sizeof(flags), hipMemcpyHostToDevice, st));
             LQCD_HIP(hipStreamSynchronize(st));
             LQCD_HIP(launch_batch_persistent(L.prog, pgrid, st));
             ++launches;
-            unsigned back[4] = {0u, 0u, 0u, 0u};
-            LQCD_HIP(hipMemcpyAsync(back, L.words, sizeof(back), hipMemcpyDeviceToHost, st));
+            unsigned back[2] = {0u, 0u};
+            LQCD_HIP(hipMemcpyAsync(back, L.words + 2 * kMaxPersistBlocks, sizeof(back), hipMemcpyDeviceToHost, st));
             LQCD_HIP(hipStreamSynchronize(st));
-            if (back[3] != 0u)
+            if (back[1] != 0u)
                 return set_error(LQCD_EHIP, "persistent batched solve: a grid barrier gave up (%s)",
                                  prm->persistent == 2 ? "give-up word set at launch" : "wait beyond the spin limit");
         } else {

@@ -339,6 +339,7 @@ struct PStep {
     int total;
     int gy;
     int nfin;
+    int pred;  // the step's predicate (the same for every system)
     const void* tab;
     const int* offs;
     const FinArgs* fin;
@@ -351,10 +352,13 @@ struct PProgram {
     int ctl_stride;        // control block of system s, right-hand side r: ctl[s * ctl_stride + r]
     Ctl* ctl;
     int max_iter;          // iterations this launch may run
-    int spin_limit;        // polls of a barrier's generation word before it gives up
-    unsigned* bar;         // [0] arrivals, [1] generation (zero before the launch)
+    int spin_limit;        // polls of a barrier word before the kernel gives up
+    unsigned* bar;         // arrival slots [kMaxPersistBlocks], then release slots (zero before the launch)
     int* flag;             // [0] give-up request from the host, [1] a barrier gave up (zero before the launch)
 };
+
+// Largest grid of the persistent kernel (one arrival and one release slot each).
+constexpr int kMaxPersistBlocks = 2048;
 
 // Blocks the device keeps resident at once for the persistent kernel
 // (hipErrorNotSupported without cooperative launch).

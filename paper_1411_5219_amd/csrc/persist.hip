@@ -9,16 +9,26 @@
 // standalone kernel would (dslash_block, blas_block, convert_block); a step
 // with a reduction is followed by its finalize as a phase of its own (one
 // block per system and right-hand side sums the partials in block order and
-// runs the solver's scalar step).  Phases are separated by a grid barrier:
-// an agent-scope release of each block's writes, one arrival counter and a
-// generation word, and an agent-scope acquire.  Every wait is bounded: a
-// barrier gives up after spin_limit polls, or at once when the host has set
-// the give-up word, and then records the failure so that every block leaves
-// at its next barrier; every wave always reaches the end of the kernel.
+// runs the solver's scalar step).  A step that would do nothing for every
+// system (the reliable-update steps of an iteration that requested no update)
+// is skipped with its barrier; every block takes that decision from the same
+// control blocks after the same barrier, so all agree.
+//
+// Phases are separated by a grid barrier without read-modify-write atomics:
+// block b stores the barrier's number into its arrival slot, block 0 waits
+// for every arrival and stores the number into every release slot, and each
+// block waits for its own.  Each block releases its writes with one
+// agent-scope fence before it arrives and acquires the others' with one after
+// it is released; the polls themselves are relaxed loads (an acquire load
+// would invalidate the caches on every poll, which made a barrier of 512
+// blocks cost tens of microseconds).  Every wait is bounded: it gives up
+// after spin_limit polls, or at once when the host has set the give-up word
+// or another block has given up, and records the failure so that every block
+// leaves at its next barrier; every wave always reaches the end of the kernel.
 //
 // The grid never exceeds the blocks the device keeps resident at once (the
 // launch is cooperative, so the runtime refuses a larger one), which the
-// barrier needs.
+// barrier needs, nor the largest phase (more blocks would only wait).
 #include "dslash_impl.h"
 #include "site_ops.h"
 
@@ -121,64 +131,82 @@ __device__ void run_finalize(const PStep& st, int nsys, int nrhs)
     }
 }
 
-// Grid barrier.  Returns false when this or another block gave up (then the
-// caller leaves the kernel).
-__device__ bool grid_sync(const PProgram& P)
+// Wait until *w holds `want` (relaxed polls).  Returns 0 when the host asked
+// to give up, another block gave up, or after spin_limit polls.
+__device__ int wait_word(const unsigned* w, unsigned want, const PProgram& P)
+{
+    for (int polls = 0; __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want; ++polls) {
+        if (polls >= P.spin_limit) return 0;
+        if ((polls & 63) == 63 && (__hip_atomic_load(&P.flag[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                                   __hip_atomic_load(&P.flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0))
+            return 0;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return 1;
+}
+
+// Grid barrier number `epoch` (1, 2, ... within a launch; the slots start at
+// zero).  A block's arrival slot holds epoch - 1 or epoch while block 0 waits
+// on it, its release slot likewise.  Returns false when this or another block
+// gave up (then the caller leaves the kernel).
+__device__ bool grid_sync(const PProgram& P, unsigned epoch)
 {
     __shared__ int ok;
+    unsigned* arrive = P.bar;
+    unsigned* release = P.bar + kMaxPersistBlocks;
     __syncthreads();
+    int good = 1;
     if (threadIdx.x == 0) {
-        unsigned* bar = P.bar;
-        int* flag = P.flag;
-        int good = 1;
-        // a give-up request or an earlier failure: leave without arriving
-        if (__hip_atomic_load(&flag[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-            __hip_atomic_load(&flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (__hip_atomic_load(&P.flag[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            __hip_atomic_load(&P.flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
             good = 0;
-        } else {
-            __threadfence();  // release this block's writes to the other XCDs
-            const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned arrived =
-                __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (arrived == gridDim.x) {
-                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                int polls = 0;
-                while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                    if (__hip_atomic_load(&flag[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                        __hip_atomic_load(&flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                        ++polls > P.spin_limit) {
-                        good = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this block's writes, before its arrival
+        __hip_atomic_store(arrive + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        int mine = 1;
+        for (int b = threadIdx.x; b < (int)gridDim.x && mine; b += blockDim.x) mine = wait_word(arrive + b, epoch, P);
+        mine = __syncthreads_and(mine);
+        if (mine) {
+            // every block's release happened before its arrival, which this
+            // block has seen: pass it on to the release slots
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+                __hip_atomic_store(release + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (!good) __hip_atomic_store(&flag[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__hip_atomic_load(&flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) good = 0;
-        __threadfence();  // acquire the other blocks' writes
+        if (threadIdx.x == 0) good = good && mine;
+    }
+    if (threadIdx.x == 0) {
+        if (good && blockIdx.x != 0) good = wait_word(release + blockIdx.x, epoch, P);
+        if (!good) __hip_atomic_store(&P.flag[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other blocks' writes
         ok = good;
     }
     __syncthreads();
     return ok != 0;
 }
 
-// Every system's every right-hand side done (read after a barrier that
-// follows the last write of a control block, so all blocks agree).
+// True when some system's right-hand side is not skipped by predicate
+// `pred` (the test every block routine and finalize applies per control
+// block); read after a barrier, so all blocks agree.
+__device__ bool any_active(const PProgram& P, int pred)
+{
+    const int n = P.nsys * P.nrhs;
+    int act = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        act |= !pred_skip(pred, P.ctl + (i / P.nrhs) * P.ctl_stride + i % P.nrhs);
+    return __syncthreads_or(act) != 0;
+}
+
+// Every system's every right-hand side done.
 __device__ bool all_done(const PProgram& P)
 {
-    __shared__ int done;
-    if (threadIdx.x == 0) {
-        int d = 1;
-        for (int s = 0; s < P.nsys && d; ++s)
-            for (int r = 0; r < P.nrhs && d; ++r)
-                d = __hip_atomic_load(&P.ctl[s * P.ctl_stride + r].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        done = d;
-    }
-    __syncthreads();
-    return done != 0;
+    const int n = P.nsys * P.nrhs;
+    int open = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        open |= __hip_atomic_load(&P.ctl[(i / P.nrhs) * P.ctl_stride + i % P.nrhs].done, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == 0;
+    return __syncthreads_or(open) == 0;
 }
 
 // Blocks of kPersistThreads; the register budget of the FP64 hop (two
@@ -187,14 +215,24 @@ __global__ void __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_p
 k_batch_persistent(const PProgram* __restrict__ prog)
 {
     const PProgram& P = *prog;
+    unsigned epoch = 0;
     for (int it = 0; it < P.max_iter; ++it) {
+        // the reliable-update steps run only when some system requested an
+        // update; requests come from a finalize, so a "no" holds until the
+        // next finalize phase
+        bool no_update = false;
         for (int k = 0; k < P.nsteps; ++k) {
             const PStep& st = P.step[k];
+            if (st.pred == PRED_UPDATE) {
+                if (!no_update) no_update = !any_active(P, PRED_UPDATE);
+                if (no_update) continue;
+            }
             run_step(st, P.nsys);
-            if (!grid_sync(P)) return;
+            if (!grid_sync(P, ++epoch)) return;
             if (st.nfin) {
                 run_finalize(st, P.nsys, P.nrhs);
-                if (!grid_sync(P)) return;
+                if (!grid_sync(P, ++epoch)) return;
+                no_update = false;
             }
         }
         if (all_done(P)) return;

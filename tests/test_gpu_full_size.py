@@ -174,12 +174,14 @@ def test_multi_rhs_32x8_certified(mods):
         assert tr <= TOL, (k, tr)
 
 
-def test_uneven_batch_full_size_certified(mods):
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_uneven_batch_full_size_certified(mods, persistent):
     """The benchmark's uneven batch: 16^3, 20^3, 24^3 and 32^3 x 8 with their
-    own eps and kappa, 4 Gaussian sources each, one batched CGNR replayed from
-    a HIP graph; all 16 solutions certified."""
+    own eps and kappa, 4 Gaussian sources each, one batched CGNR (replayed
+    from a HIP graph, or one cooperative persistent launch); all 16 solutions
+    certified."""
     torch, fields, lqcd = mods
-    print("\n[case] uneven batch full size", flush=True)
+    print(f"\n[case] uneven batch full size persistent={persistent}", flush=True)
     systems = [((16, 16, 16, 8), 0.3, 0.15), ((20, 20, 20, 8), 0.4, 0.16), ((24, 24, 24, 8), 0.5, 0.155),
                ((32, 32, 32, 8), 0.4, 0.16)]
     nrhs = 4
@@ -196,13 +198,17 @@ def test_uneven_batch_full_size_certified(mods):
         xs.append(lat.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=nrhs))
         host.append((L4, kappa, U, b, lat))
     p = lqcd.solve_params(tol=TOL, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=nrhs, use_graph=1,
-                          delta_reliable=DELTA[32])
+                          delta_reliable=DELTA[32], persistent=persistent)
     ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
         rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p, ws, stream=s)
     torch.cuda.synchronize()
     assert rc == lqcd.OK, infos
+    if persistent:
+        launches = [i["persistent_launches"] for inf in infos for i in inf]
+        print(f"  launches={max(launches)} iters={[max(i['iters'] for i in inf) for inf in infos]}", flush=True)
+        assert min(launches) >= 1
     for i, (L4, kappa, U, b, lat) in enumerate(host):
         x = lat.unpack(xs[i], 64, nrhs=nrhs)
         for k in range(nrhs):
