@@ -248,6 +248,44 @@ def persistent_batch(gs, os_, Us, bs, xs, nrhs, tol, delta, stream, reps=3):
             "launches": max(i["persistent_launches"] for inf in infos for i in inf)}
 
 
+def profile_multi_rhs(stream, dev, eps=0.4, kappa=0.16, mu=0.005, tol=1e-10):
+    """The 16-source solve on 32^3x8 (FP32/12 inner) twice, then a 1 GiB copy
+    that calibrates the byte counters: the run the in-solve counter summary
+    of the several-right-hand-side hop is taken on."""
+    import numpy as np
+    import torch
+
+    from lattice_inputs import gauge_field, gaussian_spinor, point_source
+    from paper_1411_5219_amd import fields, lqcd
+
+    Um = gauge_field(MULTI_L, "exp", eps=eps, seed=1003)
+    bm = np.concatenate([np.stack([point_source(MULTI_L, s_, c_) for s_ in range(4) for c_ in range(3)]),
+                         gaussian_spinor(MULTI_L, seed=2003, nrhs=4)])
+    pm = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=32, inner_recon=12, nrhs=bm.shape[0],
+                           delta_reliable=DELTA[32])
+    o64 = lqcd.op(kappa, mu)
+    with torch.cuda.stream(stream):
+        latm = fields.Lattice(MULTI_L, THETA, device=dev)
+        Umd = latm.gauge(Um)
+        bmd = latm.spinor(bm)
+        xmd = latm.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=bm.shape[0])
+        wsm = latm.workspace(o64, pm)
+    infos = None
+    for _ in range(2):
+        rc, infos = lqcd.cg_solve(latm.g, o64, Umd, bmd, xmd, pm, wsm, stream=stream)
+        if rc != 0:
+            raise RuntimeError(f"16-source solve failed: {infos}")
+    with torch.cuda.stream(stream):
+        a = torch.empty((1 << 30) // 4, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_multi_rhs": True, "lattice": list(MULTI_L), "nrhs": int(bm.shape[0]),
+                      "iters": max(i["iters"] for i in infos), "copy_bytes": 1 << 30}), flush=True)
+
+
 def recorded_traffic(workload, name="dslash_fp64", sources=None):
     """HBM bytes per launch of a roofline kernel (the FP64 hop by default)
     from the committed counter passes (FETCH_SIZE and WRITE_SIZE, each scaled
@@ -694,6 +732,8 @@ def main():
     ap.add_argument("--oracle-solves", action="store_true",
                     help="only the FP64 CGNR to tolerance on 4^4, 24^3x8 and 32^3x8, library and CPU oracle side "
                          "by side (about a minute of host time)")
+    ap.add_argument("--profile-multi-rhs", action="store_true",
+                    help="only the 16-source solve on 32^3x8, twice, and a 1 GiB copy (for counter passes)")
     ap.add_argument("--sweep", action="store_true",
                     help="only the hop rate per lattice size (16^3x8 .. 64^3x16), Wilson and staggered, "
                          "with the CPU oracle's hop beside it")
@@ -721,6 +761,9 @@ def main():
         return
     if args.oracle_solves:
         oracle_solves(stream)
+        return
+    if args.profile_multi_rhs:
+        profile_multi_rhs(stream, dev)
         return
     L = WORKLOADS[args.workload]
     kappa, mu, eps, tol = 0.16, 0.005, 0.4, 1e-10
