@@ -340,6 +340,22 @@ LQCD_API int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op*
                             const void* const* b, void* const* x, const lqcd_solve_params* params,
                             lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* Autotuner of a batch: times `iters` (1..1000) iterations of the batched
+ * CGNR that cg_solve_batch runs on exactly these systems (batched launches,
+ * no graph) for each candidate launch shape of the inner hop family
+ * (LQCD_KERNEL_DSLASH_RHS at params->inner_prec when params->nrhs > 1: block
+ * requests 128, 192, 256 x right-hand-side tile 1 or 2 x tile groups 0..8;
+ * LQCD_KERNEL_DSLASH when nrhs = 1: block x memory order / row tiles x XCD
+ * remap), keeps the fastest in the process-wide table for later solves and
+ * returns it in *best with the time of one iteration in *best_us (either may
+ * be NULL).  Arguments as for cg_solve_batch (params->persistent must be 0);
+ * x and ws are scratch (x is overwritten).  Synchronises stream.  On an error
+ * the table keeps its previous entry.
+ * Paper: section 4 (kernels specialised at run time for the problem at hand). */
+LQCD_API int lqcd_autotune_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,
+                                 const void* const* b, void* const* x, const lqcd_solve_params* params, void* ws,
+                                 size_t ws_bytes, int32_t iters, void* stream, lqcd_launch* best, double* best_us);
+
 /* ------------------------------------------------------------------------
  * Staggered (Kogut-Susskind) fermions.
  *

@@ -1289,6 +1289,121 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
 }
 
 
+// Autotuner of a batch: the inner hop's launch shape timed inside the batched
+// CGNR iteration itself (every system, its volume, its right-hand sides),
+// since the shape that is fastest for one lattice alone need not be for the
+// mix.  For each candidate the systems are set up from scratch, one iteration
+// is recorded and zipped exactly as cg_solve_batch does, started, run once to
+// warm up and then timed over `iters` iterations with HIP events.
+int autotune_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U, const void* const* b,
+                   void* const* x, const lqcd_solve_params* prm, void* ws, size_t ws_bytes, int iters, void* stream,
+                   lqcd_launch* best, double* best_us)
+{
+    g_err[0] = 0;
+    if (nsys < 1 || nsys > kMaxSys) return set_error(LQCD_EINVAL, "nsys %d not in [1, %d]", nsys, kMaxSys);
+    if (!geoms || !ops || !U || !b || !x) return set_error(LQCD_EINVAL, "NULL array argument");
+    if (iters < 1 || iters > 1000) return set_error(LQCD_EINVAL, "iters %d not in [1, 1000]", iters);
+    std::vector<lqcd_solve_info> scratch_info(kMaxRhs);
+    std::vector<Geom> g(nsys);
+    int rc;
+    for (int s = 0; s < nsys; ++s)
+        if ((rc = validate_solve(&geoms[s], &ops[s], U[s], b[s], x[s], prm, scratch_info.data(), M_CG, &g[s])))
+            return rc;
+    if (!ws) return set_error(LQCD_EINVAL, "workspace is NULL");
+    if (prm->persistent) return set_error(LQCD_EINVAL, "tune with persistent = 0 (the batched launches)");
+    BatchLayout L;
+    plan_batch(nsys, g.data(), ops, prm, ws, &L);
+    if (ws_bytes < L.bytes) return set_error(LQCD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nrhs = prm->nrhs;
+    const int prec = prm->inner_prec;
+    const int family = nrhs > 1 ? LQCD_KERNEL_DSLASH_RHS : LQCD_KERNEL_DSLASH;
+    const Launch orig = launch_for(family, prec);
+    std::vector<Launch> cand;
+    for (int blk : {128, 192, 256}) {
+        Launch c = orig;
+        c.block = blk;
+        c.rhs_lanes = 1;
+        if (nrhs > 1) {
+            c.order = orig.order < 1 ? 1 : orig.order;
+            c.swizzle = 1;
+            const int tg[7][2] = {{1, 0}, {1, 2}, {1, 4}, {1, 8}, {2, 0}, {2, 2}, {2, 4}};
+            for (const auto& t : tg) {
+                if (dslash_rhs_tile(prec, t[0], nrhs) != t[0] || t[0] * t[1] > 2 * nrhs) continue;
+                c.rhs_tile = t[0];
+                c.rhs_group = t[1];
+                cand.push_back(c);
+            }
+        } else {
+            for (int order : {0, 1})
+                for (int swz : {0, 1}) {
+                    c.order = order;
+                    c.swizzle = swz;
+                    cand.push_back(c);
+                }
+        }
+    }
+    auto install = [&](const Launch& l) {
+        std::lock_guard<std::mutex> lk(g_launch_mu);
+        g_launch[family][prec_slot(prec)] = l;
+    };
+    hipEvent_t e0, e1;
+    LQCD_HIP(hipEventCreate(&e0));
+    LQCD_HIP(hipEventCreate(&e1));
+    Launch win = orig;
+    float win_ms = -1.f;
+    int result = LQCD_OK;
+    for (const Launch& c : cand) {
+        install(c);
+        std::vector<CgSystem> sys(nsys);
+        for (int s = 0; s < nsys && !result; ++s) {
+            if ((result = sys[s].init(g[s], &ops[s], U[s], b[s], x[s], prm, L.plans[s], st))) break;
+            result = sys[s].setup();
+        }
+        std::vector<Recorder> rec(nsys);
+        for (int s = 0; s < nsys && !result; ++s) {
+            set_recorder(&rec[s]);
+            result = sys[s].iter();
+            set_recorder(nullptr);
+        }
+        BatchProgram prog;
+        if (!result) result = prog.build(rec, L.tables, st);
+        for (int s = 0; s < nsys && !result; ++s) result = sys[s].start();
+        if (!result) result = prog.run(st);
+        if (result) break;
+        hipError_t e = hipEventRecord(e0, st);
+        for (int i = 0; i < iters && e == hipSuccess && !result; ++i) result = prog.run(st);
+        if (result) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            result = set_error(LQCD_EHIP, "batch autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        if (win_ms < 0.f || ms < win_ms) {
+            win_ms = ms;
+            win = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    install(result ? orig : win);
+    if (result) return result;
+    if (best) {
+        best->block = win.block;
+        best->swizzle = win.swizzle;
+        best->order = win.order;
+        best->rhs_tile = win.rhs_tile;
+        best->rhs_group = win.rhs_group;
+        best->ygroup = win.ygroup;
+        best->rhs_lanes = win.rhs_lanes;
+    }
+    if (best_us) *best_us = 1e3 * win_ms / iters;
+    return LQCD_OK;
+}
+
 // Times the even-odd hop of one kernel family (launch(cfg) enqueues one hop
 // with launch shape cfg) in the 32 shapes {memory order, row tiles with y-chunk
 // groups of 1, 2, 3} x {XCD remap off, on} x block {64, 128, 192, 256} with
@@ -2034,6 +2149,13 @@ int cg_solve_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, con
                    void* ws, size_t ws_bytes, void* stream)
 {
     return solve_batch(nsys, geoms, ops, U, b, x, params, info, ws, ws_bytes, stream);
+}
+
+int lqcd_autotune_batch(int32_t nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void* const* U,
+                        const void* const* b, void* const* x, const lqcd_solve_params* params, void* ws,
+                        size_t ws_bytes, int32_t iters, void* stream, lqcd_launch* best, double* best_us)
+{
+    return autotune_batch(nsys, geoms, ops, U, b, x, params, ws, ws_bytes, iters, stream, best, best_us);
 }
 
 

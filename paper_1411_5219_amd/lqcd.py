@@ -32,7 +32,7 @@ SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_device_memory", "lqcd_field_
            "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
            "lqcd_unpack_colour", "stag_apply", "stag_eo_apply", "lqcd_workspace_bytes_stag", "stag_cg_solve",
            "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs", "lqcd_gamma5", "tm_force",
-           "dslash_eo_apply_noalloc"]
+           "dslash_eo_apply_noalloc", "lqcd_autotune_batch"]
 
 
 class Geom(ctypes.Structure):
@@ -114,6 +114,9 @@ def _load():
         "lqcd_workspace_bytes_batch": ([i32, G, O, P, szp], ctypes.c_int),
         "cg_solve_batch": ([i32, G, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), P, I, vp,
                             ctypes.c_size_t, vp], ctypes.c_int),
+        "lqcd_autotune_batch": ([i32, G, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), P, vp,
+                                 ctypes.c_size_t, i32, vp, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)],
+                                ctypes.c_int),
         "lqcd_pack_colour": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "lqcd_unpack_colour": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "stag_apply": ([G, SO, vp, vp, vp, i32, i32, vp], ctypes.c_int),
@@ -300,6 +303,25 @@ def cg_solve_batch(geoms, ops, Us, bs, xs, params, ws, stream=None):
         raise LqcdError(rc, lqcd_last_error())
     flat = [i.as_dict() for i in infos]
     return rc, [flat[s * params.nrhs:(s + 1) * params.nrhs] for s in range(n)]
+
+
+def lqcd_autotune_batch(geoms, ops, Us, bs, xs, params, ws, iters=8, stream=None):
+    """Time the batch's CGNR iteration per inner-hop launch shape and keep the
+    fastest; returns (launch dict, microseconds per iteration).  xs and ws are
+    overwritten."""
+    n = len(geoms)
+    G = (Geom * n)(*geoms)
+    O = (Op * n)(*ops)
+    vp = ctypes.c_void_p
+    Up = (vp * n)(*[_ptr(u) for u in Us])
+    Bp = (vp * n)(*[_ptr(v) for v in bs])
+    Xp = (vp * n)(*[_ptr(v) for v in xs])
+    best = Launch()
+    us = ctypes.c_double()
+    nbytes = ws.numel() * ws.element_size() if hasattr(ws, "numel") else 0
+    _check(_lib.lqcd_autotune_batch(n, G, O, Up, Bp, Xp, ctypes.byref(params), _ptr(ws), nbytes, int(iters),
+                                    _stream(stream), ctypes.byref(best), ctypes.byref(us)))
+    return best.as_dict(), us.value
 
 
 # ---------------------------------------------------------------------------

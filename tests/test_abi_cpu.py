@@ -244,3 +244,28 @@ def test_persistent_parameter_checks():
         with pytest.raises(L.LqcdError) as e:
             fn(g, o, 16, 32, 48, L.solve_params(persistent=1), 64, stream=0)
         assert e.value.code == L.EUNSUPPORTED
+
+
+def test_batch_autotune_validation():
+    """lqcd_autotune_batch refuses before any device work: iters outside
+    1..1000, the persistent launch, a workspace smaller than the batch needs,
+    and a bad lattice among the systems."""
+    from paper_1411_5219_amd import lqcd as L
+    gs = [L.geom((4, 4, 4, 4)), L.geom((6, 4, 4, 4))]
+    os_ = [L.op(0.13, 0.1), L.op(0.12, 0.0)]
+    p = L.solve_params(nrhs=2, inner_prec=32, inner_recon=12)
+    for iters in (0, 1001):
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_autotune_batch(gs, os_, [16, 16], [32, 32], [48, 48], p, 64, iters=iters, stream=0)
+        assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_autotune_batch(gs, os_, [16, 16], [32, 32], [48, 48], L.solve_params(nrhs=2, persistent=1), 64,
+                              stream=0)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LqcdError) as e:  # ws_bytes 0: too small
+        L.lqcd_autotune_batch(gs, os_, [16, 16], [32, 32], [48, 48], p, 64, stream=0)
+    assert e.value.code == L.EINVAL and "workspace" in str(e.value)
+    with pytest.raises(L.LqcdError) as e:
+        L.lqcd_autotune_batch([L.geom((4, 4, 4, 4)), L.geom((5, 4, 4, 4))], os_, [16, 16], [32, 32], [48, 48], p, 64,
+                              stream=0)
+    assert e.value.code == L.EINVAL

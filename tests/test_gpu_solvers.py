@@ -404,6 +404,44 @@ def test_uneven_batch_persistent(mods):
             assert err < 1e-8, (i, k, err)
 
 
+@pytest.mark.parametrize("nrhs,inner", [(2, (32, 12)), (1, (64, 18))])
+def test_uneven_batch_autotune(mods, nrhs, inner):
+    """lqcd_autotune_batch on the uneven batch: it returns one of the shapes
+    it sweeps, installs it for the inner hop family (the right-hand-side
+    family when nrhs > 1) and the batched solve that follows, with that
+    shape, certifies every solution.  The process-wide table is restored
+    afterwards."""
+    torch, fields, lqcd = mods
+    geoms, ops, Us, bs, xs, host, theta, mu = _uneven_batch(mods, nrhs)
+    p = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=inner[0], inner_recon=inner[1])
+    ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p), dtype=torch.uint8, device="cuda")
+    family = lqcd.KERNEL_DSLASH_RHS if nrhs > 1 else lqcd.KERNEL_DSLASH
+    before = lqcd.lqcd_get_launch(family, inner[0])
+    s = torch.cuda.Stream()
+    print(f"\n[case] uneven batch autotune nrhs={nrhs} inner={inner}", flush=True)
+    try:
+        best, us = lqcd.lqcd_autotune_batch(geoms, ops, Us, bs, xs, p, ws, iters=4, stream=s)
+        print(f"  best={best} us/iter={us:.1f}", flush=True)
+        assert best["block"] in (128, 192, 256) and us > 0
+        if nrhs > 1:
+            assert (best["rhs_tile"], best["rhs_group"]) in [(1, 0), (1, 2), (1, 4), (1, 8), (2, 0), (2, 2), (2, 4)]
+        else:
+            assert best["order"] in (0, 1) and best["swizzle"] in (0, 1)
+        assert lqcd.lqcd_get_launch(family, inner[0]) == best
+        with torch.cuda.stream(s):
+            rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p, ws, stream=s)
+        torch.cuda.synchronize()
+        assert rc == 0, infos
+        for i, (L4, kappa, U, b, lat) in enumerate(host):
+            x = lat.unpack(xs[i], 64, nrhs=nrhs)
+            if nrhs == 1:  # one right-hand side comes without the leading axis
+                x, b = x[None], b[None]
+            for k in range(nrhs):
+                assert true_res(U, x[k], b[k], L4, theta, kappa, mu) <= 1e-10, (i, k)
+    finally:
+        lqcd.lqcd_set_launch(family, inner[0], **before)
+
+
 def test_uneven_batch_persistent_give_up(mods):
     """The persistent kernel's failure path, forced from the host: with the
     give-up word set at launch (persistent = 2) every block leaves at its
