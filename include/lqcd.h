@@ -240,6 +240,39 @@ LQCD_API int lqcd_workspace_bytes(const lqcd_geom* geom, const lqcd_op* op, cons
 LQCD_API int lqcd_set_launch(int32_t kernel, int32_t prec, const lqcd_launch* cfg);
 LQCD_API int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg);
 
+/* Autotune cache (the analogue of the paper's cache of compiled kernels,
+ * section 4): launch shapes keyed by the device architecture (gcnArchName
+ * without its feature suffix, e.g. "gfx950"), kernel family
+ * (LQCD_KERNEL_DSLASH, _STAG or _DSLASH_RHS), storage precision, link
+ * reconstruction, lattice extents and right-hand sides.  lqcd_autotune_dslash,
+ * lqcd_autotune_dslash_rhs and lqcd_autotune_stag put their winner there
+ * (besides the process-wide table of lqcd_set_launch); every later launch of
+ * that family on a problem with that key uses the cached shape, which takes
+ * precedence over the table (lqcd_autotune_batch tunes for a mix of lattices
+ * and writes the table only).  The environment variable LQCD_TUNE_CACHE names
+ * a file that is read on first use of the cache (a missing file is an empty
+ * cache) and rewritten after every autotuner run.  File format: a JSON array,
+ * one object per line, {"arch", "kernel", "prec", "recon", "L": [x, y, z, t],
+ * "nrhs", "block", "swizzle", "order", "rhs_tile", "rhs_group", "ygroup",
+ * "rhs_lanes", "us"} with "us" the tuned time of one launch.
+ *   load : merge a file's entries (EINVAL naming the line for a malformed
+ *          entry or an unreadable file; nothing is merged then);
+ *   save : write every entry (to path.tmp, then renamed over path);
+ *   clear: drop every entry (and skip a later read of LQCD_TUNE_CACHE);
+ *   put  : add or replace one entry (cfg validated as by lqcd_set_launch);
+ *   get  : the shape a launch on this key uses: *found = 1 and the cached
+ *          shape (and its time in *us, may be NULL), or *found = 0 and the
+ *          table's shape.
+ * All calls are thread-safe; none touches the device except for reading
+ * the current device's architecture ("host" without a device). */
+LQCD_API int lqcd_tune_cache_load(const char* path);
+LQCD_API int lqcd_tune_cache_save(const char* path);
+LQCD_API int lqcd_tune_cache_clear(void);
+LQCD_API int lqcd_tune_cache_put(int32_t kernel, int32_t prec, int32_t recon, const lqcd_geom* geom, int32_t nrhs,
+                                 const lqcd_launch* cfg, double us);
+LQCD_API int lqcd_tune_cache_get(int32_t kernel, int32_t prec, int32_t recon, const lqcd_geom* geom, int32_t nrhs,
+                                 lqcd_launch* cfg, double* us, int32_t* found);
+
 /* Autotuner: time every Dslash launch configuration (block 64..256, XCD
  * remap on/off, memory or row-tile order) on this geometry with HIP events,
  * `reps` launches each after two warm-up launches, and install the fastest

@@ -13,7 +13,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "lqcd.h"
@@ -150,6 +154,175 @@ Launch launch_for(int kernel, int prec)
     return k < 0 ? Launch{} : g_launch[kernel][k];
 }
 
+// Autotune cache: launch shapes the autotuners found, keyed by the device
+// architecture, kernel family, storage precision, link reconstruction,
+// lattice extents and right-hand sides (the analogue of a compiled-kernel
+// cache that a later run reuses).  A launch for a key in the cache uses the
+// cached shape, any other the process-wide table.  With LQCD_TUNE_CACHE set
+// to a path the cache is read from that file on first use and written back
+// after every autotuner run.
+struct TuneKey {
+    std::string arch;
+    int kernel, prec, recon, L[4], nrhs;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(arch, kernel, prec, recon, L[0], L[1], L[2], L[3], nrhs) <
+               std::tie(o.arch, o.kernel, o.prec, o.recon, o.L[0], o.L[1], o.L[2], o.L[3], o.nrhs);
+    }
+};
+struct TuneVal {
+    Launch l;
+    double us;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+bool g_tune_env_read = false;
+
+// gcnArchName of the current device ("host" without one), e.g. "gfx950:sramecc+:xnack-"
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "host";
+    }
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+TuneKey tune_key(int kernel, int prec, int recon, const int L[4], int nrhs)
+{
+    TuneKey k{device_arch(), kernel, prec, recon, {L[0], L[1], L[2], L[3]}, nrhs};
+    return k;
+}
+
+const char* tune_env_path()
+{
+    const char* p = std::getenv("LQCD_TUNE_CACHE");
+    return p && *p ? p : nullptr;
+}
+
+// Shape checks shared by lqcd_set_launch and the cache (returns an error message or null).
+const char* launch_problem(int kernel, const Launch& c)
+{
+    if (c.block < 64 || c.block > 256 || c.block % 64) return "block not in {64, 128, 192, 256}";
+    if (c.swizzle != 0 && c.swizzle != 1) return "swizzle must be 0 or 1";
+    if (c.order < 0 || c.order > 64) return "order must be in 0..64";
+    if (c.order >= 1 && kernel == LQCD_KERNEL_BLAS) return "order >= 1 applies to the hop kernels only";
+    if (c.rhs_tile != 1 && c.rhs_tile != 2 && c.rhs_tile != 4) return "rhs_tile not in {1, 2, 4}";
+    if (c.rhs_group != 0 && (c.rhs_group < 2 || c.rhs_group > 16)) return "rhs_group not 0 or in [2, 16]";
+    if (c.ygroup < 1 || c.ygroup > 64) return "ygroup not in [1, 64]";
+    if (c.rhs_lanes != 1 && c.rhs_lanes != 2 && c.rhs_lanes != 4 && c.rhs_lanes != 8 && c.rhs_lanes != 16)
+        return "rhs_lanes not in {1, 2, 4, 8, 16}";
+    return nullptr;
+}
+
+int tune_load_locked(const char* path, bool missing_ok)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return missing_ok ? LQCD_OK : set_error(LQCD_EINVAL, "cannot read the tune cache %s", path);
+    std::map<TuneKey, TuneVal> got;
+    char line[1024];
+    int lineno = 0, rc = LQCD_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        const char* b = std::strchr(line, '{');
+        if (!b) {
+            // only the brackets of the array and blank lines carry no entry
+            for (const char* c = line; *c; ++c)
+                if (*c != '[' && *c != ']' && *c != ' ' && *c != '\n' && *c != '\r' && *c != '\t') {
+                    rc = set_error(LQCD_EINVAL, "tune cache %s line %d: not an entry", path, lineno);
+                    break;
+                }
+            if (rc) break;
+            continue;
+        }
+        char arch[64] = "";
+        TuneKey k{};
+        TuneVal v{};
+        const int n = std::sscanf(
+            b,
+            "{\"arch\": \"%63[^\"]\", \"kernel\": %d, \"prec\": %d, \"recon\": %d, \"L\": [%d, %d, %d, %d], "
+            "\"nrhs\": %d, \"block\": %d, \"swizzle\": %d, \"order\": %d, \"rhs_tile\": %d, \"rhs_group\": %d, "
+            "\"ygroup\": %d, \"rhs_lanes\": %d, \"us\": %lf}",
+            arch, &k.kernel, &k.prec, &k.recon, &k.L[0], &k.L[1], &k.L[2], &k.L[3], &k.nrhs, &v.l.block,
+            &v.l.swizzle, &v.l.order, &v.l.rhs_tile, &v.l.rhs_group, &v.l.ygroup, &v.l.rhs_lanes, &v.us);
+        const char* bad = n == 17 ? launch_problem(k.kernel, v.l) : "malformed entry";
+        if (!bad && (k.kernel < 0 || k.kernel > LQCD_KERNEL_DSLASH_RHS)) bad = "unknown kernel";
+        if (!bad && prec_slot(k.prec) < 0) bad = "prec not in {64, 32, 16}";
+        if (!bad && k.recon != 18 && k.recon != 12) bad = "recon not 18 or 12";
+        if (!bad && (k.nrhs < 1 || k.nrhs > kMaxRhs)) bad = "nrhs out of range";
+        if (bad) {
+            rc = set_error(LQCD_EINVAL, "tune cache %s line %d: %s", path, lineno, bad);
+            break;
+        }
+        k.arch = arch;
+        got[k] = v;
+    }
+    std::fclose(f);
+    if (rc) return rc;
+    for (const auto& e : got) g_tune[e.first] = e.second;
+    return LQCD_OK;
+}
+
+int tune_save_locked(const char* path)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return set_error(LQCD_EINVAL, "cannot write the tune cache %s", path);
+    std::fprintf(f, "[\n");
+    size_t i = 0;
+    for (const auto& e : g_tune) {
+        const TuneKey& k = e.first;
+        const TuneVal& v = e.second;
+        std::fprintf(f,
+                     "{\"arch\": \"%s\", \"kernel\": %d, \"prec\": %d, \"recon\": %d, \"L\": [%d, %d, %d, %d], "
+                     "\"nrhs\": %d, \"block\": %d, \"swizzle\": %d, \"order\": %d, \"rhs_tile\": %d, "
+                     "\"rhs_group\": %d, \"ygroup\": %d, \"rhs_lanes\": %d, \"us\": %.3f}%s\n",
+                     k.arch.c_str(), k.kernel, k.prec, k.recon, k.L[0], k.L[1], k.L[2], k.L[3], k.nrhs, v.l.block,
+                     v.l.swizzle, v.l.order, v.l.rhs_tile, v.l.rhs_group, v.l.ygroup, v.l.rhs_lanes, v.us,
+                     ++i < g_tune.size() ? "," : "");
+    }
+    std::fprintf(f, "]\n");
+    const bool ok = std::fflush(f) == 0;
+    std::fclose(f);
+    if (!ok || std::rename(tmp.c_str(), path) != 0) return set_error(LQCD_EINVAL, "cannot write the tune cache %s", path);
+    return LQCD_OK;
+}
+
+// First use: read the file LQCD_TUNE_CACHE names (a missing file is an empty cache).
+void tune_env_init_locked()
+{
+    if (g_tune_env_read) return;
+    g_tune_env_read = true;
+    if (const char* p = tune_env_path()) (void)tune_load_locked(p, true);
+}
+
+// Shape for a launch of kernel family `kernel` on this problem.
+Launch launch_for(int kernel, int prec, int recon, const Geom& g, int nrhs)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_env_init_locked();
+        if (!g_tune.empty()) {
+            const auto it = g_tune.find(tune_key(kernel, prec, recon, g.L, nrhs));
+            if (it != g_tune.end()) return it->second.l;
+        }
+    }
+    return launch_for(kernel, prec);
+}
+
+// An autotuner's result: into the cache (and its file, if LQCD_TUNE_CACHE is set).
+void tune_record(int kernel, int prec, int recon, const int L[4], int nrhs, const Launch& l, double us)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_init_locked();
+    g_tune[tune_key(kernel, prec, recon, L, nrhs)] = TuneVal{l, us};
+    if (const char* p = tune_env_path()) (void)tune_save_locked(p);
+}
+
 // Bump allocator over the caller's workspace.
 struct Arena {
     char* base;
@@ -204,7 +377,7 @@ struct Op {
 
     void tune()
     {
-        dcfg = launch_for(nrhs > 1 ? LQCD_KERNEL_DSLASH_RHS : LQCD_KERNEL_DSLASH, prec);
+        dcfg = launch_for(nrhs > 1 ? LQCD_KERNEL_DSLASH_RHS : LQCD_KERNEL_DSLASH, prec, recon, g, nrhs);
         bcfg = launch_for(LQCD_KERNEL_BLAS, prec);
     }
 
@@ -1412,7 +1585,8 @@ int autotune_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const v
 // the family are kept: they only matter for several right-hand sides) and
 // reports it.  Synchronises the stream.
 template <class F>
-int autotune_hop(int kernel, int prec, int reps, hipStream_t s, lqcd_launch* best, double* best_us, F&& launch)
+int autotune_hop(int kernel, int prec, int recon, const int L[4], int reps, hipStream_t s, lqcd_launch* best,
+                 double* best_us, F&& launch)
 {
     hipEvent_t e0, e1;
     LQCD_HIP(hipEventCreate(&e0));
@@ -1456,6 +1630,7 @@ int autotune_hop(int kernel, int prec, int reps, hipStream_t s, lqcd_launch* bes
         win.rhs_lanes = slot.rhs_lanes;
         slot = win;
     }
+    tune_record(kernel, prec, recon, L, 1, win, 1e3 * win_ms / reps);
     if (best) {
         best->block = win.block;
         best->swizzle = win.swizzle;
@@ -1499,7 +1674,11 @@ struct StagOp {
     RedScratch rs;
     Launch dcfg, bcfg;
 
-    void tune() { dcfg = launch_for(LQCD_KERNEL_STAG, prec); bcfg = launch_for(LQCD_KERNEL_BLAS, prec); }
+    void tune()
+    {
+        dcfg = launch_for(LQCD_KERNEL_STAG, prec, recon, g, nrhs);
+        bcfg = launch_for(LQCD_KERNEL_BLAS, prec);
+    }
 
     DslashArgs base(Ctl* ctl) const
     {
@@ -1872,6 +2051,95 @@ int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg)
     return LQCD_OK;
 }
 
+namespace {
+int tune_args(int32_t kernel, int32_t prec, int32_t recon, const lqcd_geom* geom, int32_t nrhs, Geom* g)
+{
+    if (kernel != LQCD_KERNEL_DSLASH && kernel != LQCD_KERNEL_STAG && kernel != LQCD_KERNEL_DSLASH_RHS)
+        return set_error(LQCD_EINVAL, "kernel %d has no cached shapes (DSLASH, STAG or DSLASH_RHS)", kernel);
+    if (prec_slot(prec) < 0) return set_error(LQCD_EINVAL, "prec %d not in {64, 32, 16}", prec);
+    if (recon != 18 && recon != 12) return set_error(LQCD_EINVAL, "recon %d not 18 or 12", recon);
+    if (nrhs < 1 || nrhs > kMaxRhs) return set_error(LQCD_EINVAL, "nrhs %d not in [1, %d]", nrhs, kMaxRhs);
+    return make_geom(geom, g);
+}
+}  // namespace
+
+int lqcd_tune_cache_load(const char* path)
+{
+    g_err[0] = 0;
+    if (!path) return set_error(LQCD_EINVAL, "path is NULL");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_init_locked();
+    return tune_load_locked(path, false);
+}
+
+int lqcd_tune_cache_save(const char* path)
+{
+    g_err[0] = 0;
+    if (!path) return set_error(LQCD_EINVAL, "path is NULL");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_init_locked();
+    return tune_save_locked(path);
+}
+
+int lqcd_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_env_read = true;  // an explicit clear also drops what the file would add
+    g_tune.clear();
+    return LQCD_OK;
+}
+
+int lqcd_tune_cache_put(int32_t kernel, int32_t prec, int32_t recon, const lqcd_geom* geom, int32_t nrhs,
+                        const lqcd_launch* cfg, double us)
+{
+    g_err[0] = 0;
+    Geom g;
+    int rc = tune_args(kernel, prec, recon, geom, nrhs, &g);
+    if (rc) return rc;
+    if (!cfg) return set_error(LQCD_EINVAL, "cfg is NULL");
+    const Launch l{cfg->block, cfg->swizzle, cfg->order, cfg->rhs_tile, cfg->rhs_group, cfg->ygroup, cfg->rhs_lanes};
+    if (const char* bad = launch_problem(kernel, l)) return set_error(LQCD_EINVAL, "cfg: %s", bad);
+    if (!std::isfinite(us) || us < 0) return set_error(LQCD_EINVAL, "us must be finite and >= 0");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_init_locked();
+    g_tune[tune_key(kernel, prec, recon, g.L, nrhs)] = TuneVal{l, us};
+    return LQCD_OK;
+}
+
+int lqcd_tune_cache_get(int32_t kernel, int32_t prec, int32_t recon, const lqcd_geom* geom, int32_t nrhs,
+                        lqcd_launch* cfg, double* us, int32_t* found)
+{
+    g_err[0] = 0;
+    Geom g;
+    int rc = tune_args(kernel, prec, recon, geom, nrhs, &g);
+    if (rc) return rc;
+    if (!cfg || !found) return set_error(LQCD_EINVAL, "cfg or found is NULL");
+    Launch l;
+    bool hit = false;
+    double t = 0.0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_env_init_locked();
+        const auto it = g_tune.find(tune_key(kernel, prec, recon, g.L, nrhs));
+        if (it != g_tune.end()) {
+            hit = true;
+            l = it->second.l;
+            t = it->second.us;
+        }
+    }
+    if (!hit) l = launch_for(kernel, prec);
+    cfg->block = l.block;
+    cfg->swizzle = l.swizzle;
+    cfg->order = l.order;
+    cfg->rhs_tile = l.rhs_tile;
+    cfg->rhs_group = l.rhs_group;
+    cfg->ygroup = l.ygroup;
+    cfg->rhs_lanes = l.rhs_lanes;
+    if (us) *us = t;
+    *found = hit ? 1 : 0;
+    return LQCD_OK;
+}
+
 int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* in, void* out,
                          int32_t reps, void* stream, lqcd_launch* best, double* best_us)
 {
@@ -1892,7 +2160,7 @@ int lqcd_autotune_dslash(const lqcd_geom* geom, const lqcd_op* op, const void* U
     o.nrhs = 1;
     o.pb = parity_bytes(g, op->prec);
     o.s = static_cast<hipStream_t>(stream);
-    return autotune_hop(LQCD_KERNEL_DSLASH, op->prec, reps, o.s, best, best_us, [&](const Launch& cfg) {
+    return autotune_hop(LQCD_KERNEL_DSLASH, op->prec, op->recon, g.L, reps, o.s, best, best_us, [&](const Launch& cfg) {
         o.dcfg = cfg;
         return o.hop(0, in, out, false, SpinCoef{}, nullptr, coef_real(1.0), nullptr, RED_NONE, FIN_STORE,
                      PRED_ALWAYS);
@@ -1977,6 +2245,7 @@ int lqcd_autotune_dslash_rhs(const lqcd_geom* geom, const lqcd_op* op, const voi
         std::lock_guard<std::mutex> lk(g_launch_mu);
         g_launch[LQCD_KERNEL_DSLASH_RHS][prec_slot(op->prec)] = win;
     }
+    tune_record(LQCD_KERNEL_DSLASH_RHS, op->prec, op->recon, g.L, nrhs, win, 1e3 * win_ms / reps);
     if (best) {
         best->block = win.block;
         best->swizzle = win.swizzle;
@@ -2009,7 +2278,7 @@ int lqcd_autotune_stag(const lqcd_geom* geom, const lqcd_stag_op* op, const void
     o.nrhs = 1;
     o.pb = colour_bytes(g, op->prec);
     o.s = static_cast<hipStream_t>(stream);
-    return autotune_hop(LQCD_KERNEL_STAG, op->prec, reps, o.s, best, best_us, [&](const Launch& cfg) {
+    return autotune_hop(LQCD_KERNEL_STAG, op->prec, op->recon, g.L, reps, o.s, best, best_us, [&](const Launch& cfg) {
         o.dcfg = cfg;
         return o.hop(0, in, out, 0.5, nullptr, 0.0, nullptr, RED_NONE, FIN_STORE, PRED_ALWAYS, nullptr);
     });

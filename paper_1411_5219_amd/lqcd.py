@@ -32,7 +32,8 @@ SYMBOLS = ["lqcd_last_error", "lqcd_version", "lqcd_device_memory", "lqcd_field_
            "bicgstab_solve", "lqcd_workspace_bytes_batch", "cg_solve_batch", "lqcd_pack_colour",
            "lqcd_unpack_colour", "stag_apply", "stag_eo_apply", "lqcd_workspace_bytes_stag", "stag_cg_solve",
            "stag_multishift_solve", "lqcd_autotune_stag", "lqcd_autotune_dslash_rhs", "lqcd_gamma5", "tm_force",
-           "dslash_eo_apply_noalloc", "lqcd_autotune_batch"]
+           "dslash_eo_apply_noalloc", "lqcd_autotune_batch", "lqcd_tune_cache_load", "lqcd_tune_cache_save",
+           "lqcd_tune_cache_clear", "lqcd_tune_cache_put", "lqcd_tune_cache_get"]
 
 
 class Geom(ctypes.Structure):
@@ -117,6 +118,12 @@ def _load():
         "lqcd_autotune_batch": ([i32, G, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), P, vp,
                                  ctypes.c_size_t, i32, vp, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double)],
                                 ctypes.c_int),
+        "lqcd_tune_cache_load": ([ctypes.c_char_p], ctypes.c_int),
+        "lqcd_tune_cache_save": ([ctypes.c_char_p], ctypes.c_int),
+        "lqcd_tune_cache_clear": ([], ctypes.c_int),
+        "lqcd_tune_cache_put": ([i32, i32, i32, G, i32, ctypes.POINTER(Launch), ctypes.c_double], ctypes.c_int),
+        "lqcd_tune_cache_get": ([i32, i32, i32, G, i32, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(i32)], ctypes.c_int),
         "lqcd_pack_colour": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "lqcd_unpack_colour": ([G, i32, i32, vp, vp, vp], ctypes.c_int),
         "stag_apply": ([G, SO, vp, vp, vp, i32, i32, vp], ctypes.c_int),
@@ -303,6 +310,35 @@ def cg_solve_batch(geoms, ops, Us, bs, xs, params, ws, stream=None):
         raise LqcdError(rc, lqcd_last_error())
     flat = [i.as_dict() for i in infos]
     return rc, [flat[s * params.nrhs:(s + 1) * params.nrhs] for s in range(n)]
+
+
+def lqcd_tune_cache_load(path):
+    _check(_lib.lqcd_tune_cache_load(os.fsencode(path)))
+
+
+def lqcd_tune_cache_save(path):
+    _check(_lib.lqcd_tune_cache_save(os.fsencode(path)))
+
+
+def lqcd_tune_cache_clear():
+    _check(_lib.lqcd_tune_cache_clear())
+
+
+def lqcd_tune_cache_put(kernel, prec, recon, g, nrhs, launch, us=0.0):
+    """Add or replace the cached shape for this key; launch is a dict as lqcd_get_launch returns."""
+    cfg = Launch(**{k: int(launch[k]) for k, _ in Launch._fields_})
+    _check(_lib.lqcd_tune_cache_put(int(kernel), int(prec), int(recon), ctypes.byref(g), int(nrhs),
+                                    ctypes.byref(cfg), float(us)))
+
+
+def lqcd_tune_cache_get(kernel, prec, recon, g, nrhs):
+    """(launch dict a launch on this key uses, cached microseconds, found in the cache)."""
+    cfg = Launch()
+    us = ctypes.c_double()
+    found = ctypes.c_int32()
+    _check(_lib.lqcd_tune_cache_get(int(kernel), int(prec), int(recon), ctypes.byref(g), int(nrhs),
+                                    ctypes.byref(cfg), ctypes.byref(us), ctypes.byref(found)))
+    return cfg.as_dict(), us.value, bool(found.value)
 
 
 def lqcd_autotune_batch(geoms, ops, Us, bs, xs, params, ws, iters=8, stream=None):

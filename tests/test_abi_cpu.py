@@ -269,3 +269,97 @@ def test_batch_autotune_validation():
         L.lqcd_autotune_batch([L.geom((4, 4, 4, 4)), L.geom((5, 4, 4, 4))], os_, [16, 16], [32, 32], [48, 48], p, 64,
                               stream=0)
     assert e.value.code == L.EINVAL
+
+
+def test_tune_cache_put_get_save_load(tmp_path):
+    """The autotune cache: an entry put for a key is what a launch on that
+    key uses (found), other keys fall back to the table (not found); save
+    writes a JSON array that load merges back after a clear.  Arch here is
+    "host" (no device in this process)."""
+    import json
+    from paper_1411_5219_amd import lqcd as L
+    L.lqcd_tune_cache_clear()
+    g = L.geom((8, 8, 8, 4))
+    shape = {"block": 128, "swizzle": 0, "order": 1, "rhs_tile": 1, "rhs_group": 0, "ygroup": 2, "rhs_lanes": 1}
+    try:
+        L.lqcd_tune_cache_put(L.KERNEL_DSLASH, 32, 12, g, 1, shape, 12.5)
+        got, us, found = L.lqcd_tune_cache_get(L.KERNEL_DSLASH, 32, 12, g, 1)
+        assert found and got == shape and us == 12.5
+        # another precision, reconstruction, extent or nrhs is another key
+        for key in [(L.KERNEL_DSLASH, 64, 12, g, 1), (L.KERNEL_DSLASH, 32, 18, g, 1),
+                    (L.KERNEL_DSLASH, 32, 12, L.geom((8, 8, 8, 6)), 1), (L.KERNEL_DSLASH_RHS, 32, 12, g, 2)]:
+            got2, _, found2 = L.lqcd_tune_cache_get(*key)
+            assert not found2 and got2 == L.lqcd_get_launch(key[0], key[1])
+        path = str(tmp_path / "tune.json")
+        L.lqcd_tune_cache_save(path)
+        entries = json.load(open(path))
+        assert len(entries) == 1 and entries[0]["L"] == [8, 8, 8, 4] and entries[0]["arch"] == "host"
+        assert entries[0]["block"] == 128 and entries[0]["ygroup"] == 2 and entries[0]["us"] == 12.5
+        L.lqcd_tune_cache_clear()
+        assert not L.lqcd_tune_cache_get(L.KERNEL_DSLASH, 32, 12, g, 1)[2]
+        L.lqcd_tune_cache_load(path)
+        assert L.lqcd_tune_cache_get(L.KERNEL_DSLASH, 32, 12, g, 1)[:2] == (shape, 12.5)
+    finally:
+        L.lqcd_tune_cache_clear()
+
+
+def test_tune_cache_rejects_bad_files_and_arguments(tmp_path):
+    """A malformed line fails the whole load (EINVAL naming the line, nothing
+    merged); an entry for another architecture is kept but never used here;
+    kernel families without cached shapes and invalid shapes are refused."""
+    from paper_1411_5219_amd import lqcd as L
+    L.lqcd_tune_cache_clear()
+    g = L.geom((8, 8, 8, 4))
+    good = ('{"arch": "host", "kernel": 0, "prec": 64, "recon": 18, "L": [8, 8, 8, 4], "nrhs": 1, "block": 192, '
+            '"swizzle": 1, "order": 1, "rhs_tile": 1, "rhs_group": 0, "ygroup": 1, "rhs_lanes": 1, "us": 3.0}')
+    other = good.replace('"host"', '"gfx1100"').replace('"prec": 64', '"prec": 32')
+    try:
+        bad = tmp_path / "bad.json"
+        bad.write_text("[\n" + good + ",\n" + good.replace('"block": 192', '"block": 100') + "\n]\n")
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_tune_cache_load(str(bad))
+        assert e.value.code == L.EINVAL and "line 3" in str(e.value)
+        assert not L.lqcd_tune_cache_get(L.KERNEL_DSLASH, 64, 18, g, 1)[2]
+        bad.write_text("[\nnot json\n]\n")
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_tune_cache_load(str(bad))
+        assert "line 2" in str(e.value)
+        with pytest.raises(L.LqcdError):
+            L.lqcd_tune_cache_load(str(tmp_path / "missing.json"))
+        ok = tmp_path / "ok.json"
+        ok.write_text("[\n" + good + ",\n" + other + "\n]\n")
+        L.lqcd_tune_cache_load(str(ok))
+        assert L.lqcd_tune_cache_get(L.KERNEL_DSLASH, 64, 18, g, 1)[2]
+        assert not L.lqcd_tune_cache_get(L.KERNEL_DSLASH, 32, 18, g, 1)[2]  # the gfx1100 entry
+        shape = L.lqcd_get_launch(L.KERNEL_DSLASH, 64)
+        for args in [(L.KERNEL_BLAS, 64, 18, g, 1, shape), (L.KERNEL_DSLASH, 48, 18, g, 1, shape),
+                     (L.KERNEL_DSLASH, 64, 10, g, 1, shape), (L.KERNEL_DSLASH, 64, 18, g, 0, shape),
+                     (L.KERNEL_DSLASH, 64, 18, g, 1, dict(shape, rhs_lanes=3))]:
+            with pytest.raises(L.LqcdError) as e:
+                L.lqcd_tune_cache_put(*args)
+            assert e.value.code == L.EINVAL
+    finally:
+        L.lqcd_tune_cache_clear()
+
+
+def test_tune_cache_read_from_environment(tmp_path):
+    """LQCD_TUNE_CACHE: a fresh process reads the file on first use of the
+    cache (a missing file is an empty cache)."""
+    import subprocess, sys, textwrap
+    path = tmp_path / "env.json"
+    path.write_text('[\n{"arch": "host", "kernel": 2, "prec": 32, "recon": 12, "L": [4, 4, 4, 4], "nrhs": 1, '
+                    '"block": 64, "swizzle": 0, "order": 0, "rhs_tile": 1, "rhs_group": 0, "ygroup": 1, '
+                    '"rhs_lanes": 1, "us": 1.0}\n]\n')
+    code = textwrap.dedent("""
+        import sys
+        sys.path.insert(0, %r)
+        from paper_1411_5219_amd import lqcd as L
+        got, us, found = L.lqcd_tune_cache_get(L.KERNEL_STAG, 32, 12, L.geom((4, 4, 4, 4)), 1)
+        print(found, got["block"], us)
+    """ % ROOT)
+    import os
+    for p, want in [(path, "True 64 1.0"), (tmp_path / "none.json", "False")]:
+        env = dict(os.environ, LQCD_TUNE_CACHE=str(p))
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        assert r.stdout.strip().startswith(want), r.stdout

@@ -158,6 +158,7 @@ def test_multi_rhs_equals_single(mods, prec, recon, tile, group, lanes):
             assert err <= {64: 1e-15, 32: 1e-6, 16: 2e-3}[prec], (k, err)
     finally:
         lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH_RHS, prec, **saved)
+        lqcd.lqcd_tune_cache_clear()
 
 
 @pytest.mark.parametrize("prec,recon", [(64, 18), (32, 12), (16, 12)])
@@ -222,6 +223,8 @@ def test_rhs_autotune(mods, prec, recon):
         best, us = lqcd.lqcd_autotune_dslash_rhs(lat.g, o, Ud, src, scratch, 6, reps=3)
         now = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH_RHS, prec)
         assert now == best and us > 0
+        cached, cus, found = lqcd.lqcd_tune_cache_get(lqcd.KERNEL_DSLASH_RHS, prec, recon, lat.g, 6)
+        assert found and cached == best and cus > 0  # kept for this lattice and nrhs
         assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, prec) == single
         assert {k: now[k] for k in ("swizzle", "order")} == {k: saved[k] for k in ("swizzle", "order")}
         assert now["block"] in (128, 192, 256)
@@ -320,8 +323,51 @@ def test_autotune_configs_agree(mods):
             scratch = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
             best, us = lqcd.lqcd_autotune_dslash(lat.g, o, Ud, src, scratch, reps=3)
             assert lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 64) == best and us > 0
+            cached, _, found = lqcd.lqcd_tune_cache_get(lqcd.KERNEL_DSLASH, 64, 18, lat.g, 1)
+            assert found and cached == best
+            # the cached shape is what launches on this lattice use, whatever the table says
+            lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, 64, 0, 0)
+            assert lqcd.lqcd_tune_cache_get(lqcd.KERNEL_DSLASH, 64, 18, lat.g, 1)[0] == best
+            out = lat.zeros(lqcd.FIELD_SPINOR_PARITY, 64)
+            lqcd.dslash_eo_apply(lat.g, o, Ud, src, out, 0)
+            torch.cuda.synchronize()
+            assert torch.equal(out, outs[0]), L4
+            lqcd.lqcd_tune_cache_clear()
     finally:
         lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 64, **saved)
+        lqcd.lqcd_tune_cache_clear()
+
+
+def test_tune_cache_file_round_trip(mods, tmp_path):
+    """An autotuner run on the GPU is written to the cache file under this
+    device's architecture and read back after a clear."""
+    import json
+    torch, fields, lqcd = mods
+    L4, theta = (8, 6, 10, 4), (0.0, 0.0, 0.0, math.pi)
+    U, psi = _setup(L4, theta, seed=9, kind="exp")
+    lat = fields.Lattice(L4, theta)
+    o = lqcd.op(0.16, 0.005, 32, 12)
+    Ud = lat.gauge(U, 32, 12)
+    src = lat.parity_view(lat.spinor(psi, 32), 1, 32)
+    saved = lqcd.lqcd_get_launch(lqcd.KERNEL_DSLASH, 32)
+    print("\n[case] tune cache round trip", flush=True)
+    try:
+        lqcd.lqcd_tune_cache_clear()
+        best, us = lqcd.lqcd_autotune_dslash(lat.g, o, Ud, src, lat.zeros(lqcd.FIELD_SPINOR_PARITY, 32), reps=3)
+        path = str(tmp_path / "tune.json")
+        lqcd.lqcd_tune_cache_save(path)
+        entries = json.load(open(path))
+        assert len(entries) == 1
+        e = entries[0]
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        assert e["arch"] == arch and e["L"] == list(L4) and e["prec"] == 32 and e["recon"] == 12 and e["nrhs"] == 1
+        assert {k: e[k] for k in best} == best and abs(e["us"] - us) < 1e-2
+        lqcd.lqcd_tune_cache_clear()
+        lqcd.lqcd_tune_cache_load(path)
+        assert lqcd.lqcd_tune_cache_get(lqcd.KERNEL_DSLASH, 32, 12, lat.g, 1)[0] == best
+    finally:
+        lqcd.lqcd_set_launch(lqcd.KERNEL_DSLASH, 32, **saved)
+        lqcd.lqcd_tune_cache_clear()
 
 
 def test_device_memory(mods):

@@ -232,5 +232,7 @@ def test_launch_shapes_bitwise_and_autotune(mods):
         scratch = lat.zeros(lqcd.FIELD_COLOUR_PARITY, 64)
         best, us = lqcd.lqcd_autotune_stag(lat.g, o, Ud, src, scratch, reps=3)
         assert lqcd.lqcd_get_launch(lqcd.KERNEL_STAG, 64) == best and us > 0
+        assert lqcd.lqcd_tune_cache_get(lqcd.KERNEL_STAG, 64, 18, lat.g, 1)[::2] == (best, True)
     finally:
         lqcd.lqcd_set_launch(lqcd.KERNEL_STAG, 64, **saved)
+        lqcd.lqcd_tune_cache_clear()
