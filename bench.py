@@ -321,6 +321,38 @@ def tuned_batch(gs, os_, Us, bs, xs, p, ws, stream, reps=3):
             "true_resid_max": max(i["true_resid"] for inf in infos for i in inf)}
 
 
+def precision_errors(lat, hop_out, stream):
+    """Per-site relative error of the FP32/12 and FP16/12 even-odd hops
+    against the FP64/18 hop on the same input (the FP64 hop itself matches
+    the CPU oracle to 1e-13 per site at this size in the full-size tests):
+    ||y(x) - y64(x)|| / max(||y64(x)||, RMS_x ||y64||) over the output sites,
+    maximum and RMS, computed on the device in FP64 after unpacking."""
+    import torch
+
+    from paper_1411_5219_amd import lqcd
+
+    def full(k):
+        prec = k[0]
+        pb = lat.nbytes(lqcd.FIELD_SPINOR_PARITY, prec)
+        with torch.cuda.stream(stream):
+            f = lat.zeros(lqcd.FIELD_SPINOR_FULL, prec)
+            f.view(2, pb)[0].copy_(hop_out[k].view(pb))
+            u = lat.unpack(f, prec, stream=stream, numpy=False)
+        torch.cuda.synchronize()
+        return u.reshape(lat.V, 12)
+
+    ref = full((64, 18))
+    nref = torch.linalg.vector_norm(ref, dim=1)
+    mask = nref > 0  # the odd half of the unpacked field is zero
+    rms = torch.sqrt(torch.mean(nref[mask] ** 2))
+    out = {"reference": "FP64/18 hop on the same input", "definition":
+           "||y(x) - y64(x)||_2 / max(||y64(x)||_2, RMS_x ||y64||_2) over output sites"}
+    for k in [(32, 12), (16, 12)]:
+        d = torch.linalg.vector_norm(full(k) - ref, dim=1)[mask] / torch.clamp(nref[mask], min=rms)
+        out[f"fp{k[0]}_{k[1]}"] = {"max_site_rel": float(d.max()), "rms_site_rel": float(torch.sqrt(torch.mean(d ** 2)))}
+    return out
+
+
 def recorded_traffic(workload, name="dslash_fp64", sources=None):
     """HBM bytes per launch of a roofline kernel (the FP64 hop by default)
     from the committed counter passes (FETCH_SIZE and WRITE_SIZE, each scaled
@@ -994,6 +1026,9 @@ def main():
     log("small uneven batch")
     small = uneven_small(stream, mu, tol, DELTA[32])
 
+    log("precision of the reduced-precision hops")
+    prec_err = precision_errors(lat, hop_out, stream)
+
     hop_stats = {}
     for k, evs in rec["hops"].items():
         per_burst = [a.elapsed_time(b_) / args.hops for a, b_ in evs]
@@ -1063,6 +1098,7 @@ def main():
                      "frac": main_k["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "bytes_per_launch": main_k["bytes_per_launch"], "avg_launch_us": main_k["avg_launch_us"]},
         "dslash": hop_stats,
+        "dslash_precision": prec_err,
         "solves": solve_stats,
         "multi_rhs": multi,
         "uneven_batch": uneven,
