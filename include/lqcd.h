@@ -257,7 +257,8 @@ LQCD_API int lqcd_get_launch(int32_t kernel, int32_t prec, lqcd_launch* cfg);
  * "rhs_lanes", "us"} with "us" the tuned time of one launch.
  *   load : merge a file's entries (EINVAL naming the line for a malformed
  *          entry or an unreadable file; nothing is merged then);
- *   save : write every entry (to path.tmp, then renamed over path);
+ *   save : write every entry (to a temporary file beside path, then renamed
+ *          over it);
  *   clear: drop every entry (and skip a later read of LQCD_TUNE_CACHE);
  *   put  : add or replace one entry (cfg validated as by lqcd_set_launch);
  *   get  : the shape a launch on this key uses: *found = 1 and the cached

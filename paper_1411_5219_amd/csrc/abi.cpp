@@ -15,6 +15,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <map>
+#include <unistd.h>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -178,18 +179,30 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 bool g_tune_env_read = false;
 
-// gcnArchName of the current device ("host" without one), e.g. "gfx950:sramecc+:xnack-"
+// Architecture of the current device without its feature suffix (gcnArchName
+// "gfx950:sramecc+:xnack-" -> "gfx950"; "host" without a device), looked up
+// once per device: the lookup sits on the launch path.  Callers hold g_tune_mu.
 std::string device_arch()
 {
+    static std::map<int, std::string> known;
     int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
         return "host";
     }
-    std::string a(prop.gcnArchName);
-    const size_t c = a.find(':');
-    return c == std::string::npos ? a : a.substr(0, c);
+    const auto it = known.find(dev);
+    if (it != known.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string a = "host";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        a = prop.gcnArchName;
+        const size_t c = a.find(':');
+        if (c != std::string::npos) a = a.substr(0, c);
+    } else {
+        (void)hipGetLastError();
+    }
+    known[dev] = a;
+    return a;
 }
 
 TuneKey tune_key(int kernel, int prec, int recon, const int L[4], int nrhs)
@@ -269,7 +282,7 @@ int tune_load_locked(const char* path, bool missing_ok)
 
 int tune_save_locked(const char* path)
 {
-    const std::string tmp = std::string(path) + ".tmp";
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return set_error(LQCD_EINVAL, "cannot write the tune cache %s", path);
     std::fprintf(f, "[\n");
