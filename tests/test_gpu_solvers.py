@@ -442,6 +442,46 @@ def test_uneven_batch_autotune(mods, nrhs, inner):
         lqcd.lqcd_set_launch(family, inner[0], **before)
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_batch_of_sixteen_systems(mods, persistent):
+    """The largest batch (16 systems): tiny lattices of eight different
+    shapes (extents 2..8, ragged against every block and row tile), each with
+    its own kappa, 2 right-hand sides, FP32/12 inner; all 32 solutions
+    certified by the oracle's M, as batched launches and as one persistent
+    launch."""
+    torch, fields, lqcd = mods
+    shapes = [(2, 2, 2, 2), (4, 2, 2, 2), (2, 4, 2, 4), (4, 4, 4, 2), (6, 2, 4, 2), (2, 6, 2, 6), (4, 4, 2, 6),
+              (8, 2, 2, 4)] * 2
+    theta, mu, nrhs = (0, 0, 0, math.pi), 0.005, 2
+    geoms, ops, Us, bs, xs, host = [], [], [], [], [], []
+    for i, L4 in enumerate(shapes):
+        kappa = 0.12 + 0.002 * i
+        U = gauge_field(L4, "exp", eps=0.4, seed=1300 + i)
+        b = gaussian_spinor(L4, seed=2300 + i, nrhs=nrhs)
+        lat = fields.Lattice(L4, theta)
+        geoms.append(lat.g)
+        ops.append(lqcd.op(kappa, mu))
+        Us.append(lat.gauge(U))
+        bs.append(lat.spinor(b))
+        xs.append(lat.zeros(lqcd.FIELD_SPINOR_FULL, 64, nrhs=nrhs))
+        host.append((L4, kappa, U, b, lat))
+    p = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, use_graph=1,
+                          persistent=persistent)
+    ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    print(f"\n[case] 16-system batch persistent={persistent}", flush=True)
+    with torch.cuda.stream(s):
+        rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p, ws, stream=s)
+    torch.cuda.synchronize()
+    assert rc == 0, infos
+    assert len(infos) == 16 and all(len(i) == nrhs for i in infos)
+    for i, (L4, kappa, U, b, lat) in enumerate(host):
+        x = lat.unpack(xs[i], 64, nrhs=nrhs)
+        for k in range(nrhs):
+            tr = true_res(U, x[k], b[k], L4, theta, kappa, mu)
+            assert tr <= 1e-10, (i, L4, k, tr)
+
+
 def test_uneven_batch_persistent_give_up(mods):
     """The persistent kernel's failure path, forced from the host: with the
     give-up word set at launch (persistent = 2) every block leaves at its
