@@ -130,7 +130,9 @@ typedef struct {
  *                  cooperative launch (grid barriers between the steps, no
  *                  host round trip until every system is done; needs nrhs >= 2,
  *                  inner FP32/12 and outer 18-real links, else
- *                  LQCD_EUNSUPPORTED); 2: as 1 with the kernel's give-up word
+ *                  LQCD_EUNSUPPORTED; with use_graph the reset of the barrier
+ *                  words and the cooperative launch are captured once per call
+ *                  and replayed at each start); 2: as 1 with the kernel's give-up word
  *                  set at launch, so that its first grid barrier gives up and
  *                  the call fails with LQCD_EHIP (the failure path, for tests) */
 typedef struct {

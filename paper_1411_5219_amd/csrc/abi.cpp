@@ -1429,18 +1429,44 @@ int solve_batch(int nsys, const lqcd_geom* geoms, const lqcd_op* ops, const void
         LQCD_HIP(hipStreamSynchronize(st));
     }
 
+    // the captured persistent launch (use_graph), destroyed on every way out
+    struct GraphHold {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~GraphHold()
+        {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+    } pgraph;
     std::vector<Ctl> ctl;
     int restarts = 0;
     for (;;) {
         for (int s = 0; s < nsys; ++s)
             if ((rc = sys[s].start())) return rc;
         if (prm->persistent) {
-            // barrier slots zero; the give-up word set for persistent = 2
-            const unsigned flags[2] = {prm->persistent == 2 ? 1u : 0u, 0u};
-            LQCD_HIP(hipMemsetAsync(L.words, 0, 2 * kMaxPersistBlocks * sizeof(unsigned), st));
-            LQCD_HIP(hipMemcpyAsync(L.words + 2 * kMaxPersistBlocks, flags, sizeof(flags), hipMemcpyHostToDevice, st));
-            LQCD_HIP(hipStreamSynchronize(st));
-            LQCD_HIP(launch_batch_persistent(L.prog, pgrid, st));
+            // barrier slots zero and the give-up word set for persistent = 2
+            // (a kernel), then the cooperative launch; with use_graph both
+            // are captured once and replayed at every start
+            const int give_up = prm->persistent == 2 ? 1 : 0;
+            if (prm->use_graph) {
+                if (!pgraph.exec) {
+                    LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    hipError_t e1 = launch_persist_reset(L.words, 2 * kMaxPersistBlocks, give_up, st);
+                    if (e1 == hipSuccess) e1 = launch_batch_persistent(L.prog, pgrid, st);
+                    hipGraph_t gph = nullptr;
+                    const hipError_t e2 = hipStreamEndCapture(st, &gph);
+                    pgraph.graph = gph;
+                    if (e1 != hipSuccess || e2 != hipSuccess)
+                        return set_error(LQCD_EHIP, "capture of the persistent launch failed: %s",
+                                         hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+                    LQCD_HIP(hipGraphInstantiate(&pgraph.exec, pgraph.graph, nullptr, nullptr, 0));
+                }
+                LQCD_HIP(hipGraphLaunch(pgraph.exec, st));
+            } else {
+                LQCD_HIP(launch_persist_reset(L.words, 2 * kMaxPersistBlocks, give_up, st));
+                LQCD_HIP(launch_batch_persistent(L.prog, pgrid, st));
+            }
             ++launches;
             unsigned back[2] = {0u, 0u};
             LQCD_HIP(hipMemcpyAsync(back, L.words + 2 * kMaxPersistBlocks, sizeof(back), hipMemcpyDeviceToHost, st));

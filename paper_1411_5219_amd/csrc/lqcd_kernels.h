@@ -365,6 +365,9 @@ constexpr int kMaxPersistBlocks = 2048;
 hipError_t persistent_grid(int* blocks);
 // Cooperative launch of the persistent kernel on prog_dev (device memory).
 hipError_t launch_batch_persistent(const PProgram* prog_dev, int blocks, hipStream_t s);
+// Zero the nslots barrier slots at words and set the two flags after them to
+// (give_up, 0), with a kernel (capturable without a memset node).
+hipError_t launch_persist_reset(unsigned* words, int nslots, int give_up, hipStream_t s);
 
 // Initialise control blocks on the device (every right-hand side from in;
 // the short form: a plain or reliable-update solve without stagnation

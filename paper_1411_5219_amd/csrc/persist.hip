@@ -239,7 +239,21 @@ k_batch_persistent(const PProgram* __restrict__ prog)
     }
 }
 
+// The barrier slots to zero and the two flags to (give_up, 0): a kernel, so
+// that a captured graph holds no memset node.
+__global__ void k_persist_reset(unsigned* words, int nslots, int give_up)
+{
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < nslots + 2; i += (int)(gridDim.x * blockDim.x))
+        words[i] = i < nslots ? 0u : (i == nslots ? (unsigned)give_up : 0u);
+}
+
 }  // namespace
+
+hipError_t launch_persist_reset(unsigned* words, int nslots, int give_up, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_persist_reset, dim3(16), dim3(256), 0, s, words, nslots, give_up);
+    return hipGetLastError();
+}
 
 hipError_t persistent_grid(int* blocks)
 {

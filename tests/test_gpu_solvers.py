@@ -369,18 +369,21 @@ def _uneven_batch(mods, nrhs=2):
     return geoms, ops, Us, bs, xs, host, theta, mu
 
 
-def test_uneven_batch_persistent(mods):
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_uneven_batch_persistent(mods, use_graph):
     """The uneven batch in one persistent cooperative launch per start (grid
-    barriers between the steps of the iteration): every solution certified
-    by the oracle's M and equal, within cond(M) tol, to the batched-launch
-    solve of the same systems."""
+    barriers between the steps of the iteration), launched directly or
+    replayed from a captured graph: every solution certified by the oracle's
+    M and equal, within cond(M) tol, to the batched-launch solve of the same
+    systems."""
     torch, fields, lqcd = mods
     nrhs = 2
     geoms, ops, Us, bs, xs, host, theta, mu = _uneven_batch(mods, nrhs)
-    p = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=1)
+    p = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=1,
+                          use_graph=use_graph)
     ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p), dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
-    print("\n[case] uneven batch, persistent launch", flush=True)
+    print(f"\n[case] uneven batch, persistent launch use_graph={use_graph}", flush=True)
     with torch.cuda.stream(s):
         rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p, ws, stream=s)
     torch.cuda.synchronize()
@@ -482,23 +485,28 @@ def test_batch_of_sixteen_systems(mods, persistent):
             assert tr <= 1e-10, (i, L4, k, tr)
 
 
-def test_uneven_batch_persistent_give_up(mods):
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_uneven_batch_persistent_give_up(mods, use_graph):
     """The persistent kernel's failure path, forced from the host: with the
     give-up word set at launch (persistent = 2) every block leaves at its
-    first grid barrier, the kernel ends and the call fails with EHIP; the
-    device then runs the same batch normally."""
+    first grid barrier, the kernel ends and the call fails with EHIP (also
+    when the launch is replayed from a graph); the device then runs the same
+    batch normally."""
     torch, fields, lqcd = mods
     nrhs = 2
     geoms, ops, Us, bs, xs, host, theta, mu = _uneven_batch(mods, nrhs)
-    p2 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=2)
+    p2 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=2,
+                           use_graph=use_graph)
     ws = torch.empty(lqcd.lqcd_workspace_bytes_batch(geoms, ops, p2), dtype=torch.uint8, device="cuda")
-    print("\n[case] uneven batch, persistent give-up", flush=True)
+    s = torch.cuda.Stream()
+    print(f"\n[case] uneven batch, persistent give-up use_graph={use_graph}", flush=True)
     with pytest.raises(lqcd.LqcdError) as e:
-        lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p2, ws)
+        lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p2, ws, stream=s)
     assert e.value.code == lqcd.EHIP and "gave up" in str(e.value)
     torch.cuda.synchronize()
-    p1 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=1)
-    rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p1, ws)
+    p1 = lqcd.solve_params(tol=1e-10, maxiter=20000, nrhs=nrhs, inner_prec=32, inner_recon=12, persistent=1,
+                           use_graph=use_graph)
+    rc, infos = lqcd.cg_solve_batch(geoms, ops, Us, bs, xs, p1, ws, stream=s)
     assert rc == 0, infos
     for i, (L4, kappa, U, b, lat) in enumerate(host):
         x = lat.unpack(xs[i], 64, nrhs=nrhs)
