@@ -10,7 +10,11 @@ solvers here are the textbook methods:
 * CGNR: conjugate gradient on the normal equations M^+ M x = M^+ b that
   tracks the residual r = b - M x of the original system (Saad, "Iterative
   Methods for Sparse Linear Systems", the CGNR algorithm);
-* BiCGStab (van der Vorst 1992) on the non-Hermitian M directly.
+* BiCGStab (van der Vorst 1992) on the non-Hermitian M directly;
+* BiCGStab(l) (Sleijpen and Fokkema 1993): l BiCG steps, then a minimal
+  residual polynomial of degree l instead of BiCGStab's degree 1, which
+  handles the complex eigenvalue pairs near the imaginary axis on which
+  BiCGStab's one-dimensional minimisation stalls; l = 1 is BiCGStab.
 
 Both stop when the tracked residual satisfies ||r|| <= tol * ||b_ref||, then
 recompute the true residual in FP64; if that misses the tolerance they
@@ -167,9 +171,116 @@ def bicgstab(A, b, tol, maxiter, b_ref_norm=None, residual=None, x0=None):
     return x, info
 
 
-def solve(U, b, L, theta, kappa, mu, tol, maxiter=100000, method="cgnr", eo=True):
-    """x = M^-1 b with the chosen method, on the full lattice or through the
-    even-odd Schur complement (prepare, solve on even sites, reconstruct)."""
+def bicgstab_l(A, b, tol, maxiter, ell=2, b_ref_norm=None, residual=None, x0=None):
+    """BiCGStab(ell) (Sleijpen and Fokkema 1993) on A x = b.
+
+    Each cycle takes ell BiCG steps that build r_0..r_ell with r_{j+1} =
+    A r_j (and u_0..u_ell likewise), then chooses the polynomial of degree
+    ell that minimises ||r_0 - sum_j g_j r_j|| by modified Gram-Schmidt on
+    r_1..r_ell.  maxiter and info.iters count BiCG steps (ell per cycle,
+    2 applications of A each).  Stopping and restarts as for bicgstab."""
+    info = SolveInfo()
+    bn = float(np.sqrt(_nrm2(b))) if b_ref_norm is None else float(b_ref_norm)
+    if residual is None:
+        residual = lambda x: float(np.sqrt(_nrm2(b - A(x)))) / bn  # noqa: E731
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    if bn == 0.0:
+        info.true_resid = 0.0
+        return x, info
+    if not np.all(np.isfinite(b)):
+        info.status = ENONFINITE
+        return x, info
+
+    def start(x):
+        r = [b - A(x)] + [None] * ell
+        u = [np.zeros_like(b)] + [None] * ell
+        return r, u, r[0].copy(), 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+
+    r, u, rt, rho0, alpha, omega = start(x)
+    k = 0
+    while True:
+        if np.sqrt(_nrm2(r[0])) <= tol * bn:
+            tr = residual(x)
+            if tr <= tol:
+                info.true_resid = tr
+                break
+            info.restarts += 1
+            r, u, rt, rho0, alpha, omega = start(x)
+        if k >= maxiter:
+            info.status = ENOCONV
+            info.true_resid = residual(x)
+            break
+        rho0 = -omega * rho0
+        broke = False
+        # the BiCG part: ell steps, each extending the r and u sequences by one
+        for j in range(ell):
+            rho1 = _dot(rt, r[j])
+            if rho0 == 0:
+                broke = True
+                break
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = A(u[j])
+            gamma = _dot(rt, u[j + 1])
+            if gamma == 0:
+                broke = True
+                break
+            alpha = rho0 / gamma
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = A(r[j])
+            x = x + alpha * u[0]
+        if broke:
+            info.status = EBREAKDOWN
+            info.true_resid = residual(x)
+            break
+        # the minimal residual part: modified Gram-Schmidt on r_1..r_ell
+        tau = np.zeros((ell + 1, ell + 1), dtype=complex)
+        sigma = np.zeros(ell + 1)
+        gp = np.zeros(ell + 1, dtype=complex)
+        for j in range(1, ell + 1):
+            for i in range(1, j):
+                tau[i, j] = _dot(r[i], r[j]) / sigma[i]
+                r[j] = r[j] - tau[i, j] * r[i]
+            sigma[j] = _nrm2(r[j])
+            if sigma[j] == 0.0:
+                broke = True
+                break
+            gp[j] = _dot(r[j], r[0]) / sigma[j]
+        if broke:
+            # r_j = 0 for some j: x already solves the system to rounding
+            k += ell
+            continue
+        g = np.zeros(ell + 1, dtype=complex)
+        g[ell] = gp[ell]
+        omega = g[ell]
+        for j in range(ell - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, ell + 1))
+        gpp = np.zeros(ell + 1, dtype=complex)
+        for j in range(1, ell):
+            gpp[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, ell))
+        x = x + g[1] * r[0]
+        r[0] = r[0] - gp[ell] * r[ell]
+        u[0] = u[0] - g[ell] * u[ell]
+        for j in range(1, ell):
+            u[0] = u[0] - g[j] * u[j]
+            x = x + gpp[j] * r[j]
+            r[0] = r[0] - gp[j] * r[j]
+        k += ell
+        if not np.isfinite(_nrm2(r[0])):
+            info.status = ENONFINITE
+            info.true_resid = residual(x)
+            break
+    info.iters = k
+    return x, info
+
+
+def solve(U, b, L, theta, kappa, mu, tol, maxiter=100000, method="cgnr", eo=True, ell=2):
+    """x = M^-1 b with the chosen method ("cgnr", "bicgstab" or "bicgstab_l"
+    with degree ell), on the full lattice or through the even-odd Schur
+    complement (prepare, solve on even sites, reconstruct)."""
     bn = float(np.sqrt(_nrm2(b)))
     if not eo:
         A = lambda v: W.apply_M(U, v, L, theta, kappa, mu)  # noqa: E731
@@ -177,6 +288,8 @@ def solve(U, b, L, theta, kappa, mu, tol, maxiter=100000, method="cgnr", eo=True
         res = lambda x: W.true_residual(U, x, b, L, theta, kappa, mu)  # noqa: E731
         if method == "cgnr":
             x, info = cgnr(A, Ah, b, tol, maxiter, bn, res)
+        elif method == "bicgstab_l":
+            x, info = bicgstab_l(A, b, tol, maxiter, ell, bn, res)
         else:
             x, info = bicgstab(A, b, tol, maxiter, bn, res)
         return x, info
@@ -191,6 +304,8 @@ def solve(U, b, L, theta, kappa, mu, tol, maxiter=100000, method="cgnr", eo=True
 
     if method == "cgnr":
         x_e, info = cgnr(A, Ah, bhat, tol, maxiter, bn, res)
+    elif method == "bicgstab_l":
+        x_e, info = bicgstab_l(A, bhat, tol, maxiter, ell, bn, res)
     else:
         x_e, info = bicgstab(A, bhat, tol, maxiter, bn, res)
     x = W.eo_reconstruct(U, x_e, b, L, theta, kappa, mu)
