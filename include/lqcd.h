@@ -134,7 +134,16 @@ typedef struct {
  *                  words and the cooperative launch are captured once per call
  *                  and replayed at each start); 2: as 1 with the kernel's give-up word
  *                  set at launch, so that its first grid barrier gives up and
- *                  the call fails with LQCD_EHIP (the failure path, for tests) */
+ *                  the call fails with LQCD_EHIP (the failure path, for tests)
+ *   bicgstab_ell   bicgstab_solve only (the other solvers ignore it; values
+ *                  outside {0, 1, 2} are LQCD_EINVAL everywhere).  0 or 1:
+ *                  BiCGStab; 2: BiCGStab(2) (Sleijpen and Fokkema 1993):
+ *                  cycles of two BiCG steps and a minimal-residual polynomial
+ *                  of degree 2, which keeps converging on spectra with complex
+ *                  eigenvalue pairs where BiCGStab's degree-1 factors stall.
+ *                  info.iters counts BiCG steps (2 per cycle, each 2
+ *                  applications of the operator, as one BiCGStab iteration);
+ *                  maxiter bounds the same count; FP64 only (inner_prec 64) */
 typedef struct {
     double tol;
     int32_t maxiter;
@@ -149,6 +158,7 @@ typedef struct {
     double tol_inner;
     int32_t max_stagnations;
     int32_t persistent;
+    int32_t bicgstab_ell;
 } lqcd_solve_params;
 
 /* Filled by the solvers (one per right-hand side / system). */
@@ -352,7 +362,9 @@ LQCD_API int dslash_eo_apply_noalloc(const lqcd_geom* geom, const lqcd_op* op, c
 LQCD_API int cg_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
              const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
-/* Same contract, BiCGStab on M (or on Mhat with eo = 1).
+/* Same contract, BiCGStab on M (or on Mhat with eo = 1); BiCGStab(2) with
+ * params->bicgstab_ell = 2 (workspace: 9 FP64 vectors per right-hand side
+ * with eo, 7 without, against BiCGStab's 8 and 6).
  * Paper: section 3 (standard inversion algorithms). */
 LQCD_API int bicgstab_solve(const lqcd_geom* geom, const lqcd_op* op, const void* U, const void* b, void* x,
                    const lqcd_solve_params* params, lqcd_solve_info* info, void* ws, size_t ws_bytes,

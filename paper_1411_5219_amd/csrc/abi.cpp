@@ -372,7 +372,7 @@ void plan_reductions(Arena& ar, const Geom& g, int nrhs, RedScratch* rs)
 {
     const int64_t nblk = max_blocks(g);
     rs->capacity = (int)nblk;
-    rs->partials = static_cast<double*>(ar.take(sizeof(double) * 3 * nblk * nrhs));
+    rs->partials = static_cast<double*>(ar.take(sizeof(double) * kMaxFin * nblk * nrhs));
     rs->ctl = static_cast<Ctl*>(ar.take(sizeof(Ctl) * kMaxRhs));
 }
 
@@ -572,8 +572,10 @@ int plan_solver(const Geom& g, const lqcd_op* op, const lqcd_solve_params* prm, 
     const bool mixed = prm->inner_prec != 64;
     // FP64 vectors: CG eo: r p w z t bhat | BiCG eo: r r0 p v s t tmp bhat
     //               CG full: r p w z     | BiCG full: r r0 p v s t
+    //               BiCGStab(2) eo: r_0 r_1 r_2 u_0 u_1 u_2 rt tmp bhat (full: the first 7)
     int nv = 0;
     if (method == M_CG) nv = mixed ? 3 : (eo ? 6 : 4);
+    else if (prm->bicgstab_ell == 2) nv = eo ? 9 : 7;
     else nv = eo ? 8 : 6;
     for (int i = 0; i < nv; ++i) sp->v[i] = ar.take((size_t)vec);
     if (mixed) {
@@ -607,6 +609,8 @@ int check_params(const lqcd_solve_params* p, int method)
             return set_error(LQCD_EINVAL, "tol_inner must be in [0, 1)");
     }
     if (p->persistent < 0 || p->persistent > 2) return set_error(LQCD_EINVAL, "persistent %d not in {0, 1, 2}", p->persistent);
+    if (p->bicgstab_ell < 0 || p->bicgstab_ell > 2)
+        return set_error(LQCD_EINVAL, "bicgstab_ell %d not in {0, 1, 2}", p->bicgstab_ell);
     return LQCD_OK;
 }
 
@@ -1089,6 +1093,10 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
         char* xc = static_cast<char*>(x);
         void *r = sp.v[0], *r0 = sp.v[1], *p = sp.v[2], *v = sp.v[3], *sv = sp.v[4], *t = sp.v[5];
         void *tmp = sp.v[6], *bhat = sp.v[7];
+        if (prm->bicgstab_ell == 2) {
+            tmp = sp.v[7];
+            bhat = sp.v[8];
+        }
         if ((rc = solver_setup(o, prm, eo, false, bc, xc, bhat, tmp))) return rc;
         auto apply = [&](const void* in, void* out, int red, int fin, const void* aux) -> hipError_t {
             if (eo) return o.schur(in, out, tmp, false, 1.0, nullptr, red, fin, PRED_ACTIVE, aux);
@@ -1121,9 +1129,58 @@ int solve(int method, const lqcd_geom* geom, const lqcd_op* opi, const void* U, 
             LQCD_K(launch_blas(64, BLAS_BI_XR, a, nrhs, o.bcfg, s));
             return LQCD_OK;
         };
+        // BiCGStab(2) (Sleijpen and Fokkema 1993): one cycle is two BiCG
+        // steps, each extending u_0.. and r_0.. by one application of the
+        // operator, then the minimal-residual polynomial of degree 2 over
+        // r_1, r_2 (Gram-Schmidt).  u_0 -= g1 u_1 + g2 u_2 of the polynomial
+        // step is folded into the next cycle's first update of u_0.
+        void *q0 = sp.v[0], *q1 = sp.v[1], *q2 = sp.v[2], *u0 = sp.v[3], *u1 = sp.v[4], *u2 = sp.v[5];
+        void* rt = sp.v[6];
+        auto start2 = [&]() -> int {
+            if (eo) LQCD_K(o.schur(xc, q0, tmp, false, -1.0, bhat, RED_NONE, FIN_STORE, PRED_ACTIVE, nullptr, fb, pb));
+            else LQCD_K(o.full_M(xc, q0, false, -1.0, bc, RED_NONE, FIN_STORE, PRED_ACTIVE));
+            LQCD_K(o.blas(BLAS_COPY, nsub, PRED_ACTIVE, FIN_STORE, q0, rt));
+            LQCD_K(o.blas(BLAS_NORM_DOT, nsub, PRED_ACTIVE, FIN_BL_INIT, q0, nullptr, nullptr, nullptr, nullptr, rt));
+            for (void* u : {u0, u1, u2}) LQCD_K(o.blas(BLAS_ZERO, nsub, PRED_ACTIVE, FIN_STORE, nullptr, u));
+            return LQCD_OK;
+        };
+        // the solution x (the even half of the caller's full field with eo) is strided by fb
+        auto blas_x = [&](int op, int fin, void* y, void* z, void* w, void* v, const void* r0v) -> hipError_t {
+            BlasArgs a = o.blas_base(nsub);
+            a.pred = PRED_ACTIVE;
+            a.x = xc;
+            a.y = y;
+            a.z = z;
+            a.w = w;
+            a.v = v;
+            a.r0 = r0v;
+            a.st_x = fb;
+            a.r.fin = fin;
+            return launch_blas(64, op, a, nrhs, o.bcfg, s);
+        };
+        auto iter2 = [&]() -> int {
+            // first BiCG step: u_1 = A u_0, r_1 = A r_0
+            LQCD_K(o.blas(BLAS_BL_U0, nsub, PRED_ACTIVE, FIN_STORE, nullptr, u0, q0, u1, u2));
+            LQCD_K(apply(u0, u1, RED_DOT_AUX, FIN_BL_ALPHA, rt));
+            LQCD_K(blas_x(BLAS_BL_XR0, FIN_STORE, u0, q0, u1, nullptr, nullptr));
+            LQCD_K(apply(q0, q1, RED_DOT_AUX, FIN_BL_BETA, rt));
+            // second BiCG step: u_2 = A u_1, r_2 = A r_1
+            LQCD_K(o.blas(BLAS_BL_U01, nsub, PRED_ACTIVE, FIN_STORE, nullptr, u0, q0, u1, q1));
+            LQCD_K(apply(u1, u2, RED_DOT_AUX, FIN_BL_ALPHA, rt));
+            LQCD_K(blas_x(BLAS_BL_XR01, FIN_STORE, u0, q0, u1, q1, u2));
+            LQCD_K(apply(q1, q2, RED_NONE, FIN_STORE, nullptr));
+            // minimal residual over r_1, r_2
+            LQCD_K(o.blas(BLAS_BL_GRAM, nsub, PRED_ACTIVE, FIN_BL_TAU, nullptr, nullptr, q0, q1, q2));
+            LQCD_K(o.blas(BLAS_BL_ORTH, nsub, PRED_ACTIVE, FIN_BL_OMEGA, nullptr, nullptr, q0, q1, q2));
+            LQCD_K(blas_x(BLAS_BL_MR, FIN_BL_RES, nullptr, q0, q1, q2, rt));
+            return LQCD_OK;
+        };
+        const bool ell2 = prm->bicgstab_ell == 2;
         for (;;) {
-            if ((rc = start())) return rc;
-            if ((rc = drive(s, sp.rs.ctl, 1, nrhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter))) return rc;
+            if ((rc = ell2 ? start2() : start())) return rc;
+            if (ell2) rc = drive(s, sp.rs.ctl, 1, nrhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter2);
+            else rc = drive(s, sp.rs.ctl, 1, nrhs, nrhs, chunk, prm->maxiter, prm->use_graph != 0, iter);
+            if (rc) return rc;
             if ((rc = solver_finish(o, eo, bc, xc))) return rc;
             if ((rc = read_ctls(s, sp.rs.ctl, nrhs, ctl))) return rc;
             const unsigned reopen = reopen_mask(ctl.data(), nrhs, prm);

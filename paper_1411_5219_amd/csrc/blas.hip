@@ -66,6 +66,13 @@ static hipError_t blas_op(int op, const BlasLaunch& L, dim3 grid, dim3 block, hi
             LQCD_BLAS_CASE(BLAS_BI_XR)
             LQCD_BLAS_CASE(BLAS_XPY)
             LQCD_BLAS_CASE(BLAS_NORM_DOT)
+            LQCD_BLAS_CASE(BLAS_BL_U0)
+            LQCD_BLAS_CASE(BLAS_BL_XR0)
+            LQCD_BLAS_CASE(BLAS_BL_U01)
+            LQCD_BLAS_CASE(BLAS_BL_XR01)
+            LQCD_BLAS_CASE(BLAS_BL_GRAM)
+            LQCD_BLAS_CASE(BLAS_BL_ORTH)
+            LQCD_BLAS_CASE(BLAS_BL_MR)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -113,9 +120,10 @@ hipError_t plan_blas(int prec, int op, const BlasArgs& a, int nrhs, const Launch
     p.grid = dim3(nbs * a.nsub, nrhs);
     p.a.gx = (int)p.grid.x;
     p.block = dim3(blk);
-    p.nfin = (op == BLAS_CG_XR || op == BLAS_NORM || op == BLAS_AXMY_NORM) ? 1
-             : (op == BLAS_BI_XR || op == BLAS_NORM_DOT)                  ? 3
-                                                                          : 0;
+    p.nfin = (op == BLAS_CG_XR || op == BLAS_NORM || op == BLAS_AXMY_NORM)                       ? 1
+             : (op == BLAS_BI_XR || op == BLAS_NORM_DOT || op == BLAS_BL_ORTH || op == BLAS_BL_MR) ? 3
+             : op == BLAS_BL_GRAM                                                                 ? 5
+                                                                                                  : 0;
     p.slots = (int)p.grid.x;
     if (p.nfin && p.slots > a.r.capacity) return hipErrorInvalidValue;  // partials too small
     return hipSuccess;
@@ -205,6 +213,7 @@ hipError_t launch_finalize_batch(int N, const FinArgs* tab, int nsys, int nrhs, 
     if (N == 1) hipLaunchKernelGGL(k_finalize_batch<1>, g, b, 0, s, tab, nrhs);
     else if (N == 2) hipLaunchKernelGGL(k_finalize_batch<2>, g, b, 0, s, tab, nrhs);
     else if (N == 3) hipLaunchKernelGGL(k_finalize_batch<3>, g, b, 0, s, tab, nrhs);
+    else if (N == 5) hipLaunchKernelGGL(k_finalize_batch<5>, g, b, 0, s, tab, nrhs);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -217,6 +226,7 @@ hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, 
     if (N == 1) hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
     else if (N == 2) hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
     else if (N == 3) hipLaunchKernelGGL(k_finalize<3>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
+    else if (N == 5) hipLaunchKernelGGL(k_finalize<5>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -41,9 +41,12 @@ enum Pred {
     PRED_NO_UPDATE = 3,   // run only while no update is pending (and not done)
 };
 
+// Most values one reduction produces per block (BiCGStab(2)'s Gram step).
+constexpr int kMaxFin = 5;
+
 struct RedArgs {
     double* partials;       // [nrhs][nblocks][N]
-    int capacity;           // blocks the partials hold per right-hand side (N = 3)
+    int capacity;           // blocks the partials hold per right-hand side (N <= kMaxFin)
     int fin;                // Fin
 };
 
@@ -211,6 +214,16 @@ enum Blas {
     BLAS_MS_AXPY = 11,    // x += alpha p                          (alpha of each right-hand side's Ctl)
     BLAS_MS_P = 12,       // p = zeta z + beta p                   (zeta, beta of each Ctl)
     BLAS_AXMY_NORM = 13,  // z -= alpha w;                         red ||z||^2
+    // BiCGStab(2) (coefficients from each right-hand side's Ctl): y = u_0,
+    // z = r_0, w = u_1 or r_1, v = u_2, r_1 or r_2, r0 = u_2 or rt
+    BLAS_BL_U0 = 14,      // u_0 = r_0 - beta (u_0 - g1 u_1 - g2 u_2)         (y, z, w = u_1, v = u_2)
+    BLAS_BL_XR0 = 15,     // x += alpha u_0; r_0 -= alpha u_1                 (x, y, z, w = u_1)
+    BLAS_BL_U01 = 16,     // u_0 = r_0 - beta u_0; u_1 = r_1 - beta u_1       (y, z, w = u_1, v = r_1)
+    BLAS_BL_XR01 = 17,    // x += alpha u_0; r_0 -= alpha u_1; r_1 -= alpha u_2 (x, y, z, w = u_1, v = r_1, r0 = u_2)
+    BLAS_BL_GRAM = 18,    // red ||r_1||^2, <r_1, r_2>, <r_1, r_0>            (z, w = r_1, v = r_2)
+    BLAS_BL_ORTH = 19,    // r_2 -= tau r_1; red ||r_2||^2, <r_2, r_0>         (z, w = r_1, v = r_2)
+    BLAS_BL_MR = 20,      // x += g1 r_0 + g2 r_1; r_0 -= gp1 r_1 + gp2 r_2; red ||r_0||^2, <rt, r_0>
+                          //                                                  (x, z, w = r_1, v = r_2, r0 = rt)
 };
 
 struct BlasArgs {

@@ -14,7 +14,9 @@ namespace lqcd {
 template <int OP>
 struct BlasRed {
     static constexpr int N = (OP == BLAS_CG_XR || OP == BLAS_NORM || OP == BLAS_AXMY_NORM) ? 1
-                             : (OP == BLAS_BI_XR || OP == BLAS_NORM_DOT)                  ? 3
+                             : (OP == BLAS_BI_XR || OP == BLAS_NORM_DOT || OP == BLAS_BL_ORTH ||
+                                OP == BLAS_BL_MR)                                          ? 3
+                             : OP == BLAS_BL_GRAM                                          ? 5
                                                                                           : 0;
 };
 
@@ -174,6 +176,113 @@ __device__ __forceinline__ void blas_block(const BlasArgs& a, int bx, int nbx, i
 #pragma unroll
             for (int k = 0; k < NC; ++k) F::at(p, k) = ze * F::at(z, k) + be * F::at(p, k);
             F::store(P(a.y, a.st_y), S, h, p);
+        } else if (OP == BLAS_BL_U0) {
+            const cplx<R> be = cval<R>(ctl->bl_beta), g1 = cval<R>(ctl->bl_g1), g2 = cval<R>(ctl->bl_g2);
+            Vec u0, r0v, u1, u2;
+            F::load(P(a.y, a.st_y), S, h, u0);
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, u1);
+            F::load(P(a.v, a.st_v), S, h, u2);
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                F::at(u0, k) = F::at(r0v, k) - be * (F::at(u0, k) - g1 * F::at(u1, k) - g2 * F::at(u2, k));
+            F::store(P(a.y, a.st_y), S, h, u0);
+        } else if (OP == BLAS_BL_XR0) {
+            const cplx<R> al = cval<R>(ctl->balpha);
+            Vec x, u0, r0v, u1;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.y, a.st_y), S, h, u0);
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, u1);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                F::at(x, k) = F::at(x, k) + al * F::at(u0, k);
+                F::at(r0v, k) = F::at(r0v, k) - al * F::at(u1, k);
+            }
+            F::store(P(a.x, a.st_x), S, h, x);
+            F::store(P(a.z, a.st_z), S, h, r0v);
+        } else if (OP == BLAS_BL_U01) {
+            const cplx<R> be = cval<R>(ctl->bl_beta);
+            Vec u0, r0v, u1, r1;
+            F::load(P(a.y, a.st_y), S, h, u0);
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, u1);
+            F::load(P(a.v, a.st_v), S, h, r1);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                F::at(u0, k) = F::at(r0v, k) - be * F::at(u0, k);
+                F::at(u1, k) = F::at(r1, k) - be * F::at(u1, k);
+            }
+            F::store(P(a.y, a.st_y), S, h, u0);
+            F::store(P(a.w, a.st_w), S, h, u1);
+        } else if (OP == BLAS_BL_XR01) {
+            const cplx<R> al = cval<R>(ctl->balpha);
+            Vec x, u0, r0v, u1, r1, u2;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.y, a.st_y), S, h, u0);
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, u1);
+            F::load(P(a.v, a.st_v), S, h, r1);
+            F::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, u2);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                F::at(x, k) = F::at(x, k) + al * F::at(u0, k);
+                F::at(r0v, k) = F::at(r0v, k) - al * F::at(u1, k);
+                F::at(r1, k) = F::at(r1, k) - al * F::at(u2, k);
+            }
+            F::store(P(a.x, a.st_x), S, h, x);
+            F::store(P(a.z, a.st_z), S, h, r0v);
+            F::store(P(a.v, a.st_v), S, h, r1);
+        } else if (OP == BLAS_BL_GRAM) {
+            Vec r0v, r1, r2;
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, r1);
+            F::load(P(a.v, a.st_v), S, h, r2);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                red[0] += (double)norm2(F::at(r1, k));
+                const cplx<R> d12 = cmulc(F::at(r1, k), F::at(r2, k));
+                const cplx<R> d10 = cmulc(F::at(r1, k), F::at(r0v, k));
+                red[1] += (double)d12.x;
+                red[2] += (double)d12.y;
+                red[3] += (double)d10.x;
+                red[4] += (double)d10.y;
+            }
+        } else if (OP == BLAS_BL_ORTH) {
+            const cplx<R> ta = cval<R>(ctl->bl_tau);
+            Vec r0v, r1, r2;
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, r1);
+            F::load(P(a.v, a.st_v), S, h, r2);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                F::at(r2, k) = F::at(r2, k) - ta * F::at(r1, k);
+                red[0] += (double)norm2(F::at(r2, k));
+                const cplx<R> d = cmulc(F::at(r2, k), F::at(r0v, k));
+                red[1] += (double)d.x;
+                red[2] += (double)d.y;
+            }
+            F::store(P(a.v, a.st_v), S, h, r2);
+        } else if (OP == BLAS_BL_MR) {
+            const cplx<R> g1 = cval<R>(ctl->bl_g1), g2 = cval<R>(ctl->bl_g2);
+            const cplx<R> gp1 = cval<R>(ctl->bl_gp1), gp2 = cval<R>(ctl->bl_gp2);
+            Vec x, r0v, r1, r2, rt;
+            F::load(P(a.x, a.st_x), S, h, x);
+            F::load(P(a.z, a.st_z), S, h, r0v);
+            F::load(P(a.w, a.st_w), S, h, r1);
+            F::load(P(a.v, a.st_v), S, h, r2);
+            F::load(static_cast<const char*>(a.r0) + r64 * a.st_r0 + soff, S, h, rt);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                F::at(x, k) = F::at(x, k) + g1 * F::at(r0v, k) + g2 * F::at(r1, k);
+                F::at(r0v, k) = F::at(r0v, k) - gp1 * F::at(r1, k) - gp2 * F::at(r2, k);
+                red[0] += (double)norm2(F::at(r0v, k));
+                const cplx<R> d = cmulc(F::at(rt, k), F::at(r0v, k));
+                red[1] += (double)d.x;
+                red[2] += (double)d.y;
+            }
+            F::store(P(a.x, a.st_x), S, h, x);
+            F::store(P(a.z, a.st_z), S, h, r0v);
         } else if (OP == BLAS_AXMY_NORM) {
             // z -= alpha w ; red ||z||^2
             const R al = R(ctl->alpha);

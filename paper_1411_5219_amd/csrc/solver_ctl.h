@@ -7,7 +7,8 @@
 //     precision and FP64 reliable updates (Sleijpen and van der Vorst 1996,
 //     residual replacement), an outer defect correction, stagnation
 //     detection and a fall back from FP16 to FP32 storage;
-//   BiCGStab (van der Vorst 1992);
+//   BiCGStab (van der Vorst 1992) and BiCGStab(2) (Sleijpen and Fokkema
+//     1993, two BiCG steps and a minimal-residual polynomial of degree 2);
 //   the multi-shift CG (Jegerlehner 1996, shift added to the operator).
 // The paper names the inversion with Krylov methods as the dominant cost
 // (section 1) and standard inversion algorithms (section 3); the solvers
@@ -48,6 +49,14 @@ enum Fin {
     FIN_MS_INIT_KEEP = 16,// rr = ||r||^2, zeta = 1; bb and thresh already set
     FIN_MS_ALPHA = 17,    // alpha = rr / <p, A p>; zeta_{k+1}, alpha_i of every shift
     FIN_MS_BETA = 18,     // rr' = ||r||^2, beta, beta_i, zeta shift, per-shift convergence
+    // BiCGStab(2): one cycle is two BiCG steps (u_1 = A u_0, r_1 = A r_0,
+    // u_2 = A u_1, r_2 = A r_1) and the minimal residual over r_1, r_2
+    FIN_BL_INIT = 19,     // rr = ||r_0||^2, <rt, r_0>: rho0 = 1, alpha = 0, omega = 1, first cycle's beta
+    FIN_BL_ALPHA = 20,    // gamma = <rt, u_{j+1}>, alpha = rho0 / gamma
+    FIN_BL_BETA = 21,     // rho1 = <rt, r_1>, beta = alpha rho1 / rho0, rho0 = rho1
+    FIN_BL_TAU = 22,      // sigma1 = ||r_1||^2, tau = <r_1, r_2> / sigma1, gp1 = <r_1, r_0> / sigma1
+    FIN_BL_OMEGA = 23,    // sigma2 = ||r_2'||^2 (r_2' = r_2 - tau r_1), gp2 = <r_2', r_0> / sigma2: omega, g1, g2
+    FIN_BL_RES = 24,      // rr = ||r_0||^2, <rt, r_0>: convergence, next cycle's beta
 };
 
 // Status of a solve that handed control back to the host to continue at FP32
@@ -77,6 +86,12 @@ struct Ctl {
     // Mixed precision: FP64 ||r||^2 at the last reliable update and at the
     // start of the current outer (defect-correction) step, tol_inner^2.
     double rr_prev_upd, rr_outer, tol_inner2;
+    // BiCGStab(2) (rho0, rho1, alpha and omega in rho_old, rho, balpha and
+    // omega): beta, the Gram-Schmidt coefficient tau = <r_1, r_2> / ||r_1||^2,
+    // the projections gp1, gp2 of r_0 on r_1, r_2', and the polynomial
+    // coefficients g1, g2 in the basis r_1, r_2 (x += g1 r_0 + g2 r_1,
+    // r_0 -= g1 r_1 + g2 r_2, u_0 -= g1 u_1 + g2 u_2)
+    double bl_beta[2], bl_tau[2], bl_gp1[2], bl_gp2[2], bl_g1[2], bl_g2[2], bl_sigma1;
     int ms_index, ms_n, ms_base;
     int iter;         // completed iterations
     int done;         // 1 when converged (or failed): every kernel becomes a no-op
@@ -93,7 +108,7 @@ struct Ctl {
     int outer_req;    // the pending update ends an outer step (tol_inner reached)
     int nouter;       // outer steps ended by tol_inner
     int fallback_ok;  // the inner storage may fall back (FP16 inner)
-    int pad[1];
+    int bl_skip;      // BiCGStab(2): r_1 or r_2' vanished, the cycle takes no minimal-residual step
 };
 
 // Parameters of a control block at the start of a solve.
@@ -127,6 +142,14 @@ LQCD_HD inline void cdiv(const double* a, const double* b, double* out)
     const double d = b[0] * b[0] + b[1] * b[1];
     const double re = (a[0] * b[0] + a[1] * b[1]) / d;
     const double im = (a[1] * b[0] - a[0] * b[1]) / d;
+    out[0] = re;
+    out[1] = im;
+}
+
+LQCD_HD inline void cmul(const double* a, const double* b, double* out)
+{
+    const double re = a[0] * b[0] - a[1] * b[1];
+    const double im = a[0] * b[1] + a[1] * b[0];
     out[0] = re;
     out[1] = im;
 }
@@ -309,6 +332,96 @@ LQCD_HD inline void finalize_totals(int fin, Ctl* c, const double* v)
             break;
         }
         if (c->iter >= c->iter_limit) fail(c, LQCD_ENOCONV);
+        break;
+    case FIN_BL_INIT:
+    case FIN_BL_RES: {
+        c->rr = v[0];
+        if (fin == FIN_BL_INIT) {
+            c->rho_old[0] = 1.0;
+            c->rho_old[1] = 0.0;
+            c->balpha[0] = 0.0;
+            c->balpha[1] = 0.0;
+            c->omega[0] = 1.0;
+            c->omega[1] = 0.0;
+            c->bl_g1[0] = c->bl_g1[1] = c->bl_g2[0] = c->bl_g2[1] = 0.0;
+            c->bl_skip = 0;
+        } else {
+            c->iter += 2;
+        }
+        if (!finite(v[0]) || !finite(v[1]) || !finite(v[2])) { fail(c, LQCD_ENONFINITE); break; }
+        if (v[0] <= c->thresh) { c->done = 1; break; }
+        if (c->iter >= c->iter_limit) { fail(c, LQCD_ENOCONV); break; }
+        // next cycle: rho0 = -omega rho0, then its first BiCG step's beta
+        double r0n[2];
+        cmul(c->omega, c->rho_old, r0n);
+        r0n[0] = -r0n[0];
+        r0n[1] = -r0n[1];
+        if (r0n[0] == 0.0 && r0n[1] == 0.0) { fail(c, LQCD_EBREAKDOWN); break; }
+        c->rho[0] = v[1];
+        c->rho[1] = v[2];
+        double q[2];
+        cdiv(c->rho, r0n, q);
+        cmul(c->balpha, q, c->bl_beta);
+        c->rho_old[0] = v[1];
+        c->rho_old[1] = v[2];
+        break;
+    }
+    case FIN_BL_ALPHA: {
+        const double g[2] = {v[0], v[1]};
+        if (!finite(g[0]) || !finite(g[1])) { fail(c, LQCD_ENONFINITE); break; }
+        if (g[0] == 0.0 && g[1] == 0.0) { fail(c, LQCD_EBREAKDOWN); break; }
+        cdiv(c->rho_old, g, c->balpha);
+        break;
+    }
+    case FIN_BL_BETA: {
+        if (!finite(v[0]) || !finite(v[1])) { fail(c, LQCD_ENONFINITE); break; }
+        if (c->rho_old[0] == 0.0 && c->rho_old[1] == 0.0) { fail(c, LQCD_EBREAKDOWN); break; }
+        c->rho[0] = v[0];
+        c->rho[1] = v[1];
+        double q[2];
+        cdiv(c->rho, c->rho_old, q);
+        cmul(c->balpha, q, c->bl_beta);
+        c->rho_old[0] = v[0];
+        c->rho_old[1] = v[1];
+        break;
+    }
+    case FIN_BL_TAU:
+        for (int j = 0; j < 5; ++j)
+            if (!finite(v[j])) fail(c, LQCD_ENONFINITE);
+        if (c->done) break;
+        c->bl_sigma1 = v[0];
+        c->bl_skip = v[0] == 0.0;
+        if (c->bl_skip) {
+            c->bl_tau[0] = c->bl_tau[1] = c->bl_gp1[0] = c->bl_gp1[1] = 0.0;
+        } else {
+            c->bl_tau[0] = v[1] / v[0];
+            c->bl_tau[1] = v[2] / v[0];
+            c->bl_gp1[0] = v[3] / v[0];
+            c->bl_gp1[1] = v[4] / v[0];
+        }
+        break;
+    case FIN_BL_OMEGA:
+        if (!finite(v[0]) || !finite(v[1]) || !finite(v[2])) { fail(c, LQCD_ENONFINITE); break; }
+        if (c->bl_skip || v[0] == 0.0) {
+            // r_1 = 0 or r_2' = 0: the cycle ends without the minimal residual
+            // step (omega kept), as the published algorithm does
+            c->bl_skip = 1;
+            c->bl_gp1[0] = c->bl_gp1[1] = c->bl_gp2[0] = c->bl_gp2[1] = 0.0;
+            c->bl_g1[0] = c->bl_g1[1] = c->bl_g2[0] = c->bl_g2[1] = 0.0;
+            break;
+        }
+        c->bl_gp2[0] = v[1] / v[0];
+        c->bl_gp2[1] = v[2] / v[0];
+        c->bl_g2[0] = c->bl_gp2[0];
+        c->bl_g2[1] = c->bl_gp2[1];
+        c->omega[0] = c->bl_g2[0];
+        c->omega[1] = c->bl_g2[1];
+        {
+            double tg[2];
+            cmul(c->bl_tau, c->bl_g2, tg);
+            c->bl_g1[0] = c->bl_gp1[0] - tg[0];
+            c->bl_g1[1] = c->bl_gp1[1] - tg[1];
+        }
         break;
     case FIN_MS_INIT:
     case FIN_MS_INIT_KEEP: {

@@ -54,7 +54,8 @@ class SolveParams(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("inner_recon", ctypes.c_int32), ("nrhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("stag_window", ctypes.c_int32), ("tol_inner", ctypes.c_double),
-                ("max_stagnations", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("max_stagnations", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("bicgstab_ell", ctypes.c_int32)]
 
 
 class Launch(ctypes.Structure):
@@ -186,10 +187,10 @@ def op(kappa, mu=0.0, prec=64, recon=18) -> Op:
 
 def solve_params(tol=1e-10, maxiter=10000, eo=1, inner_prec=64, inner_recon=12, nrhs=1, use_graph=0,
                  delta_reliable=0.1, check_every=8, stag_window=0, tol_inner=0.0, max_stagnations=0,
-                 persistent=0) -> SolveParams:
+                 persistent=0, bicgstab_ell=0) -> SolveParams:
     return SolveParams(float(tol), int(maxiter), int(eo), int(inner_prec), int(inner_recon), int(nrhs),
                        int(use_graph), float(delta_reliable), int(check_every), int(stag_window), float(tol_inner),
-                       int(max_stagnations), int(persistent))
+                       int(max_stagnations), int(persistent), int(bicgstab_ell))
 
 
 def lqcd_last_error() -> str:

@@ -29,6 +29,13 @@ const Field kFields[] = {
     {"balpha_re", offsetof(Ctl, balpha), 0}, {"balpha_im", offsetof(Ctl, balpha) + 8, 0},
     {"omega_re", offsetof(Ctl, omega), 0}, {"omega_im", offsetof(Ctl, omega) + 8, 0},
     {"omega_step_re", offsetof(Ctl, omega_step), 0}, {"omega_step_im", offsetof(Ctl, omega_step) + 8, 0},
+    {"bl_beta_re", offsetof(Ctl, bl_beta), 0}, {"bl_beta_im", offsetof(Ctl, bl_beta) + 8, 0},
+    {"bl_tau_re", offsetof(Ctl, bl_tau), 0}, {"bl_tau_im", offsetof(Ctl, bl_tau) + 8, 0},
+    {"bl_gp1_re", offsetof(Ctl, bl_gp1), 0}, {"bl_gp1_im", offsetof(Ctl, bl_gp1) + 8, 0},
+    {"bl_gp2_re", offsetof(Ctl, bl_gp2), 0}, {"bl_gp2_im", offsetof(Ctl, bl_gp2) + 8, 0},
+    {"bl_g1_re", offsetof(Ctl, bl_g1), 0}, {"bl_g1_im", offsetof(Ctl, bl_g1) + 8, 0},
+    {"bl_g2_re", offsetof(Ctl, bl_g2), 0}, {"bl_g2_im", offsetof(Ctl, bl_g2) + 8, 0},
+    D(bl_sigma1), I(bl_skip),
     I(ms_index), I(ms_n), I(ms_base), I(iter), I(done), I(status), I(update), I(nupdates), I(iter_limit),
     I(lucky), I(last_upd_iter), I(stag_window), I(max_stag), I(nstag), I(reset_p), I(outer_req), I(nouter),
     I(fallback_ok),
@@ -82,6 +89,14 @@ void ctl_fin(void* buf, int idx, int fin, double v0, double v1, double v2)
     lqcd::finalize_totals(fin, static_cast<Ctl*>(buf) + idx, v);
 }
 
+// Up to six totals (the five of BiCGStab(2)'s Gram step).
+void ctl_fin_v(void* buf, int idx, int fin, const double* vals, int n)
+{
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < n && j < 6; ++j) v[j] = vals[j];
+    lqcd::finalize_totals(fin, static_cast<Ctl*>(buf) + idx, v);
+}
+
 // Field by name (NaN-free doubles; ints widened); returns -1e300 for an unknown name.
 double ctl_get(const void* buf, int idx, const char* name)
 {
@@ -123,7 +138,9 @@ int ctl_fin_code(const char* name)
              {"BI_INIT", lqcd::FIN_BI_INIT},   {"RU_RR", lqcd::FIN_RU_RR},       {"BB_E", lqcd::FIN_BB_E},
              {"BB", lqcd::FIN_BB},             {"BB_FULL", lqcd::FIN_BB_FULL},   {"RR_INIT", lqcd::FIN_RR_INIT},
              {"MS_INIT", lqcd::FIN_MS_INIT},   {"MS_INIT_KEEP", lqcd::FIN_MS_INIT_KEEP},
-             {"MS_ALPHA", lqcd::FIN_MS_ALPHA}, {"MS_BETA", lqcd::FIN_MS_BETA}};
+             {"MS_ALPHA", lqcd::FIN_MS_ALPHA}, {"MS_BETA", lqcd::FIN_MS_BETA},
+             {"BL_INIT", lqcd::FIN_BL_INIT},   {"BL_ALPHA", lqcd::FIN_BL_ALPHA}, {"BL_BETA", lqcd::FIN_BL_BETA},
+             {"BL_TAU", lqcd::FIN_BL_TAU},     {"BL_OMEGA", lqcd::FIN_BL_OMEGA}, {"BL_RES", lqcd::FIN_BL_RES}};
     for (auto& e : t)
         if (std::strcmp(e.n, name) == 0) return e.v;
     return -1;

@@ -92,6 +92,26 @@ def test_workspace_grows_with_rhs_and_mixed():
     assert b > 3 * a > 0 and c > 0
 
 
+def test_bicgstab_ell_parameter():
+    """params.bicgstab_ell: 0, 1 or 2 (anything else EINVAL before any device
+    work); with 2 the workspace holds BiCGStab(2)'s 9 FP64 vectors per
+    right-hand side against BiCGStab's 8 (even-odd)."""
+    from paper_1411_5219_amd import lqcd as L
+    g = L.geom((8, 8, 8, 8))
+    o = L.op(0.16, 0.005)
+    for bad in (-1, 3):
+        with pytest.raises(L.LqcdError) as e:
+            L.lqcd_workspace_bytes(g, o, L.solve_params(bicgstab_ell=bad))
+        assert e.value.code == L.EINVAL
+    pb = 8 * 8 * 8 * 8 // 2 * 24 * 8            # one parity field, without the layout's padding sites
+    w0 = L.lqcd_workspace_bytes(g, o, L.solve_params(nrhs=2))
+    w2 = L.lqcd_workspace_bytes(g, o, L.solve_params(nrhs=2, bicgstab_ell=2))
+    assert 2 * pb <= w2 - w0 <= 2 * pb * 1.1
+    with pytest.raises(L.LqcdError) as e:
+        L.bicgstab_solve(g, o, 16, 32, 48, L.solve_params(bicgstab_ell=2, inner_prec=32), 64, stream=0)
+    assert e.value.code == L.EUNSUPPORTED
+
+
 def test_batch_workspace_query_validates():
     from paper_1411_5219_amd import lqcd as L
     g = [L.geom((4, 4, 4, 4)), L.geom((6, 6, 6, 4))]

@@ -31,6 +31,8 @@ def run_solve(mods, L4, theta, U, b, kappa, mu, method="cg", nrhs=1, stream=None
     torch, fields, lqcd = mods
     lat = fields.Lattice(L4, theta)
     o = lqcd.op(kappa, mu, 64, outer_recon)
+    if method == "bicgstab2":
+        kw = dict(kw, bicgstab_ell=2)
     p = lqcd.solve_params(nrhs=nrhs, **kw)
     Ud = lat.gauge(U, 64, outer_recon)
     bd = lat.spinor(b)
@@ -46,7 +48,7 @@ def true_res(U, x, b, L4, theta, kappa, mu):
     return W.true_residual(U, x, b, L4, theta, kappa, mu)
 
 
-@pytest.mark.parametrize("method", ["cg", "bicgstab"])
+@pytest.mark.parametrize("method", ["cg", "bicgstab", "bicgstab2"])
 @pytest.mark.parametrize("eo", [0, 1])
 def test_config0_like_4x4x4x4(mods, method, eo):
     """Plain Wilson, Haar links, kappa = 0.12, full tolerance 1e-12."""
@@ -67,7 +69,7 @@ def test_dense_lu_2x2x2x2(mods):
     U = gauge_field(L4, "haar", seed=7)
     b = gaussian_spinor(L4, seed=8)
     x_ref = np.linalg.solve(W.dense_M(U, L4, theta, kappa, mu), b.ravel()).reshape(b.shape)
-    for method in ["cg", "bicgstab"]:
+    for method in ["cg", "bicgstab", "bicgstab2"]:
         rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, method, tol=1e-13, maxiter=500)
         assert rc == 0
         assert np.linalg.norm((x - x_ref).ravel()) / np.linalg.norm(x_ref.ravel()) < 1e-11
@@ -130,6 +132,69 @@ def test_bicgstab_twisted_eo(mods, use_graph):
     x_ref, ref_info = S.solve(U, b, L4, theta, kappa, mu, tol=1e-12, method="cgnr", eo=True)
     assert ref_info.status == 0
     assert np.linalg.norm((x - x_ref).ravel()) / np.linalg.norm(x_ref.ravel()) <= 2e-9
+
+
+@pytest.mark.parametrize("eo", [0, 1])
+def test_bicgstab2_iterates_match_oracle(mods, eo):
+    """BiCGStab(2) stopped after k BiCG steps (ENOCONV) returns the oracle's
+    BiCGStab(ell = 2) iterate after the same steps (then reconstructed, with
+    eo): the device's fused launch sequence takes the published algorithm's
+    steps.  Twisted mass and twisted boundaries on 4^4, where rounding is
+    not amplified over a few cycles."""
+    L4, theta, kappa, mu = (4, 4, 4, 4), (0.3, 0, 0, math.pi), 0.12, 0.05
+    U = gauge_field(L4, "haar", seed=1002)
+    b = gaussian_spinor(L4, seed=2002)
+    for k in (2, 4, 8):
+        print(f"\n[case] 4^4 bicgstab2 eo={eo} after {k} steps", flush=True)
+        rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "bicgstab2", tol=1e-14, maxiter=k, eo=eo)
+        x_ref, ref = S.solve(U, b, L4, theta, kappa, mu, tol=1e-14, maxiter=k, method="bicgstab_l", eo=bool(eo),
+                             ell=2)
+        assert ref.status == S.ENOCONV and ref.iters == k
+        assert info[0]["status"] == S.ENOCONV and info[0]["iters"] == k
+        err = np.linalg.norm((x - x_ref).ravel()) / np.linalg.norm(x_ref.ravel())
+        print(f"  rel diff {err:.2e}", flush=True)
+        assert err < 1e-12
+        # x agrees to 1e-12 relative, so the residuals agree to about ||M|| times that
+        assert abs(info[0]["true_resid"] - ref.true_resid) <= 1e-11
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_bicgstab2_twisted_eo(mods, use_graph):
+    """BiCGStab(2) at the production parameters on 8^3 x 4 (where BiCGStab
+    needs 398 iterations): certified by the oracle's M and within 2e-9 of the
+    oracle's CGNR solution (the bound of the BiCGStab test)."""
+    torch = mods[0]
+    L4, theta, kappa, mu = (8, 8, 8, 4), (0, 0, 0, math.pi), 0.16, 0.005
+    U = gauge_field(L4, "exp", eps=0.4, seed=1001)
+    b = gaussian_spinor(L4, seed=2001)
+    print(f"\n[case] 8^3x4 tm bicgstab2 graph={use_graph}", flush=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "bicgstab2", tol=1e-10, maxiter=20000,
+                                stream=s, use_graph=use_graph)
+    print(f"  rc={rc} iters={info[0]['iters']} restarts={info[0]['restarts']}", flush=True)
+    assert rc == 0, info
+    tr = true_res(U, x, b, L4, theta, kappa, mu)
+    assert tr <= 1e-10 and abs(tr - info[0]["true_resid"]) <= 1e-13
+    x_ref, ref_info = S.solve(U, b, L4, theta, kappa, mu, tol=1e-12, method="cgnr", eo=True)
+    assert ref_info.status == 0
+    assert np.linalg.norm((x - x_ref).ravel()) / np.linalg.norm(x_ref.ravel()) <= 2e-9
+
+
+def test_bicgstab2_multi_rhs(mods):
+    """Three right-hand sides (a point source and two Gaussians) solved
+    together by BiCGStab(2): each has its own scalars and stops on its own;
+    each solution is certified by the oracle's M."""
+    L4, theta, kappa, mu = (8, 8, 8, 4), (0, 0, 0, math.pi), 0.16, 0.005
+    U = gauge_field(L4, "exp", eps=0.4, seed=1003)
+    b = np.concatenate([point_source(L4, 1, 2)[None], gaussian_spinor(L4, seed=2003, nrhs=2)])
+    print("\n[case] 8^3x4 tm bicgstab2 nrhs=3", flush=True)
+    rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "bicgstab2", nrhs=3, tol=1e-10, maxiter=20000)
+    print(f"  rc={rc} iters={[i['iters'] for i in info]}", flush=True)
+    assert rc == 0, info
+    for i in range(3):
+        tr = true_res(U, x[i], b[i], L4, theta, kappa, mu)
+        assert tr <= 1e-10 and abs(tr - info[i]["true_resid"]) <= 1e-13
 
 
 def test_multi_rhs_point_and_gaussian(mods):
@@ -227,6 +292,31 @@ def test_config1_bicgstab_reports_what_it_reached(mods):
     assert np.all(np.isfinite(x))
     assert rc == info[0]["status"]
     assert abs(tr - info[0]["true_resid"]) <= 1e-12 * max(1.0, tr)
+    if rc == 0:
+        assert tr <= 1e-10
+    else:
+        assert rc in (lqcd.ENOCONV, lqcd.EBREAKDOWN) and tr > 1e-10
+
+
+def test_config1_bicgstab2(mods):
+    """BiCGStab(2) on the 24^3 x 8 system where BiCGStab stalls: whatever it
+    stops with is reported truthfully (a converged status only with a
+    certified x, otherwise ENOCONV or EBREAKDOWN with info.true_resid equal
+    to the oracle's true residual of the returned x), and it must get below
+    1e-6 within 3000 BiCG steps (the oracle's BiCGStab(2) is at 3e-7 after
+    2200, BiCGStab stalls near 2e-2)."""
+    torch, fields, lqcd = mods
+    L4, theta, kappa, mu = (24, 24, 24, 8), (0, 0, 0, math.pi), 0.16, 0.005
+    U = gauge_field(L4, "exp", eps=0.4, seed=1001)
+    b = gaussian_spinor(L4, seed=2001)
+    print("\n[case] 24^3x8 fp64 eo bicgstab2, 3000 steps", flush=True)
+    rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "bicgstab2", tol=1e-10, maxiter=3000)
+    tr = true_res(U, x, b, L4, theta, kappa, mu)
+    print(f"  rc={rc} iters={info[0]['iters']} t={info[0]['seconds']:.3f}s true={tr:.2e}", flush=True)
+    assert np.all(np.isfinite(x))
+    assert rc == info[0]["status"]
+    assert abs(tr - info[0]["true_resid"]) <= 1e-12 * max(1.0, tr)
+    assert tr < 1e-6
     if rc == 0:
         assert tr <= 1e-10
     else:

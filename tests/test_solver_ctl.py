@@ -50,6 +50,8 @@ def H(tmp_path_factory):
     lib.ctl_get.restype = ctypes.c_double
     lib.ctl_set.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_double]
     lib.ctl_fin_code.argtypes = [ctypes.c_char_p]
+    lib.ctl_fin_v.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_int]
     return lib
 
 
@@ -67,6 +69,12 @@ class Ctl:
         code = self.lib.ctl_fin_code(name.encode())
         assert code >= 0, name
         self.lib.ctl_fin(self.buf, idx, code, float(v0), float(v1), float(v2))
+
+    def fin_v(self, name, *vals, idx=0):
+        code = self.lib.ctl_fin_code(name.encode())
+        assert code >= 0, name
+        arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+        self.lib.ctl_fin_v(self.buf, idx, code, arr, len(vals))
 
     def __getitem__(self, name):
         return self.get(name)
@@ -240,6 +248,179 @@ def test_bicgstab_breakdowns(H):
     c.fin("BI_OMEGA", 1.0, 0.0, 0.0)
     c.fin("BI_RHO", 1e-22, 0.0, 0.0)
     assert c["status"] == 0 and c["done"] == 1
+
+
+def bicgstab2_by_ctl(H, A, b, tol, maxiter=1000):
+    """The library's BiCGStab(2) launch sequence: start r_0 = b - A x,
+    rt = r_0 (FIN_BL_INIT), u_0 = u_1 = u_2 = 0; cycle u_0 = r_0 - beta (u_0 -
+    g1 u_1 - g2 u_2), u_1 = A u_0 (FIN_BL_ALPHA), x += alpha u_0, r_0 -= alpha
+    u_1, r_1 = A r_0 (FIN_BL_BETA), u_0 = r_0 - beta u_0, u_1 = r_1 - beta u_1,
+    u_2 = A u_1 (FIN_BL_ALPHA), x += alpha u_0, r_0 -= alpha u_1, r_1 -= alpha
+    u_2, r_2 = A r_1, Gram totals (FIN_BL_TAU), r_2 -= tau r_1 (FIN_BL_OMEGA),
+    x += g1 r_0 + g2 r_1, r_0 -= gp1 r_1 + gp2 r_2 (FIN_BL_RES)."""
+    c = Ctl(H, tol=tol, iter_limit=maxiter)
+    c.fin("BB_FULL", nrm2(b))
+    x = np.zeros_like(b)
+    r0 = b - A @ x
+    rt = r0.copy()
+    d = np.vdot(rt, r0)
+    c.fin("BL_INIT", nrm2(r0), d.real, d.imag)
+    u0, u1, u2 = (np.zeros_like(b) for _ in range(3))
+    while not c["done"]:
+        be, g1, g2 = c.cplx("bl_beta"), c.cplx("bl_g1"), c.cplx("bl_g2")
+        u0 = r0 - be * (u0 - g1 * u1 - g2 * u2)
+        u1 = A @ u0
+        d = np.vdot(rt, u1)
+        c.fin("BL_ALPHA", d.real, d.imag)
+        if c["done"]:
+            break
+        al = c.cplx("balpha")
+        x = x + al * u0
+        r0 = r0 - al * u1
+        r1 = A @ r0
+        d = np.vdot(rt, r1)
+        c.fin("BL_BETA", d.real, d.imag)
+        if c["done"]:
+            break
+        be = c.cplx("bl_beta")
+        u0 = r0 - be * u0
+        u1 = r1 - be * u1
+        u2 = A @ u1
+        d = np.vdot(rt, u2)
+        c.fin("BL_ALPHA", d.real, d.imag)
+        if c["done"]:
+            break
+        al = c.cplx("balpha")
+        x = x + al * u0
+        r0 = r0 - al * u1
+        r1 = r1 - al * u2
+        r2 = A @ r1
+        d12, d10 = np.vdot(r1, r2), np.vdot(r1, r0)
+        c.fin_v("BL_TAU", nrm2(r1), d12.real, d12.imag, d10.real, d10.imag)
+        if c["done"]:
+            break
+        r2 = r2 - c.cplx("bl_tau") * r1
+        d = np.vdot(r2, r0)
+        c.fin("BL_OMEGA", nrm2(r2), d.real, d.imag)
+        if c["done"]:
+            break
+        g1, g2, gp1, gp2 = (c.cplx(n) for n in ("bl_g1", "bl_g2", "bl_gp1", "bl_gp2"))
+        x = x + g1 * r0 + g2 * r1
+        r0 = r0 - gp1 * r1 - gp2 * r2
+        d = np.vdot(rt, r0)
+        c.fin("BL_RES", nrm2(r0), d.real, d.imag)
+    return x, c
+
+
+@pytest.mark.parametrize("n,seed,shift", [(24, 2, 0.0), (40, 5, -2.0)])
+def test_bicgstab2_sequence_matches_oracle(H, n, seed, shift):
+    """The fused launch sequence (the polynomial step's u_0 update folded into
+    the next cycle) against the oracle's BiCGStab(ell = 2): the same BiCG step
+    count and the same solution to rounding."""
+    A, b = dense_system(n, seed, shift=shift)
+    x, c = bicgstab2_by_ctl(H, A, b, 1e-12)
+    assert c["status"] == 0
+    xo, info = S.bicgstab_l(lambda v: A @ v, b, 1e-12, 1000, ell=2)
+    assert info.status == 0 and int(c["iter"]) == info.iters
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-12
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-12
+
+
+def test_bicgstab2_sequence_first_cycles_near_singular(H):
+    """On a shifted system whose spectrum reaches within 0.012 of the origin
+    the iteration amplifies rounding (a 1e-15 change of b moves the oracle's
+    own iterate by 4e-8 after 10 steps), so only the first cycles are compared,
+    each within a few times that self-sensitivity."""
+    A, b = dense_system(40, 5, shift=-3.0)
+    for k, bound in ((2, 1e-14), (4, 1e-13), (6, 1e-10)):
+        x, c = bicgstab2_by_ctl(H, A, b, 1e-30, maxiter=k)
+        xo, info = S.bicgstab_l(lambda v: A @ v, b, 1e-30, k, ell=2)
+        assert c["status"] == info.status == ENOCONV and int(c["iter"]) == info.iters == k
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < bound, k
+
+
+def test_bicgstab2_first_cycle_scalars(H):
+    """FIN_BL_INIT and the first BiCG step by hand: beta = 0 in the first
+    cycle (alpha = 0), alpha = rho / gamma, beta = alpha rho1 / rho0."""
+    c = Ctl(H, tol=1e-10)
+    c.fin("BB_FULL", 1.0)
+    c.fin("BL_INIT", 1.0, 0.8, 0.2)
+    assert c.cplx("bl_beta") == 0 and c.cplx("rho_old") == complex(0.8, 0.2)
+    assert c.cplx("bl_g1") == 0 and c.cplx("bl_g2") == 0 and c["done"] == 0
+    c.fin("BL_ALPHA", 0.4, -0.2)
+    al = complex(0.8, 0.2) / complex(0.4, -0.2)
+    assert abs(c.cplx("balpha") - al) < 1e-15
+    c.fin("BL_BETA", 0.3, 0.1)
+    assert abs(c.cplx("bl_beta") - al * complex(0.3, 0.1) / complex(0.8, 0.2)) < 1e-15
+    assert c.cplx("rho_old") == complex(0.3, 0.1)
+    c.fin("BL_ALPHA", 0.5, 0.0)
+    c.fin_v("BL_TAU", 2.0, 0.4, 0.2, 1.0, -0.6)
+    assert c.cplx("bl_tau") == complex(0.2, 0.1) and c.cplx("bl_gp1") == complex(0.5, -0.3)
+    c.fin("BL_OMEGA", 4.0, 1.0, 2.0)
+    assert c.cplx("bl_gp2") == complex(0.25, 0.5) and c.cplx("omega") == complex(0.25, 0.5)
+    assert abs(c.cplx("bl_g1") - (complex(0.5, -0.3) - complex(0.2, 0.1) * complex(0.25, 0.5))) < 1e-15
+    c.fin("BL_RES", 0.5, 0.1, 0.0)
+    assert c["iter"] == 2 and c["done"] == 0
+    # next cycle: rho0 = -omega rho0, beta = alpha rho1 / rho0
+    rho0 = -complex(0.25, 0.5) * complex(0.3, 0.1)
+    assert abs(c.cplx("bl_beta") - c.cplx("balpha") * complex(0.1, 0.0) / rho0) < 1e-15
+
+
+def test_bicgstab2_degenerate_cycles(H):
+    """r_1 = 0 or r_2' = 0 ends the cycle without the polynomial step
+    (omega kept, g = 0); gamma = 0 and omega = 0 are breakdowns; a NaN total
+    is reported; convergence wins over a breakdown."""
+    def cycle(c, tau_totals, omega_totals):
+        c.fin("BL_ALPHA", 1.0, 0.0)
+        c.fin("BL_BETA", 0.5, 0.0)
+        c.fin("BL_ALPHA", 1.0, 0.0)
+        c.fin_v("BL_TAU", *tau_totals)
+        c.fin("BL_OMEGA", *omega_totals)
+
+    for tau_totals, omega_totals in [((0.0, 0.0, 0.0, 0.0, 0.0), (1.0, 0.5, 0.0)),
+                                     ((1.0, 0.2, 0.0, 0.3, 0.0), (0.0, 0.0, 0.0))]:
+        c = Ctl(H, tol=1e-10)
+        c.fin("BB_FULL", 1.0)
+        c.fin("BL_INIT", 1.0, 1.0, 0.0)
+        cycle(c, tau_totals, omega_totals)
+        assert c["bl_skip"] == 1 and c["status"] == 0
+        assert c.cplx("omega") == 1.0 and c.cplx("bl_g1") == 0 and c.cplx("bl_g2") == 0
+        assert c.cplx("bl_gp1") == 0 and c.cplx("bl_gp2") == 0
+        c.fin("BL_RES", 0.5, 0.2, 0.0)
+        assert c["done"] == 0 and c["iter"] == 2
+        cycle(c, (1.0, 0.2, 0.0, 0.3, 0.0), (2.0, 1.0, 0.0))     # an ordinary cycle clears the skip
+        assert c["bl_skip"] == 0 and c.cplx("omega") == 0.5
+    c = Ctl(H, tol=1e-10)
+    c.fin("BB_FULL", 1.0)
+    c.fin("BL_INIT", 1.0, 1.0, 0.0)
+    c.fin("BL_ALPHA", 0.0, 0.0)                                  # gamma = <rt, u_1> = 0
+    assert c["status"] == EBREAKDOWN and c["done"] == 1
+    c = Ctl(H, tol=1e-10)
+    c.fin("BB_FULL", 1.0)
+    c.fin("BL_INIT", 1.0, 1.0, 0.0)
+    cycle(c, (1.0, 0.2, 0.0, 0.3, 0.0), (2.0, 0.0, 0.0))         # omega = gp2 = 0
+    c.fin("BL_RES", 0.5, 0.2, 0.0)
+    assert c["status"] == EBREAKDOWN
+    c = Ctl(H, tol=1e-10)
+    c.fin("BB_FULL", 1.0)
+    c.fin("BL_INIT", 1.0, 1.0, 0.0)
+    cycle(c, (1.0, 0.2, 0.0, 0.3, 0.0), (2.0, 0.0, 0.0))
+    c.fin("BL_RES", 1e-22, 0.0, 0.0)
+    assert c["status"] == 0 and c["done"] == 1
+    c = Ctl(H, tol=1e-10)
+    c.fin("BB_FULL", 1.0)
+    c.fin("BL_INIT", 1.0, 1.0, 0.0)
+    c.fin("BL_ALPHA", 1.0, 0.0)
+    c.fin("BL_BETA", 0.5, 0.0)
+    c.fin("BL_ALPHA", 1.0, 0.0)
+    c.fin_v("BL_TAU", 1.0, 0.2, 0.0, float("nan"), 0.0)
+    assert c["status"] == ENONFINITE and c["done"] == 1
+    c = Ctl(H, tol=1e-10, iter_limit=2)
+    c.fin("BB_FULL", 1.0)
+    c.fin("BL_INIT", 1.0, 1.0, 0.0)
+    cycle(c, (1.0, 0.2, 0.0, 0.3, 0.0), (2.0, 1.0, 0.0))
+    c.fin("BL_RES", 0.5, 0.2, 0.0)
+    assert c["status"] == ENOCONV and c["iter"] == 2
 
 
 def test_multishift_sequence_matches_oracle(H):
