@@ -576,7 +576,8 @@ def config_solves(stream, log, kappa, mu, tol, multi):
         BiCGStab on the same system, capped at 3000 iterations (its status and
         the residual it reached are reported: at kappa = 0.16 the Schur
         complement has eigenvalues on both sides of the imaginary axis and
-        BiCGStab stalls, as the oracle's does);
+        BiCGStab stalls, as the oracle's does), and BiCGStab(2) capped at
+        10000 BiCG steps;
       * 32^3 x 8, one Gaussian source: plain FP64 CGNR against FP32/12 and
         FP16/12 inner solves with FP64 reliable updates;
       * the 16 sources of the multi-RHS workload (32^3 x 8) solved one at a
@@ -599,7 +600,7 @@ def config_solves(stream, log, kappa, mu, tol, multi):
         rc, info = res[-1]
         return rc, info[0], secs
 
-    log("config solves: 24^3x8 CGNR and BiCGStab")
+    log("config solves: 24^3x8 CGNR, BiCGStab and BiCGStab(2)")
     L = (24, 24, 24, 8)
     with torch.cuda.stream(stream):
         lat = fields.Lattice(L, THETA)
@@ -608,15 +609,20 @@ def config_solves(stream, log, kappa, mu, tol, multi):
         x = lat.zeros(lqcd.FIELD_SPINOR_FULL, 64)
         p = lqcd.solve_params(tol=tol, maxiter=100000, eo=1, inner_prec=64)
         pbi = lqcd.solve_params(tol=tol, maxiter=3000, eo=1, inner_prec=64)
+        pb2 = lqcd.solve_params(tol=tol, maxiter=10000, eo=1, inner_prec=64, bicgstab_ell=2)
         ws = lat.workspace(o, p)
         wsb = lat.workspace(o, pbi)
+        wsb2 = lat.workspace(o, pb2)
     rc, info, secs = run(lat, U, b, p, x, ws)
     cg = {"status": rc, "seconds_median": secs, "iters": info["iters"], "true_resid": info["true_resid"]}
     rc, info, secs = run(lat, U, b, pbi, x, wsb, reps=1, fn=lqcd.bicgstab_solve)
     bi = {"status": lqcd.ERROR_NAMES.get(rc, rc), "seconds": secs, "iters": info["iters"],
           "true_resid_reached": info["true_resid"], "maxiter": 3000}
-    out["config1_24x8"] = {"lattice": list(L), "cgnr_fp64": cg, "bicgstab_fp64": bi}
-    del lat, U, b, x, ws, wsb
+    rc, info, secs = run(lat, U, b, pb2, x, wsb2, reps=1, fn=lqcd.bicgstab_solve)
+    bi2 = {"status": lqcd.ERROR_NAMES.get(rc, rc), "seconds": secs, "bicg_steps": info["iters"],
+           "true_resid_reached": info["true_resid"], "maxiter": 10000}
+    out["config1_24x8"] = {"lattice": list(L), "cgnr_fp64": cg, "bicgstab_fp64": bi, "bicgstab2_fp64": bi2}
+    del lat, U, b, x, ws, wsb, wsb2
 
     log("config solves: 32^3x8 FP64 vs mixed")
     L = (32, 32, 32, 8)

@@ -212,6 +212,33 @@ def test_multi_rhs_point_and_gaussian(mods):
         assert true_res(U, x[k], b[k], L4, theta, kappa, mu) <= 1e-10, k
 
 
+@pytest.mark.parametrize("nrhs", [2, 3, 5])
+@pytest.mark.parametrize("inner", [(32, 12), (16, 12)])
+def test_interleaved_inner_fields(mods, nrhs, inner):
+    """Mixed solves of several right-hand sides keep their inner fields with
+    the right-hand sides interleaved site by site (the next power of two of
+    slots, so nrhs = 3 and 5 leave idle slots): every solution certified by
+    the oracle's M, and a graph-replayed solve equal to the direct one."""
+    torch = mods[0]
+    L4, theta, kappa, mu = (6, 6, 6, 4), (0.2, 0, 0, math.pi), 0.155, 0.01
+    U = gauge_field(L4, "exp", eps=0.4, seed=1010 + nrhs)
+    b = np.concatenate([point_source(L4, 2, 1)[None], gaussian_spinor(L4, seed=2010 + nrhs, nrhs=nrhs - 1)])
+    print(f"\n[case] 6^3x4 interleaved inner nrhs={nrhs} inner={inner}", flush=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "cg", nrhs=nrhs, tol=1e-10, maxiter=20000,
+                                inner_prec=inner[0], inner_recon=inner[1], stream=s)
+        rcg, infog, xg = run_solve(mods, L4, theta, U, b, kappa, mu, "cg", nrhs=nrhs, tol=1e-10, maxiter=20000,
+                                   inner_prec=inner[0], inner_recon=inner[1], stream=s, use_graph=1)
+    print(f"  rc={rc} iters={[i['iters'] for i in info]}", flush=True)
+    assert rc == 0 and rcg == 0, info
+    for k in range(nrhs):
+        tr = true_res(U, x[k], b[k], L4, theta, kappa, mu)
+        assert tr <= 1e-10 and abs(tr - info[k]["true_resid"]) <= 1e-13, k
+    assert [i["iters"] for i in info] == [i["iters"] for i in infog]
+    assert np.array_equal(x, xg)
+
+
 def test_multi_rhs_matches_single(mods):
     L4, theta, kappa, mu = (4, 4, 4, 4), (0, 0, 0, math.pi), 0.16, 0.005
     U = gauge_field(L4, "exp", eps=0.4, seed=1)
@@ -299,28 +326,18 @@ def test_config1_bicgstab_reports_what_it_reached(mods):
 
 
 def test_config1_bicgstab2(mods):
-    """BiCGStab(2) on the 24^3 x 8 system where BiCGStab stalls: whatever it
-    stops with is reported truthfully (a converged status only with a
-    certified x, otherwise ENOCONV or EBREAKDOWN with info.true_resid equal
-    to the oracle's true residual of the returned x), and it must get below
-    1e-6 within 3000 BiCG steps (the oracle's BiCGStab(2) is at 3e-7 after
-    2200, BiCGStab stalls near 2e-2)."""
-    torch, fields, lqcd = mods
+    """BiCGStab(2) on the 24^3 x 8 system where BiCGStab stalls (near 2e-2)
+    must converge to 1e-10 within 10000 BiCG steps (about 4600 are needed),
+    certified by the oracle's M."""
     L4, theta, kappa, mu = (24, 24, 24, 8), (0, 0, 0, math.pi), 0.16, 0.005
     U = gauge_field(L4, "exp", eps=0.4, seed=1001)
     b = gaussian_spinor(L4, seed=2001)
-    print("\n[case] 24^3x8 fp64 eo bicgstab2, 3000 steps", flush=True)
-    rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "bicgstab2", tol=1e-10, maxiter=3000)
+    print("\n[case] 24^3x8 fp64 eo bicgstab2, 10000 steps", flush=True)
+    rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "bicgstab2", tol=1e-10, maxiter=10000)
     tr = true_res(U, x, b, L4, theta, kappa, mu)
     print(f"  rc={rc} iters={info[0]['iters']} t={info[0]['seconds']:.3f}s true={tr:.2e}", flush=True)
-    assert np.all(np.isfinite(x))
-    assert rc == info[0]["status"]
-    assert abs(tr - info[0]["true_resid"]) <= 1e-12 * max(1.0, tr)
-    assert tr < 1e-6
-    if rc == 0:
-        assert tr <= 1e-10
-    else:
-        assert rc in (lqcd.ENOCONV, lqcd.EBREAKDOWN) and tr > 1e-10
+    assert rc == 0, info
+    assert tr <= 1e-10 and abs(tr - info[0]["true_resid"]) <= 1e-13
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
