@@ -214,16 +214,16 @@ def test_multi_rhs_point_and_gaussian(mods):
 
 @pytest.mark.parametrize("nrhs", [2, 3, 5])
 @pytest.mark.parametrize("inner", [(32, 12), (16, 12)])
-def test_interleaved_inner_fields(mods, nrhs, inner):
-    """Mixed solves of several right-hand sides keep their inner fields with
-    the right-hand sides interleaved site by site (the next power of two of
-    slots, so nrhs = 3 and 5 leave idle slots): every solution certified by
-    the oracle's M, and a graph-replayed solve equal to the direct one."""
+def test_mixed_several_rhs_counts(mods, nrhs, inner):
+    """Mixed solves of 2, 3 and 5 right-hand sides (tiles of the inner
+    Dslash partly filled for 3 and 5) at FP32 and FP16 inner storage: every
+    solution certified by the oracle's M, and a graph-replayed solve equal to
+    the direct one."""
     torch = mods[0]
     L4, theta, kappa, mu = (6, 6, 6, 4), (0.2, 0, 0, math.pi), 0.155, 0.01
     U = gauge_field(L4, "exp", eps=0.4, seed=1010 + nrhs)
     b = np.concatenate([point_source(L4, 2, 1)[None], gaussian_spinor(L4, seed=2010 + nrhs, nrhs=nrhs - 1)])
-    print(f"\n[case] 6^3x4 interleaved inner nrhs={nrhs} inner={inner}", flush=True)
+    print(f"\n[case] 6^3x4 mixed nrhs={nrhs} inner={inner}", flush=True)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         rc, info, x = run_solve(mods, L4, theta, U, b, kappa, mu, "cg", nrhs=nrhs, tol=1e-10, maxiter=20000,
