@@ -286,6 +286,33 @@ def test_edge_cases(mods):
     assert 0 < true_res(U, x, b, L4, theta, 0.12, 0.0) < 1
 
 
+@pytest.mark.parametrize("method", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("eo", [0, 1])
+def test_edge_cases_bicgstab(mods, method, eo):
+    """b = 0 returns x = 0 after no iteration; a NaN in b is ENONFINITE; a
+    maxiter below what the solve needs is ENOCONV after maxiter iterations
+    (BiCGStab(2) counts BiCG steps and tests once per cycle of two, so 3
+    becomes 4, as in the oracle), with an x that lowered the residual."""
+    torch, fields, lqcd = mods
+    L4, theta = (4, 4, 4, 4), (0, 0, 0, math.pi)
+    U = gauge_field(L4, "haar", seed=3)
+    zero = np.zeros((256, 4, 3), complex)
+    rc, info, x = run_solve(mods, L4, theta, U, zero, 0.12, 0.05, method, tol=1e-10, eo=eo)
+    assert rc == 0 and info[0]["iters"] == 0 and not x.any()
+    bad = gaussian_spinor(L4, seed=4)
+    bad[5, 1, 1] = np.nan
+    rc, info, x = run_solve(mods, L4, theta, U, bad, 0.12, 0.05, method, tol=1e-10, eo=eo)
+    assert rc == lqcd.ENONFINITE
+    b = gaussian_spinor(L4, seed=5)
+    rc, info, x = run_solve(mods, L4, theta, U, b, 0.12, 0.05, method, tol=1e-12, maxiter=3, eo=eo)
+    want = 4 if method == "bicgstab2" else 3
+    assert rc == lqcd.ENOCONV and info[0]["iters"] == want
+    _, ref = S.solve(U, b, L4, theta, 0.12, 0.05, tol=1e-12, maxiter=3, eo=bool(eo),
+                     method="bicgstab_l" if method == "bicgstab2" else "bicgstab", ell=2)
+    assert ref.status == S.ENOCONV and ref.iters == want
+    assert 0 < true_res(U, x, b, L4, theta, 0.12, 0.05) < 1
+
+
 def test_config1_full_size_certified(mods):
     """24^3 x 8, exp(i eps H) links at eps = 0.4, kappa = 0.16, a mu = 0.005,
     FP64 even-odd CGNR to 1e-10: the returned x is certified by the oracle's M."""
