@@ -614,7 +614,8 @@ def config_solves(stream, log, kappa, mu, tol, multi):
         wsb = lat.workspace(o, pbi)
         wsb2 = lat.workspace(o, pb2)
     rc, info, secs = run(lat, U, b, p, x, ws)
-    cg = {"status": rc, "seconds_median": secs, "iters": info["iters"], "true_resid": info["true_resid"]}
+    cg = {"status": rc, "seconds_median": secs, "iters": info["iters"], "true_resid": info["true_resid"],
+          "eo_resid": info["eo_resid"]}
     rc, info, secs = run(lat, U, b, pbi, x, wsb, reps=1, fn=lqcd.bicgstab_solve)
     bi = {"status": lqcd.ERROR_NAMES.get(rc, rc), "seconds": secs, "iters": info["iters"],
           "true_resid_reached": info["true_resid"], "maxiter": 3000}
@@ -1052,7 +1053,8 @@ def main():
     for n in solves:
         last = rec[n][-1][0]
         solve_stats[n] = {"seconds_median": med([i[0]["seconds"] for i in rec[n]]), "iters": last["iters"],
-                          "reliable_updates": last["reliable_updates"], "true_resid": last["true_resid"]}
+                          "reliable_updates": last["reliable_updates"], "true_resid": last["true_resid"],
+                          "eo_resid": last["eo_resid"]}
     for n in ("fp64_links12", "mixed_fp32", "mixed_fp16"):
         solve_stats[n]["speedup_vs_fp64"] = solve_stats["fp64"]["seconds_median"] / solve_stats[n]["seconds_median"]
     mr = rec["multi_rhs"]

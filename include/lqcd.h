@@ -177,6 +177,9 @@ typedef struct {
     int32_t stagnations;       /* stagnations of the inner solve detected */
     int32_t fallbacks;         /* 1: the FP16 inner solve continued at FP32 storage */
     int32_t persistent_launches; /* persistent launches of a batched solve (one per start) */
+    double eo_resid;           /* even-odd solves (eo = 1): ||bhat - Mhat x_e||_2 / ||bhat||_2 in FP64,
+                                  the even half of b - M x after the reconstruction of x_o;
+                                  NaN for full-lattice and staggered solves */
 } lqcd_solve_info;
 
 /* Launch configuration of a kernel family (LQCD_KERNEL_DSLASH: the Wilson

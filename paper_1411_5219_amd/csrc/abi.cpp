@@ -427,10 +427,12 @@ struct Op {
 
     // out = add + sgn * M in on full-lattice fields (M^+ for dag), one launch.
     hipError_t full_M(const void* in, void* out, bool dag, double sgn, const void* add, int red, int fin, int pred,
-                      const void* aux = nullptr, int64_t st_in = -1, int64_t st_out = -1, int64_t st_add = -1) const
+                      const void* aux = nullptr, int64_t st_in = -1, int64_t st_out = -1, int64_t st_add = -1,
+                      int fin_even = 0) const
     {
         DslashArgs a = base();
         a.full = 1;
+        a.r.fin_even = fin_even;
         a.pred = pred;
         a.in = in;
         a.site = in;
@@ -715,6 +717,7 @@ void fill_info(const Ctl* ctl, int nrhs, int method, bool eo, bool mixed, int re
         in.reliable_updates = ctl[i].nupdates;
         in.restarts = restarts;
         in.true_resid = ctl[i].bb > 0 ? std::sqrt(ctl[i].true_rr / ctl[i].bb) : 0.0;
+        in.eo_resid = !eo ? std::nan("") : ctl[i].bbh > 0 ? std::sqrt(ctl[i].eo_rr / ctl[i].bbh) : 0.0;
         in.seconds = secs;
         // Dslash applications (eo-hop units): eo solves apply Mhat as 2 hops,
         // full-lattice solves apply M as one launch over V = 2 x V/2 sites.
@@ -784,7 +787,8 @@ int solver_setup(const Op& o, const lqcd_solve_params* prm, bool eo, bool mixed,
         d.add = bc;
         d.st_add = fb;
         d.c = coef_real(o.kappa);
-        LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, nrhs, o.dcfg, s));
+        d.r.fin = FIN_BBHAT;  // ||bhat||^2, the scale of the even-odd residual
+        LQCD_K(launch_dslash(64, o.recon, false, RED_NORM, d, nrhs, o.dcfg, s));
         BlasArgs z = o.blas_base(1);
         z.pred = PRED_ALWAYS;
         z.y = xc;
@@ -815,7 +819,10 @@ int solver_finish(const Op& o, bool eo, char* bc, char* xc)
         d.c = coef_Ainv(o.kappa, o.mu, false, o.kappa);
         LQCD_K(launch_dslash(64, o.recon, false, RED_NONE, d, o.nrhs, o.dcfg, o.s));
     }
-    LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS));
+    // ||b - M x||^2, and with eo its even half, which is ||bhat - Mhat x_e||^2
+    // once x_o has been reconstructed from x_e
+    LQCD_K(o.full_M(xc, nullptr, false, -1.0, bc, RED_NORM, FIN_TRUE_RR, PRED_ALWAYS, nullptr, -1, -1, -1,
+                    eo ? FIN_EO_RR : 0));
     return LQCD_OK;
 }
 
@@ -2679,6 +2686,7 @@ int stag_cg_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const void* U, 
     in.reliable_updates = 0;
     in.restarts = restarts;
     in.true_resid = h[0].bb > 0 ? std::sqrt(h[0].true_rr / h[0].bb) : 0.0;
+    in.eo_resid = std::nan("");
     in.seconds = now_s() - t0;
     // even-odd hops: bhat 1, 2 per iteration and per restart residual, reconstruct 1 and full M 2 per pass
     in.hops_outer = 1.0 + 2.0 * h[0].iter + 2.0 * restarts + 3.0 * (restarts + 1);
@@ -2787,6 +2795,7 @@ int stag_multishift_solve(const lqcd_geom* geom, const lqcd_stag_op* op, const v
         in.reliable_updates = 0;
         in.restarts = passes[i];
         in.true_resid = true_res(h[i]);
+        in.eo_resid = std::nan("");
         in.seconds = secs;
         // the shared iterations are counted on every system: 2 hops each, plus
         // its true residual; a refinement adds its own iterations, residual

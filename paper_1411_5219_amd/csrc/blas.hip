@@ -167,14 +167,14 @@ Recorder* active_recorder() { return g_recorder; }
 void set_recorder(Recorder* r) { g_recorder = r; }
 
 template <int N>
-__global__ void __launch_bounds__(kFinThreads) k_finalize(const double* partials, int nblocks, int fin, Ctl* ctl,
-                                                          int pred)
+__global__ void __launch_bounds__(kFinThreads) k_finalize(const double* partials, int nblocks, int count, int fin,
+                                                          Ctl* ctl, int pred)
 {
     const int rhs = blockIdx.x;
     Ctl* c = ctl + rhs;
     if (pred_skip(pred, c)) return;
     double v[N];
-    sum_partials<N>(partials + (int64_t)rhs * nblocks * N, nblocks, v);
+    sum_partials<N>(partials + (int64_t)rhs * nblocks * N, count, v);
     __shared__ double tot[N];
     block_reduce_store<N>(v, tot, 0);
     __syncthreads();
@@ -219,14 +219,15 @@ hipError_t launch_finalize_batch(int N, const FinArgs* tab, int nsys, int nrhs, 
 }
 
 hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, Ctl* ctl, int pred, int nrhs,
-                           hipStream_t s)
+                           hipStream_t s, int count)
 {
     if (!ctl) return hipErrorInvalidValue;
+    if (count < 0 || count > nblocks) count = nblocks;
     dim3 g(nrhs), b(kFinThreads);
-    if (N == 1) hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
-    else if (N == 2) hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
-    else if (N == 3) hipLaunchKernelGGL(k_finalize<3>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
-    else if (N == 5) hipLaunchKernelGGL(k_finalize<5>, g, b, 0, s, partials, nblocks, fin, ctl, pred);
+    if (N == 1) hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, partials, nblocks, count, fin, ctl, pred);
+    else if (N == 2) hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, partials, nblocks, count, fin, ctl, pred);
+    else if (N == 3) hipLaunchKernelGGL(k_finalize<3>, g, b, 0, s, partials, nblocks, count, fin, ctl, pred);
+    else if (N == 5) hipLaunchKernelGGL(k_finalize<5>, g, b, 0, s, partials, nblocks, count, fin, ctl, pred);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

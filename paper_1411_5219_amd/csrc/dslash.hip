@@ -162,7 +162,11 @@ hipError_t exec_dslash(const DslashPlan& p, hipStream_t s)
     DslashLaunch L{&p.a, nullptr, nullptr, 1};
     const hipError_t e = launch_dslash_prec(p, L, p.grid, s);
     if (e != hipSuccess || p.nfin == 0) return e;
-    return launch_finalize(p.nfin, p.a.r.partials, p.slots, p.a.r.fin, p.a.ctl, p.a.pred, p.a.nrhs, s);
+    const hipError_t f = launch_finalize(p.nfin, p.a.r.partials, p.slots, p.a.r.fin, p.a.ctl, p.a.pred, p.a.nrhs, s);
+    // both parities in one launch: the even-parity blocks hold the first half of the partials
+    if (f != hipSuccess || !p.a.full || !p.a.r.fin_even) return f;
+    return launch_finalize(p.nfin, p.a.r.partials, p.slots, p.a.r.fin_even, p.a.ctl, p.a.pred, p.a.nrhs, s,
+                           p.slots / 2);
 }
 
 hipError_t exec_dslash_batch(const DslashPlan* plans, int n, const DslashArgs* tab, const int* offs, int total_blocks,

@@ -48,6 +48,7 @@ struct RedArgs {
     double* partials;       // [nrhs][nblocks][N]
     int capacity;           // blocks the partials hold per right-hand side (N <= kMaxFin)
     int fin;                // Fin
+    int fin_even;           // full-lattice launches: a second Fin on the even-parity blocks' partials (0: none)
 };
 
 // Dslash_eo with a fused epilogue:
@@ -145,8 +146,10 @@ int dslash_rhs_tile(int prec, int want, int nrhs);
 
 // Sum N block partials per right-hand side in block order and run the
 // solver's scalar step (Fin) on the totals; one block per right-hand side.
+// count < nblocks sums only the first count partials of each right-hand
+// side (nblocks stays the stride between right-hand sides).
 hipError_t launch_finalize(int N, const double* partials, int nblocks, int fin, Ctl* ctl, int pred, int nrhs,
-                           hipStream_t s);
+                           hipStream_t s, int count = -1);
 
 // ---- launchers (return hipError_t) ----
 hipError_t launch_dslash(int prec, int recon, bool dagger, int red, const DslashArgs& a, int nrhs,

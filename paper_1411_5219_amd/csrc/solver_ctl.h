@@ -57,6 +57,8 @@ enum Fin {
     FIN_BL_TAU = 22,      // sigma1 = ||r_1||^2, tau = <r_1, r_2> / sigma1, gp1 = <r_1, r_0> / sigma1
     FIN_BL_OMEGA = 23,    // sigma2 = ||r_2'||^2 (r_2' = r_2 - tau r_1), gp2 = <r_2', r_0> / sigma2: omega, g1, g2
     FIN_BL_RES = 24,      // rr = ||r_0||^2, <rt, r_0>: convergence, next cycle's beta
+    FIN_EO_RR = 25,       // eo_rr = ||(b - M x)_e||^2 = ||bhat - Mhat x_e||^2 once x_o is reconstructed
+    FIN_BBHAT = 26,       // bbh = ||bhat||^2
 };
 
 // Status of a solve that handed control back to the host to continue at FP32
@@ -86,6 +88,8 @@ struct Ctl {
     // Mixed precision: FP64 ||r||^2 at the last reliable update and at the
     // start of the current outer (defect-correction) step, tol_inner^2.
     double rr_prev_upd, rr_outer, tol_inner2;
+    // Even-odd solves: ||bhat - Mhat x_e||^2 at the end and ||bhat||^2.
+    double eo_rr, bbh;
     // BiCGStab(2) (rho0, rho1, alpha and omega in rho_old, rho, balpha and
     // omega): beta, the Gram-Schmidt coefficient tau = <r_1, r_2> / ||r_1||^2,
     // the projections gp1, gp2 of r_0 on r_1, r_2', and the polynomial
@@ -262,6 +266,12 @@ LQCD_HD inline void finalize_totals(int fin, Ctl* c, const double* v)
         break;
     case FIN_TRUE_RR:
         c->true_rr = v[0];
+        break;
+    case FIN_EO_RR:
+        c->eo_rr = v[0];
+        break;
+    case FIN_BBHAT:
+        c->bbh = v[0];
         break;
     case FIN_BB_E:
         c->red[0] = v[0];

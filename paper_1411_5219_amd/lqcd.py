@@ -75,7 +75,7 @@ class SolveInfo(ctypes.Structure):
                 ("restarts", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("hops_outer", ctypes.c_double), ("hops_inner", ctypes.c_double),
                 ("outer_iters", ctypes.c_int32), ("stagnations", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
-                ("persistent_launches", ctypes.c_int32)]
+                ("persistent_launches", ctypes.c_int32), ("eo_resid", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

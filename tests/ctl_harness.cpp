@@ -23,7 +23,7 @@ struct Field {
 const Field kFields[] = {
     D(bb), D(thresh), D(zz), D(ww), D(rr), D(alpha), D(beta), D(rr_max), D(delta2), D(tol2), D(true_rr),
     D(tt), D(sigma), D(zeta_prev), D(zeta), D(zeta_next), D(alpha_prev), D(beta_prev), D(rr_prev_upd),
-    D(rr_outer), D(tol_inner2),
+    D(rr_outer), D(tol_inner2), D(eo_rr), D(bbh),
     {"rho_re", offsetof(Ctl, rho), 0}, {"rho_im", offsetof(Ctl, rho) + 8, 0},
     {"rho_old_re", offsetof(Ctl, rho_old), 0}, {"rho_old_im", offsetof(Ctl, rho_old) + 8, 0},
     {"balpha_re", offsetof(Ctl, balpha), 0}, {"balpha_im", offsetof(Ctl, balpha) + 8, 0},
@@ -140,7 +140,8 @@ int ctl_fin_code(const char* name)
              {"MS_INIT", lqcd::FIN_MS_INIT},   {"MS_INIT_KEEP", lqcd::FIN_MS_INIT_KEEP},
              {"MS_ALPHA", lqcd::FIN_MS_ALPHA}, {"MS_BETA", lqcd::FIN_MS_BETA},
              {"BL_INIT", lqcd::FIN_BL_INIT},   {"BL_ALPHA", lqcd::FIN_BL_ALPHA}, {"BL_BETA", lqcd::FIN_BL_BETA},
-             {"BL_TAU", lqcd::FIN_BL_TAU},     {"BL_OMEGA", lqcd::FIN_BL_OMEGA}, {"BL_RES", lqcd::FIN_BL_RES}};
+             {"BL_TAU", lqcd::FIN_BL_TAU},     {"BL_OMEGA", lqcd::FIN_BL_OMEGA}, {"BL_RES", lqcd::FIN_BL_RES},
+             {"EO_RR", lqcd::FIN_EO_RR},       {"BBHAT", lqcd::FIN_BBHAT}};
     for (auto& e : t)
         if (std::strcmp(e.n, name) == 0) return e.v;
     return -1;

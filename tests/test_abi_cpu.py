@@ -21,6 +21,39 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_binding_structs_match_the_header(tmp_path):
+    """Every argument struct of the binding has the C header's size and
+    field offsets (a host C compiler lays the header's structs out)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_1411_5219_amd import lqcd as L
+    cc = shutil.which("gcc")
+    if not cc:
+        pytest.skip("no host C compiler")
+    pairs = {"lqcd_geom": L.Geom, "lqcd_op": L.Op, "lqcd_stag_op": L.StagOp, "lqcd_solve_params": L.SolveParams,
+             "lqcd_launch": L.Launch, "lqcd_solve_info": L.SolveInfo}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "lqcd.h"', "int main(void) {"]
+    for c, py in pairs.items():
+        lines.append(f'    printf("{c} size %zu\\n", sizeof({c}));')
+        for f, _ in py._fields_:
+            lines.append(f'    printf("{c} {f} %zu\\n", offsetof({c}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        c, f, v = ln.split()
+        got[(c, f)] = int(v)
+    for c, py in pairs.items():
+        assert got[(c, "size")] == ctypes.sizeof(py), c
+        for f, _ in py._fields_:
+            assert got[(c, f)] == getattr(py, f).offset, (c, f)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1411_5219_amd import lqcd as L
     names = _declared()

@@ -48,6 +48,20 @@ def true_res(U, x, b, L4, theta, kappa, mu):
     return W.true_residual(U, x, b, L4, theta, kappa, mu)
 
 
+def eo_res(U, x, b, L4, theta, kappa, mu):
+    """||bhat - Mhat x_e|| / ||bhat|| by the oracle on the returned x."""
+    bhat = W.eo_source(U, b, L4, theta, kappa, mu)
+    r = bhat - W.schur(U, W.mask(x, L4, 0), L4, theta, kappa, mu)
+    return float(np.linalg.norm(r.ravel()) / np.linalg.norm(bhat.ravel()))
+
+
+def check_eo_resid(info, U, x, b, L4, theta, kappa, mu):
+    """The reported even-odd residual equals the oracle's on the returned x
+    (both are rounding-limited near 1e-10: 1e-3 relative)."""
+    ref = eo_res(U, x, b, L4, theta, kappa, mu)
+    assert abs(info["eo_resid"] - ref) <= 1e-3 * ref + 1e-15, (info["eo_resid"], ref)
+
+
 @pytest.mark.parametrize("method", ["cg", "bicgstab", "bicgstab2"])
 @pytest.mark.parametrize("eo", [0, 1])
 def test_config0_like_4x4x4x4(mods, method, eo):
@@ -60,6 +74,10 @@ def test_config0_like_4x4x4x4(mods, method, eo):
     assert rc == 0, info
     tr = true_res(U, x, b, L4, theta, kappa, mu)
     assert tr <= 1e-12 and abs(tr - info[0]["true_resid"]) < 1e-13
+    if eo:
+        check_eo_resid(info[0], U, x, b, L4, theta, kappa, mu)
+    else:
+        assert math.isnan(info[0]["eo_resid"])
     x_ref, _ = S.solve(U, b, L4, theta, kappa, mu, tol=1e-13, method="cgnr", eo=True)
     assert np.linalg.norm((x - x_ref).ravel()) / np.linalg.norm(x_ref.ravel()) < 1e-10
 
@@ -89,6 +107,7 @@ def test_twisted_mass_eo_mixed(mods, inner):
     tr = true_res(U, x, b, L4, theta, kappa, mu)
     print(f"  iters={info[0]['iters']} updates={info[0]['reliable_updates']} true={tr:.2e}", flush=True)
     assert tr <= 1e-10
+    check_eo_resid(info[0], U, x, b, L4, theta, kappa, mu)
 
 
 @pytest.mark.parametrize("inner", [(64, 18), (32, 12), (32, 18), (16, 12)])
@@ -176,6 +195,7 @@ def test_bicgstab2_twisted_eo(mods, use_graph):
     assert rc == 0, info
     tr = true_res(U, x, b, L4, theta, kappa, mu)
     assert tr <= 1e-10 and abs(tr - info[0]["true_resid"]) <= 1e-13
+    check_eo_resid(info[0], U, x, b, L4, theta, kappa, mu)
     x_ref, ref_info = S.solve(U, b, L4, theta, kappa, mu, tol=1e-12, method="cgnr", eo=True)
     assert ref_info.status == 0
     assert np.linalg.norm((x - x_ref).ravel()) / np.linalg.norm(x_ref.ravel()) <= 2e-9
@@ -235,6 +255,7 @@ def test_mixed_several_rhs_counts(mods, nrhs, inner):
     for k in range(nrhs):
         tr = true_res(U, x[k], b[k], L4, theta, kappa, mu)
         assert tr <= 1e-10 and abs(tr - info[k]["true_resid"]) <= 1e-13, k
+        check_eo_resid(info[k], U, x[k], b[k], L4, theta, kappa, mu)
     assert [i["iters"] for i in info] == [i["iters"] for i in infog]
     assert np.array_equal(x, xg)
 
@@ -402,6 +423,7 @@ def test_uneven_batch(mods, use_graph, inner):
         for k in range(nrhs):
             assert true_res(U, x[k], b[k], L4, theta, kappa, mu) <= 1e-10, (i, k)
             assert abs(infos[i][k]["true_resid"] - true_res(U, x[k], b[k], L4, theta, kappa, mu)) < 1e-12
+            check_eo_resid(infos[i][k], U, x[k], b[k], L4, theta, kappa, mu)
         rc1, info1, x1 = run_solve(mods, L4, theta, U, b, kappa, mu, "cg", nrhs=nrhs, tol=1e-10, maxiter=20000,
                                    inner_prec=inner[0], inner_recon=inner[1])
         assert rc1 == 0

@@ -150,6 +150,7 @@ def test_cg_solve(mods, L4, kind, mass, tol, use_graph):
     tr = S.true_residual(U, x, b, L4, theta, mass)
     assert tr <= tol, (tr, info)
     assert abs(tr - info["true_resid"]) <= 1e-3 * tol + 1e-15
+    assert math.isnan(info["eo_resid"])  # reported for the Wilson even-odd solves only
     xo, oinfo = SV.stag_solve(U, b, L4, theta, mass, tol)
     assert np.linalg.norm((x - xo).ravel()) / np.linalg.norm(xo.ravel()) < 1e3 * tol / mass
     assert abs(info["iters"] - oinfo.iters) <= 2

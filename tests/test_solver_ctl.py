@@ -423,6 +423,21 @@ def test_bicgstab2_degenerate_cycles(H):
     assert c["status"] == ENOCONV and c["iter"] == 2
 
 
+def test_eo_residual_scalars_leave_the_solve_alone(H):
+    """FIN_BBHAT and FIN_EO_RR only record ||bhat||^2 and the even half of
+    ||b - M x||^2: no other field of the control block changes."""
+    c = Ctl(H, tol=1e-10)
+    c.fin("BB_FULL", 4.0)
+    c.fin("CG_ZZ", 1.0)
+    before = {n: c[n] for n in ("bb", "thresh", "rr", "zz", "iter", "done", "status", "true_rr")}
+    c.fin("BBHAT", 2.5)
+    c.fin("TRUE_RR", 3e-20)
+    c.fin("EO_RR", 2e-20)
+    assert c["bbh"] == 2.5 and c["eo_rr"] == 2e-20 and c["true_rr"] == 3e-20
+    before["true_rr"] = 3e-20
+    assert {n: c[n] for n in before} == before
+
+
 def test_multishift_sequence_matches_oracle(H):
     """The library's multi-shift iteration (w = (A + s0) p_base with
     <p, w> -> FIN_MS_ALPHA; x_i += alpha_i p_i; r -= alpha w -> FIN_MS_BETA;
