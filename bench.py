@@ -1042,9 +1042,15 @@ def main():
         ms = sum(per_burst) / len(per_burst)
         bpl = Vh * HOP_BYTES[k]
         gbs = bpl / (ms * 1e-3) / 1e9
+        # context beside the compulsory-byte rate: the standard 1320 flop per
+        # site and the paper's byte convention (8 neighbour spinors + 8 links
+        # + the output, no reuse: 2880 B per site at FP64/18)
+        paper_b = 9 * SPINOR_B[k[0]] + 8 * LINK_B[k]
         hop_stats[f"fp{k[0]}_{k[1]}"] = {"avg_launch_us": ms * 1e3, "median_burst_us": float(np.median(per_burst)) * 1e3,
                                          "bursts": len(per_burst), "bytes_per_launch": bpl, "GBps": gbs,
-                                         "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+                                         "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                                         "gflops_1320": Vh * 1320 / (ms * 1e-3) / 1e9,
+                                         "paper_convention_GBps": Vh * paper_b / (ms * 1e-3) / 1e9}
     main_k = hop_stats["fp64_18"]
     traffic, traffic_note = recorded_traffic(args.workload)
 
