@@ -8,6 +8,7 @@
 // back once per chunk, overlapped with the next chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -621,11 +622,15 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Runs enqueue_iter() in chunks of `chunk` iterations until every solve is
-// done: the control blocks ctl[s * stride + r] (s < nsys, r < nrhs) are read
-// back after each chunk, and the read-back of chunk n is waited for while
-// chunk n + 1 runs.  With use_graph the chunk is captured once as a HIP graph
-// and replayed.
+// Runs enqueue_iter() in chunks of at most `chunk` iterations until every
+// solve is done: the control blocks ctl[s * stride + r] (s < nsys, r < nrhs)
+// are read back after each chunk, and the read-back of chunk n is waited for
+// while chunk n + 1 runs.  Near the end the chunks shrink: from two
+// read-backs of each open solve the rate at which ||r||^2 falls per
+// iteration gives the iterations it still needs, and the next chunk covers
+// what the chunk in flight does not (at least one iteration), so few no-op
+// iterations follow convergence.  With use_graph the chunk is captured once
+// as a HIP graph and replayed at full length.
 template <class F>
 int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int chunk, int maxiter, bool use_graph,
           F&& enqueue_iter)
@@ -640,7 +645,7 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int result = LQCD_OK;
-    auto enqueue_chunk = [&]() -> int {
+    auto enqueue_chunk = [&](int len) -> int {
         if (use_graph) {
             if (!exec) {
                 LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -656,17 +661,32 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
             LQCD_HIP(hipGraphLaunch(exec, st));
             return LQCD_OK;
         }
-        for (int k = 0; k < chunk; ++k) {
+        for (int k = 0; k < len; ++k) {
             int r = enqueue_iter();
             if (r) return r;
         }
         return LQCD_OK;
     };
-    const int max_chunks = maxiter / chunk + 2;
+    // The solver's own iteration limit ends the work (the kernels of a
+    // finished solve are no-ops); this bounds the host loop.
+    const int64_t max_enqueue = (int64_t)maxiter + 2 * (int64_t)chunk;
+    int64_t enqueued = 0;
+    int len[2] = {0, 0};                        // iterations of the chunks enqueued at even and odd steps
+    std::vector<double> prev_rr(count, -1.0);  // ||r||^2 and iteration at the previous read-back
+    std::vector<int> prev_it(count, -1);
+    int need = -1;                              // iterations the slowest open solve still needs (-1: unknown)
     for (int n = 0;; ++n) {
-        if (n < max_chunks) {
-            result = enqueue_chunk();
+        const bool more = enqueued < max_enqueue;
+        if (more) {
+            int c = chunk;
+            if (!use_graph && need >= 0) {
+                const int after = need - (n >= 1 ? len[(n - 1) & 1] : 0);  // beyond the chunk in flight
+                c = std::min(chunk, std::max(1, after + 1));
+            }
+            result = enqueue_chunk(c);
             if (result) break;
+            enqueued += c;
+            len[n & 1] = c;
             hipError_t e = hipMemcpyAsync(pin + (n & 1) * kPinned, ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipEventRecord(ev[n & 1], st);
             if (e != hipSuccess) { result = set_error(LQCD_EHIP, "status read-back: %s", hipGetErrorString(e)); break; }
@@ -675,10 +695,31 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
         const int m = (n - 1) & 1;
         hipError_t e = hipEventSynchronize(ev[m]);
         if (e != hipSuccess) { result = set_error(LQCD_EHIP, "stream: %s", hipGetErrorString(e)); break; }
-        bool all = true;
+        bool all = true, known = true;
+        int most = 0;
         for (int sy = 0; sy < nsys; ++sy)
-            for (int i = 0; i < nrhs; ++i) all = all && pin[m * kPinned + sy * stride + i].done;
-        if (all || n >= max_chunks) break;
+            for (int i = 0; i < nrhs; ++i) {
+                const int k = sy * stride + i;
+                const Ctl& c = pin[m * kPinned + k];
+                if (c.done) continue;
+                all = false;
+                if (prev_it[k] >= 0 && c.iter > prev_it[k] && prev_rr[k] > 0.0 && c.rr > 0.0 && c.rr > c.thresh &&
+                    c.thresh > 0.0) {
+                    const double rate = std::pow(c.rr / prev_rr[k], 1.0 / (c.iter - prev_it[k]));
+                    if (rate < 1.0 && rate > 0.0) {
+                        const double it = std::ceil(std::log(c.thresh / c.rr) / std::log(rate));
+                        most = std::max(most, (int)std::min(it, 1e6));
+                    } else {
+                        known = false;
+                    }
+                } else if (!(c.rr > 0.0 && c.rr <= c.thresh)) {
+                    known = false;
+                }
+                prev_rr[k] = c.rr;
+                prev_it[k] = c.iter;
+            }
+        need = known ? most : -1;
+        if (all || !more) break;
     }
     (void)hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
