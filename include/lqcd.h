@@ -123,7 +123,9 @@ typedef struct {
  *                  workspace then holds FP32 inner fields).  0: 3; < 0: never.
  *                  Batched solves (cg_solve_batch) never fall back.
  *   use_graph      1: replay iterations from a captured HIP graph
- *   check_every    iterations enqueued between status read-backs (>= 1)
+ *   check_every    iterations enqueued between status read-backs (>= 1; near
+ *                  convergence fewer, as many as the residual's rate of
+ *                  decrease says are left, except with use_graph)
  *   persistent     cg_solve_batch only (other solvers: 0).  0: every step of
  *                  an iteration is one batched launch (replayed from a graph
  *                  with use_graph); 1: all iterations run in one persistent
