@@ -22,6 +22,7 @@
 #include <tuple>
 #include <vector>
 
+#include "chunking.h"
 #include "lqcd.h"
 #include "lqcd_device.h"
 #include "lqcd_kernels.h"
@@ -678,11 +679,7 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
     for (int n = 0;; ++n) {
         const bool more = enqueued < max_enqueue;
         if (more) {
-            int c = chunk;
-            if (!use_graph && need >= 0) {
-                const int after = need - (n >= 1 ? len[(n - 1) & 1] : 0);  // beyond the chunk in flight
-                c = std::min(chunk, std::max(1, after + 1));
-            }
+            const int c = use_graph ? chunk : next_chunk(need, n >= 1 ? len[(n - 1) & 1] : 0, chunk);
             result = enqueue_chunk(c);
             if (result) break;
             enqueued += c;
@@ -703,18 +700,9 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
                 const Ctl& c = pin[m * kPinned + k];
                 if (c.done) continue;
                 all = false;
-                if (prev_it[k] >= 0 && c.iter > prev_it[k] && prev_rr[k] > 0.0 && c.rr > 0.0 && c.rr > c.thresh &&
-                    c.thresh > 0.0) {
-                    const double rate = std::pow(c.rr / prev_rr[k], 1.0 / (c.iter - prev_it[k]));
-                    if (rate < 1.0 && rate > 0.0) {
-                        const double it = std::ceil(std::log(c.thresh / c.rr) / std::log(rate));
-                        most = std::max(most, (int)std::min(it, 1e6));
-                    } else {
-                        known = false;
-                    }
-                } else if (!(c.rr > 0.0 && c.rr <= c.thresh)) {
-                    known = false;
-                }
+                const int left = iterations_left(prev_rr[k], prev_it[k], c.rr, c.iter, c.thresh);
+                if (left < 0) known = false;
+                else most = std::max(most, left);
                 prev_rr[k] = c.rr;
                 prev_it[k] = c.iter;
             }

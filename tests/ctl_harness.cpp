@@ -1,4 +1,5 @@
-// Host build of the solvers' scalar steps (solver_ctl.h) for the CPU tests:
+// Host build of the solvers' scalar steps (solver_ctl.h) and of the host
+// loop's chunk sizing (chunking.h) for the CPU tests:
 // a control block (or a family of them, for the multi-shift CG) is driven
 // with reduction totals chosen by the test, and its fields are read back by
 // name.  Compiled by the tests with a host C++ compiler; not part of the
@@ -6,6 +7,7 @@
 #include <cstddef>
 #include <cstring>
 
+#include "chunking.h"
 #include "solver_ctl.h"
 
 using lqcd::Ctl;
@@ -148,4 +150,11 @@ int ctl_fin_code(const char* name)
 }
 
 int ctl_status_fallback() { return lqcd::kStatusFallback; }
+
+// The host loop's chunk sizing.
+int chunk_iterations_left(double rr_prev, int it_prev, double rr, int it, double thresh)
+{
+    return lqcd::iterations_left(rr_prev, it_prev, rr, it, thresh);
+}
+int chunk_next(int need, int in_flight, int chunk) { return lqcd::next_chunk(need, in_flight, chunk); }
 }

@@ -52,6 +52,9 @@ def H(tmp_path_factory):
     lib.ctl_fin_code.argtypes = [ctypes.c_char_p]
     lib.ctl_fin_v.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                               ctypes.c_int]
+    lib.chunk_iterations_left.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double]
+    lib.chunk_next.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     return lib
 
 
@@ -620,3 +623,27 @@ def test_mixed_cgnr_with_float32_inner_converges(H):
         assert c["iter"] < 500
     assert c["status"] == 0 and c["nupdates"] >= 2
     assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-12
+
+
+def test_chunk_sizing(H):
+    """The host loop's estimate of the iterations left: ||r||^2 falling by
+    0.8 per iteration from 1 to 1e-20 needs ceil(log(1e-20 / rr) / log 0.8)
+    more; no estimate without a decrease or a second read-back; 0 once below
+    the threshold; the next chunk covers what the chunk in flight does not,
+    between 1 and the full chunk."""
+    left = H.chunk_iterations_left
+    rr_prev, rr = 0.8 ** 10, 0.8 ** 18
+    assert left(rr_prev, 10, rr, 18, 1e-20) == int(np.ceil(np.log(1e-20 / rr) / np.log(0.8)))
+    assert left(rr_prev, 10, rr, 18, 1e-20) == 189
+    assert left(rr, 18, rr_prev, 26, 1e-20) == -1        # increasing
+    assert left(rr, 18, rr, 26, 1e-20) == -1             # stalled
+    assert left(-1.0, -1, rr, 18, 1e-20) == -1           # first read-back
+    assert left(rr_prev, 10, rr, 10, 1e-20) == -1        # no iteration in between
+    assert left(rr_prev, 10, 1e-21, 18, 1e-20) == 0      # already below
+    assert left(rr_prev, 10, rr, 18, 0.0) == -1          # b = 0 has no threshold to reach
+    nxt = H.chunk_next
+    assert nxt(-1, 8, 8) == 8
+    assert nxt(100, 8, 8) == 8
+    assert nxt(10, 8, 8) == 3
+    assert nxt(3, 8, 8) == 1
+    assert nxt(0, 0, 8) == 1
