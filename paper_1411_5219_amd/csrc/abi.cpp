@@ -625,13 +625,15 @@ double now_s()
 
 // Runs enqueue_iter() in chunks of at most `chunk` iterations until every
 // solve is done: the control blocks ctl[s * stride + r] (s < nsys, r < nrhs)
-// are read back after each chunk, and the read-back of chunk n is waited for
-// while chunk n + 1 runs.  Near the end the chunks shrink: from two
+// are read back after each chunk, and the read-back of a chunk is waited
+// for while the next one runs.  Near the end the chunks shrink: from two
 // read-backs of each open solve the rate at which ||r||^2 falls per
 // iteration gives the iterations it still needs, and the next chunk covers
 // what the chunk in flight does not (at least one iteration), so few no-op
 // iterations follow convergence.  With use_graph the chunk is captured once
-// as a HIP graph and replayed at full length.
+// as a HIP graph and replayed at full length; instead of shrinking, the
+// host then reads the status of the chunk in flight before replaying
+// another when that chunk should finish every solve.
 template <class F>
 int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int chunk, int maxiter, bool use_graph,
           F&& enqueue_iter)
@@ -672,26 +674,37 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
     // finished solve are no-ops); this bounds the host loop.
     const int64_t max_enqueue = (int64_t)maxiter + 2 * (int64_t)chunk;
     int64_t enqueued = 0;
-    int len[2] = {0, 0};                        // iterations of the chunks enqueued at even and odd steps
+    int issued = 0, seen = 0;                   // chunks enqueued, chunks whose status was read
+    int len[2] = {0, 0};                        // iterations of chunk i, at len[i & 1] (two in flight at most)
     std::vector<double> prev_rr(count, -1.0);  // ||r||^2 and iteration at the previous read-back
     std::vector<int> prev_it(count, -1);
     int need = -1;                              // iterations the slowest open solve still needs (-1: unknown)
-    for (int n = 0;; ++n) {
-        const bool more = enqueued < max_enqueue;
-        if (more) {
-            const int c = use_graph ? chunk : next_chunk(need, n >= 1 ? len[(n - 1) & 1] : 0, chunk);
+    // The chunks in flight cover `out` iterations; once they cover what the
+    // slowest solve needs (plus one without graph replay, whose chunks are
+    // sized to it) no further chunk is queued before their status is read.
+    const int margin = use_graph ? 0 : 1;
+    for (;;) {
+        while (enqueued < max_enqueue && issued - seen < 2) {
+            int out = 0;
+            for (int i = seen; i < issued; ++i) out += len[i & 1];
+            if (issued > seen && need >= 0 && need + margin <= out) break;
+            const int c = use_graph ? chunk : next_chunk(need, out, chunk);
             result = enqueue_chunk(c);
             if (result) break;
-            enqueued += c;
-            len[n & 1] = c;
-            hipError_t e = hipMemcpyAsync(pin + (n & 1) * kPinned, ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipEventRecord(ev[n & 1], st);
+            const int slot = issued & 1;
+            hipError_t e = hipMemcpyAsync(pin + slot * kPinned, ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(ev[slot], st);
             if (e != hipSuccess) { result = set_error(LQCD_EHIP, "status read-back: %s", hipGetErrorString(e)); break; }
+            enqueued += c;
+            len[slot] = c;
+            ++issued;
         }
-        if (n == 0) continue;
-        const int m = (n - 1) & 1;
+        if (result) break;
+        if (issued == seen) break;  // the iteration bound is reached and every chunk was read
+        const int m = seen & 1;
         hipError_t e = hipEventSynchronize(ev[m]);
         if (e != hipSuccess) { result = set_error(LQCD_EHIP, "stream: %s", hipGetErrorString(e)); break; }
+        ++seen;
         bool all = true, known = true;
         int most = 0;
         for (int sy = 0; sy < nsys; ++sy)
@@ -707,7 +720,7 @@ int drive(hipStream_t st, const Ctl* ctl, int nsys, int stride, int nrhs, int ch
                 prev_it[k] = c.iter;
             }
         need = known ? most : -1;
-        if (all || !more) break;
+        if (all) break;
     }
     (void)hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
